@@ -1,0 +1,260 @@
+/*
+ * mucite.h -- C ABI of the MI355X (gfx950) ion-pack propagation library.
+ *
+ * The library advances weighted ion packs through baked axisymmetric DC, RF
+ * and gas-flow fields with particle-in-cell space charge, stochastic
+ * hard-sphere collisions with internal-energy exchange, dissociation
+ * survival, and terminal classification -- the per-timestep path of the
+ * MuCITE method (paper sections "Simulation scope and modular architecture"
+ * through "Terminal events, snapshots, and reported observables", Eqs. 1-8).
+ * Every step of the path runs in hand-written HIP kernels on one GPU.
+ *
+ * Conventions
+ *  - Status: every call returns int32_t, MC_OK (0) or a negative MC_E* code.
+ *    No C++ exception crosses this boundary.  mc_last_error() returns a
+ *    ctx-owned NUL-terminated message, valid until the next call on that ctx.
+ *  - Units: SI throughout (m, s, V, Pa, K, kg via Da, J).  Masses in Da,
+ *    cross sections in m^2, activation enthalpy in J/mol, entropy in
+ *    J/(mol K), Arrhenius energy in eV.
+ *  - Grid: node (r_i = i*dr, z_j = j*dz), 0 <= i < nr, 0 <= j < nz.  Every
+ *    table is row-major [nz][nr]: element j*nr + i.
+ *  - Ownership: host arrays passed in are borrowed for the duration of the
+ *    call and copied; host output buffers belong to the caller and must have
+ *    the sizes stated at each call.  Device memory belongs to the ctx; it is
+ *    obtained from the allocator callbacks in mc_options when given (so a
+ *    framework's caching allocator can back it), otherwise from hipMalloc.
+ *  - Streams: work is enqueued on the stream given in mc_options (a
+ *    hipStream_t passed as void*), or on a stream the ctx creates.  mc_step,
+ *    mc_inject and mc_pic_update are asynchronous; every mc_read_* call
+ *    synchronises the stream first.  A ctx is not thread-safe.
+ *  - Fixed point: pack weights and charges are int64 in units of 2^-32 real
+ *    ions and 2^-32 elementary charges, so deposits and tallies are exact
+ *    and independent of summation order.
+ */
+#ifndef MUCITE_H
+#define MUCITE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_ABI_VERSION 1
+
+enum {
+    MC_OK = 0,
+    MC_EINVAL = -1,     /* invalid argument */
+    MC_ESTATE = -2,     /* call out of order (e.g. step before fields/operating point) */
+    MC_ENOMEM = -3,     /* allocation failed or capacity exceeded */
+    MC_EBUDGET = -4,    /* request exceeds the configured device-memory budget */
+    MC_EDEVICE = -5,    /* HIP runtime error */
+    MC_ENUMERIC = -6,   /* non-finite state detected (packs are counted, not dropped silently) */
+    MC_EINTERNAL = -7
+};
+
+enum { MC_PREC_FP64 = 0, MC_PREC_FP32 = 1 };
+
+/* Terminal classes ("Terminal events" section): transmitted through the
+ * detector plane within the detector radius, electrode hit, radial loss,
+ * axial domain exit; numeric marks a pack whose state became non-finite. */
+enum { MC_ACTIVE = 0, MC_TRANSMITTED = 1, MC_ELECTRODE = 2, MC_RADIAL = 3, MC_AXIAL = 4, MC_NUMERIC = 5 };
+enum { MC_NCLASS = 6 };
+
+/* Histogram layouts (index 0 = underflow, last = overflow):
+ *   KE      200 log10 bins over [1e-3, 1e3] eV            -> MC_HIST_KE entries
+ *   T_eff   200 linear bins over [0, 5000] K              -> MC_HIST_TEFF entries
+ *   r_exit  100 linear bins over [0, r_det] (transmitted) -> MC_HIST_R entries */
+enum { MC_HIST_KE = 202, MC_HIST_TEFF = 202, MC_HIST_R = 102 };
+
+typedef void *(*mc_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*mc_free_fn)(void *ptr, void *stream, void *user);
+
+typedef struct mc_options {
+    int32_t precision;       /* MC_PREC_FP64, or MC_PREC_FP32 (FP32 state and math, BF16 tables) */
+    int32_t device;          /* HIP device ordinal */
+    uint64_t seed;           /* key of the counter-based random streams */
+    int64_t pack_capacity;   /* maximum number of pack slots (> 0) */
+    int64_t exit_capacity;   /* exit-record buffer size; 0 = pack_capacity */
+    int64_t hbm_budget;      /* device bytes this ctx may allocate; 0 = unlimited */
+    void *stream;            /* hipStream_t to enqueue on; NULL = ctx-owned stream */
+    mc_alloc_fn alloc;       /* optional device allocator (both or neither) */
+    mc_free_fn free;
+    void *alloc_user;
+    int32_t timing;          /* non-zero: record HIP events around every kernel (mc_read_timing) */
+    int32_t fp32_tables;     /* FP32 form only: FP32 field tables instead of BF16 with per-table scale */
+} mc_options;
+
+typedef struct mc_grid {
+    int32_t nr, nz;          /* nodes (>= 3 each) */
+    double dr, dz;           /* spacings [m] */
+} mc_grid;
+
+/* Field tables on the node grid (host FP64 arrays of nr*nz, row-major [nz][nr]).
+ * phi_dc: DC potential [V]; phi_off: DC-offset basis [V/V] (nullable);
+ * phi_rf: RF basis potential for +/-1 V on the RF electrodes [V/V] (Eq. 4,
+ * V_ref = 1 V; nullable); gas_ur, gas_uz [m/s], gas_p [Pa], gas_t [K]
+ * (gas_ur, gas_uz nullable = 0); mask: 1 on metal nodes (nullable = none).
+ * E = -grad(phi) is baked on the device by second-order central differences
+ * (one-sided at the outer edges, E_r = 0 on the axis). */
+typedef struct mc_field_tables {
+    const double *phi_dc, *phi_off, *phi_rf;
+    const double *gas_ur, *gas_uz, *gas_p, *gas_t;
+    const uint8_t *mask;
+} mc_field_tables;
+
+/* Ion template ("An ion template specifies mass, charge state, collision
+ * cross section, atom count, heat capacity profile, and optional
+ * activation parameters").  Heat capacity: Einstein model, s = 3N-6
+ * oscillators at theta_e.  alpha < 0 selects the default internal-exchange
+ * probability 4 mg ma / (mg + ma)^2, ma = m / n_atoms. */
+typedef struct mc_ion {
+    double mass_da;
+    int32_t charge_z;        /* non-zero */
+    double ccs_m2;
+    int32_t n_atoms;         /* >= 3 */
+    double theta_e;          /* [K] */
+    double alpha;
+    double t_eff0;           /* initial effective temperature [K] */
+    int32_t act_kind;        /* 0 none, 1 Eyring (p1 = dH J/mol, p2 = dS J/mol/K), 2 Arrhenius (p1 = A 1/s, p2 = Ea eV) */
+    double act_p1, act_p2;
+} mc_ion;
+
+/* Source definition ("A separate source definition specifies current,
+ * spatial profile, injection plane, and initial velocity distribution").
+ * kind 0: burst, packs only via mc_inject, weight = weight;
+ * kind 1: packs_per_step packs every step from step_start, weight
+ *         I dt / (z e packs_per_step) so the packs carry the current;
+ * kind 2: Eq. 5 accumulator: N_real = I dt / (z e) per step, a pack of
+ *         weight `weight` emitted each time the accumulator reaches it.
+ * Emission stops after n_total packs.  Radial profile: Gaussian of width
+ * sigma_r truncated at r_trunc; injection plane z_inj; velocity: local gas
+ * flow plus the ion's Maxwellian at the local gas temperature. */
+typedef struct mc_source {
+    int32_t kind;
+    int32_t ion;             /* id from mc_define_ion */
+    double current_a;
+    double weight;
+    int64_t packs_per_step;
+    int64_t n_total;
+    double sigma_r, r_trunc, z_inj;
+    int64_t step_start;
+} mc_source;
+
+/* Operating point.  dt: fixed step [s]; RF: V_RF cos(2 pi f t + phase) (Eq. 4);
+ * v_off scales the DC-offset basis; collisions_on enables the collision
+ * step; sc_on/sc_every: deposit + Poisson + field every sc_every steps;
+ * z_det/r_det: detector plane and radius; d_hit: electrode hit distance;
+ * exit current (Eq. 8) is binned in n_exit_bins bins of exit_bin_dt. */
+typedef struct mc_operating {
+    double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
+    int32_t collisions_on, sc_on, sc_every;
+    double z_det, r_det, d_hit, exit_bin_dt;
+    int32_t n_exit_bins;
+} mc_operating;
+
+/* Pack population (host arrays of length n) for snapshot read/write.
+ * Read: all slots in slot order, terminal packs included; every pointer may
+ * be NULL to skip that field; n on input = buffer length.  Write: replaces
+ * the population by n active packs (x..w, id and tag required; q and
+ * status ignored -- q is recomputed from the ion charge and w). */
+typedef struct mc_packs {
+    int64_t n;
+    double *x, *y, *z, *vx, *vy, *vz, *e_int, *h, *w;
+    int64_t *id, *q;
+    int32_t *tag, *status;
+} mc_packs;
+
+/* Tallies.  Scalars are filled by mc_read_tallies; each array pointer, when
+ * non-NULL, must hold: exit_bins[n_exit_bins], loss_map[nz*nr],
+ * hist_ke[MC_HIST_KE], hist_teff[MC_HIST_TEFF], hist_r[MC_HIST_R],
+ * act_hist_ke[MC_HIST_KE], act_hist_teff[MC_HIST_TEFF].
+ * class_n/class_w: packs and int64 weights per class (MC_ACTIVE = the
+ * current active population); exit bins, loss map and hist_* collect the
+ * weights of transmitted (hist_*, exit_bins) and electrode (loss_map) packs;
+ * act_hist_* histogram the active population at read time.
+ * n_cand/n_coll: collision candidates and accepted collisions; n_cap: pack
+ * steps that hit the candidate cap; n_clamp: internal-energy clamps;
+ * pack_steps: sum over steps of the active packs advanced.
+ * sum_w_*: FP64 sums, reduced in a fixed order (run-to-run identical). */
+typedef struct mc_tallies {
+    int64_t emitted_n, emitted_w;
+    int64_t class_n[MC_NCLASS], class_w[MC_NCLASS];
+    int64_t n_cand, n_coll, n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped;
+    double sum_w_ke_active, sum_w_eint_active, sum_w_dissoc_terminal;
+    int64_t *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r, *act_hist_ke, *act_hist_teff;
+} mc_tallies;
+
+/* One terminal event.  inode/jnode: nearest node for electrode hits, else -1;
+ * t_cross/r_cross: plane-crossing time and radius for axial/transmitted exits. */
+typedef struct mc_exit_rec {
+    int64_t id, step;
+    int32_t cls, inode, jnode, tag;
+    double x, y, z, vx, vy, vz, t_cross, r_cross, ke_ev, t_eff, h, w;
+} mc_exit_rec;
+
+typedef struct mc_info {
+    int64_t step, n_slots, capacity, exit_capacity, device_bytes;
+    int32_t nr, nz, n_exit_bins, precision, n_ions, n_sources;
+} mc_info;
+
+/* Per-kernel timing from HIP events (requires mc_options.timing). */
+enum { MC_K_EMIT = 0, MC_K_STEP = 1, MC_K_DEPOSIT = 2, MC_K_POISSON = 3, MC_K_FIELD = 4, MC_K_TALLY = 5, MC_NKERNEL = 6 };
+typedef struct mc_timing {
+    double ms[MC_NKERNEL];
+    int64_t launches[MC_NKERNEL];
+    int64_t pack_steps;      /* sum over step launches of the slots scanned */
+} mc_timing;
+
+typedef struct mc_ctx mc_ctx;
+
+int32_t mc_abi_version(void);
+
+/* Create a context on options->device.  *out receives the handle.
+ * Errors: MC_EINVAL (bad options), MC_EDEVICE. */
+int32_t mc_create(const mc_options *options, mc_ctx **out);
+/* Release all device memory and the ctx-owned stream.  NULL is a no-op. */
+void mc_destroy(mc_ctx *ctx);
+const char *mc_last_error(const mc_ctx *ctx);
+
+/* Load and bake the field tables (coordinate-system and gas sections).  May
+ * be called once per ctx.  Errors: MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET. */
+int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *grid, const mc_field_tables *tables);
+/* Define an ion template; *ion_id receives its index (species tag of packs). */
+int32_t mc_define_ion(mc_ctx *ctx, const mc_ion *ion, int32_t *ion_id);
+/* Set the operating point; requires fields.  Rebuilds the electrode hit table
+ * and the folded static field.  Must precede mc_define_source. */
+int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op);
+/* Define a source; *src_id receives its index.  Pack ids of source s are
+ * (s << 32) | k for its k-th pack; they key the random streams. */
+int32_t mc_define_source(mc_ctx *ctx, const mc_source *src, int32_t *src_id);
+/* Emit n packs from source src_id now, at the current step (burst). */
+int32_t mc_inject(mc_ctx *ctx, int32_t src_id, int64_t n);
+/* Advance n_steps steps.  Each step: space-charge update when sc_on and
+ * step % sc_every == 0; emission of due packs; then for every active pack
+ * RK4 push, classification, collisions, dissociation. Asynchronous. */
+int32_t mc_step(mc_ctx *ctx, int64_t n_steps);
+/* Space-charge update now (deposit, Poisson, field) from the current packs. */
+int32_t mc_pic_update(mc_ctx *ctx);
+int32_t mc_synchronize(mc_ctx *ctx);
+int32_t mc_get_info(const mc_ctx *ctx, mc_info *info);
+
+int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out);
+/* Copy up to cap exit records (sorted by pack id) into buf; *n receives the
+ * total number recorded (may exceed cap). */
+int32_t mc_read_exits(mc_ctx *ctx, mc_exit_rec *buf, int64_t cap, int64_t *n);
+int32_t mc_read_packs(mc_ctx *ctx, mc_packs *out);
+int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in);
+/* int64 charge grid of the last deposit, nz*nr, units of 2^-32 e. */
+int32_t mc_read_charge(mc_ctx *ctx, int64_t *q);
+/* Space-charge potential and field of the last update (nz*nr each; nullable). */
+int32_t mc_read_sc(mc_ctx *ctx, double *phi, double *er, double *ez);
+/* Electrode hit table (nz*nr bytes). */
+int32_t mc_read_hit(mc_ctx *ctx, uint8_t *hit);
+int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out);
+int32_t mc_reset_timing(mc_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

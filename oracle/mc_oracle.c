@@ -391,11 +391,12 @@ typedef struct {
 
 static void collide(const coll_env_t *E, const uint32_t key[2], int64_t id, int64_t step, double dt, double v[3],
                     double *e_int, int frozen, coll_count_t *cnt) {
-    if (!(E->n_gas > 0.0)) return;
+    if (!(E->n_gas > 0.0) || !isfinite(E->n_gas)) return;
     double rel0[3] = {v[0] - E->u[0], v[1] - E->u[1], v[2] - E->u[2]};
     double s0 = sqrt(rel0[0] * rel0[0] + rel0[1] * rel0[1] + rel0[2] * rel0[2]);
     double lam0 = E->n_gas * E->sigma * (s0 + E->abar);
-    int64_t cap = 64 + 8 * (int64_t)ceil(lam0 * dt);
+    double nexp = lam0 * dt; /* candidate cap; a non-finite rate ends the loop at once */
+    int64_t cap = (nexp < 1e6) ? 64 + 8 * (int64_t)ceil(nexp) : (nexp >= 1e6 ? 8000064 : 0);
     double t_left = dt;
     for (int64_t c = 0;; ++c) {
         if (c == cap) {
@@ -408,7 +409,7 @@ static void collide(const coll_env_t *E, const uint32_t key[2], int64_t id, int6
         uint32_t wa[4], wb[4], wc[4];
         draw(key, id, step, PURPOSE_COLLIDE, (uint32_t)(3 * c), wa);
         double tau = -log(u01(wa[0])) / lam;
-        if (tau >= t_left) break;
+        if (!(tau < t_left)) break;
         t_left -= tau;
         cnt->n_cand++;
         draw(key, id, step, PURPOSE_COLLIDE, (uint32_t)(3 * c + 1), wb);
@@ -772,6 +773,7 @@ static void deposit(orc_sim *s) {
     memset(s->qgrid, 0, sizeof(int64_t) * (size_t)s->nr * s->nz);
     for (int64_t k = 0; k < s->n; ++k) {
         if (s->status[k] != ORC_ACTIVE) continue;
+        if (!isfinite(s->x[k]) || !isfinite(s->y[k]) || !isfinite(s->z[k])) continue;
         double r = sqrt(s->x[k] * s->x[k] + s->y[k] * s->y[k]);
         double ur = r * s->inv_dr, uz = s->z[k] * s->inv_dz;
         double fi = floor(ur), fj = floor(uz);
@@ -868,7 +870,7 @@ static void advance(orc_sim *s, int64_t k, int64_t step, const double cst[3], co
     } else if (r1 > s->R) cls = ORC_RADIAL;
     else {
         int32_t ii = (int32_t)floor(r1 * s->inv_dr + 0.5), jj = (int32_t)floor(x1[2] * s->inv_dz + 0.5);
-        if (s->hit[(int64_t)jj * s->nr + ii]) {
+        if (ii < s->nr && jj < s->nz && s->hit[(int64_t)jj * s->nr + ii]) {
             cls = ORC_ELECTRODE;
             in = ii;
             jn = jj;
@@ -959,6 +961,9 @@ int32_t orc_write_packs(orc_sim *s, const orc_packs *in) {
     for (int64_t k = 0; k < in->n; ++k) {
         int32_t t = in->tag[k];
         if (t < 0 || t >= s->n_ion) return -1;
+        if (!isfinite(in->x[k]) || !isfinite(in->y[k]) || !isfinite(in->z[k]) || !isfinite(in->vx[k]) ||
+            !isfinite(in->vy[k]) || !isfinite(in->vz[k]) || !isfinite(in->e_int[k]) || !isfinite(in->w[k]))
+            return -1;
         s->x[k] = in->x[k]; s->y[k] = in->y[k]; s->z[k] = in->z[k];
         s->vx[k] = in->vx[k]; s->vy[k] = in->vy[k]; s->vz[k] = in->vz[k];
         s->eint[k] = in->e_int[k]; s->h[k] = in->h[k]; s->w[k] = in->w[k];
@@ -977,18 +982,19 @@ int32_t orc_write_packs(orc_sim *s, const orc_packs *in) {
 static int bin_ke(double ke_ev) {
     if (!(ke_ev > 0.0)) return 0;
     double u = (log10(ke_ev) + 3.0) * (200.0 / 6.0);
-    if (u < 0.0) return 0;
+    if (!(u >= 0.0)) return 0;
     if (u >= 200.0) return 201;
     return 1 + (int)floor(u);
 }
 static int bin_teff(double t) {
     double u = t * (200.0 / 5000.0);
-    if (u < 0.0) return 0;
+    if (!(u >= 0.0)) return 0;
     if (u >= 200.0) return 201;
     return 1 + (int)floor(u);
 }
 static int bin_r(double r, double rdet) {
     double u = r / rdet * 100.0;
+    if (!(u >= 0.0)) return 0;
     if (u >= 100.0) return 101;
     return 1 + (int)floor(u);
 }

@@ -1,0 +1,193 @@
+// mc_device.hpp -- device-side building blocks of the ion-pack step on gfx950.
+//
+// Precision policies (P64: FP64 state, math and tables; P32: FP32 math,
+// two-float positions and internal energy, BF16 or FP32 tables with a
+// per-table scale), the Philox4x32-10 counter generator, uniform and normal
+// draws, bilinear table access and the Einstein heat-capacity conversion.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mc {
+
+// Exact SI constants and CODATA 2022 values.
+constexpr double kB = 1.380649e-23;
+constexpr double kQe = 1.602176634e-19;
+constexpr double kH = 6.62607015e-34;
+constexpr double kNA = 6.02214076e23;
+constexpr double kEps0 = 8.8541878188e-12;
+constexpr double kDa = 1.66053906892e-27;
+constexpr double kPi = 3.14159265358979323846;
+
+enum : int32_t { ST_ACTIVE = 0, ST_TRANSMITTED = 1, ST_ELECTRODE = 2, ST_RADIAL = 3, ST_AXIAL = 4, ST_NUMERIC = 5 };
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// with multipliers 0xD2511F53 and 0xCD9E8D57, key bumped by the Weyl
+// constants 0x9E3779B9 / 0xBB67AE85 after each round.  The key is uniform
+// across a wavefront, so the key schedule lives in scalar registers.
+// Stream layout: counter = (pack id low 32, step, purpose << 24 | block,
+// pack id high 32); purpose 0 = emission, 1 = collisions.
+// ---------------------------------------------------------------------------
+struct W4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)0xD2511F53u * c0;
+        const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(pb >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(pa >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)pb;
+        c3 = (uint32_t)pa;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return W4{c0, c1, c2, c3};
+}
+
+constexpr uint32_t kPurposeEmit = 0u, kPurposeCollide = 1u;
+
+__device__ __forceinline__ W4 draw(int64_t id, int64_t step, uint32_t purpose, uint32_t block, uint32_t k0,
+                                   uint32_t k1) {
+    return philox((uint32_t)((uint64_t)id), (uint32_t)step, (purpose << 24) | block, (uint32_t)((uint64_t)id >> 32),
+                  k0, k1);
+}
+
+// ---------------------------------------------------------------------------
+// Precision policies.
+// ---------------------------------------------------------------------------
+struct P64 {
+    using T = double;
+    static constexpr bool kTwo = false;
+    // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double
+    static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+};
+
+struct P32 {
+    using T = float;
+    static constexpr bool kTwo = true;
+    // the top 24 bits of the same word: ((w >> 8) + 1/2) 2^-24, exact in float
+    static __device__ __forceinline__ float u01(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 0x1p-24f; }
+};
+
+// sin(2 pi u), cos(2 pi u) without a large-argument reduction.
+__device__ __forceinline__ void sincos2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
+__device__ __forceinline__ void sincos2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
+
+// Error-free sum a + b = s + e (Knuth), for two-float accumulation.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// (hi, lo) += d, renormalised.  (The FP64 overload is a plain sum.)
+__device__ __forceinline__ void acc2(double &hi, double &, double d) { hi += d; }
+__device__ __forceinline__ void acc2(float &hi, float &lo, float d) {
+    float s, e;
+    two_sum(hi, d, s, e);
+    e += lo;
+    hi = s + e;
+    lo = e - (hi - s);
+}
+
+// ---------------------------------------------------------------------------
+// Field tables.  Four channels per node, node-interleaved so one bilinear
+// gather reads four 32-byte (FP64), 16-byte (FP32) or 8-byte (BF16) nodes.
+//   E table:   (E_S,r, E_S,z, E_RF,r, E_RF,z)   E_S = E_DC + V_off E_OFF + E_SC
+//   gas table: (u_r, u_z, p, T)
+// ---------------------------------------------------------------------------
+struct bf16x4 {
+    uint16_t a, b, c, d;
+};
+
+__device__ __forceinline__ float bf16_to_f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+template <class T>
+struct Q4 {
+    T a, b, c, d;
+};
+
+__device__ __forceinline__ Q4<double> load4(const double4 *t, int64_t k, const float *) {
+    const double4 v = t[k];
+    return Q4<double>{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Q4<float> load4(const float4 *t, int64_t k, const float *) {
+    const float4 v = t[k];
+    return Q4<float>{v.x, v.y, v.z, v.w};
+}
+__device__ __forceinline__ Q4<float> load4(const bf16x4 *t, int64_t k, const float *sc) {
+    const bf16x4 v = t[k];
+    return Q4<float>{bf16_to_f(v.a) * sc[0], bf16_to_f(v.b) * sc[1], bf16_to_f(v.c) * sc[2], bf16_to_f(v.d) * sc[3]};
+}
+
+// Cell location with clamping (constant extension outside the grid).
+template <class T>
+struct Cell {
+    int32_t i, j;
+    T f, g;
+};
+
+template <class T>
+__device__ __forceinline__ Cell<T> locate(T r, T z, T inv_dr, T inv_dz, int32_t nr, int32_t nz) {
+    const T ur = r * inv_dr, uz = z * inv_dz;
+    T fi = floor(ur), fj = floor(uz);
+    fi = fmin(fmax(fi, (T)0), (T)(nr - 2));
+    fj = fmin(fmax(fj, (T)0), (T)(nz - 2));
+    Cell<T> c;
+    c.f = fmin(fmax(ur - fi, (T)0), (T)1);
+    c.g = fmin(fmax(uz - fj, (T)0), (T)1);
+    c.i = (int32_t)fi;
+    c.j = (int32_t)fj;
+    return c;
+}
+
+template <class T, class Tab>
+__device__ __forceinline__ Q4<T> gather4(const Tab *tab, const float *sc, const Cell<T> &c, int32_t nr) {
+    const int64_t k = (int64_t)c.j * nr + c.i;
+    const Q4<T> t00 = load4(tab, k, sc), t10 = load4(tab, k + 1, sc);
+    const Q4<T> t01 = load4(tab, k + nr, sc), t11 = load4(tab, k + nr + 1, sc);
+    const T w00 = ((T)1 - c.f) * ((T)1 - c.g), w10 = c.f * ((T)1 - c.g);
+    const T w01 = ((T)1 - c.f) * c.g, w11 = c.f * c.g;
+    Q4<T> o;
+    o.a = w00 * t00.a + w10 * t10.a + w01 * t01.a + w11 * t11.a;
+    o.b = w00 * t00.b + w10 * t10.b + w01 * t01.b + w11 * t11.b;
+    o.c = w00 * t00.c + w10 * t10.c + w01 * t01.c + w11 * t11.c;
+    o.d = w00 * t00.d + w10 * t10.d + w01 * t01.d + w11 * t11.d;
+    return o;
+}
+
+// Einstein model inverse: T = theta / ln(1 + s kB theta / U).
+template <class T>
+__device__ __forceinline__ T einstein_t(T e, T skt, T theta) {
+    return e > (T)0 ? theta / log1p(skt / e) : (T)0;
+}
+
+// Dissociation rate k(T) = A T^p exp(-B / T): Eyring (p = 1, A = kB/h e^{dS/R},
+// B = dH/R) or Arrhenius (p = 0, A, B = Ea/kB).
+template <class T>
+__device__ __forceinline__ T rate(int32_t kind, T a, T b, T t) {
+    if (kind == 0 || !(t > (T)0)) return (T)0;
+    const T e = exp(-b / t);
+    return kind == 1 ? a * t * e : a * e;
+}
+
+// Per-species constants resolved on the host at mc_define_ion/mc_set_operating.
+struct Species {
+    double m, qm, ccs, alpha, theta, skt, act_a, act_b, e0;
+    int32_t act_kind, n_atoms;
+};
+
+// Wavefront sum of a 64-bit counter (all lanes participate).
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+}  // namespace mc

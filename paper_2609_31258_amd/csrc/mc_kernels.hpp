@@ -1,0 +1,758 @@
+// mc_kernels.hpp -- HIP kernels of the ion-pack step (gfx950).
+//
+//   k_emit      source emission: truncated Gaussian radius, gas-flow plus
+//               Maxwellian velocity (Eq. 5 and the Gaussian-source section)
+//   k_step      fused per-pack step: RK4 push in E_S + c(t) E_RF (Eqs. 3-4),
+//               terminal classification, collisions (Eq. 6, thinning with
+//               internal-energy exchange), dissociation hazard (Eq. 7),
+//               terminal tallies (Eq. 8)
+//   k_deposit   int64 cloud-in-cell deposit (PIC section)
+//   k_dst_rows, k_thomas, k_idst_rows  cylindrical Poisson solve by a sine
+//               transform along z and one tridiagonal system per mode
+//   k_bake, k_fold  E = -grad(phi) on nodes; folded static field table
+//   k_hit       electrode hit table from the mask and hit distance
+//   k_snapshot  read-time tallies of the active population
+//
+// Everything is compiled with -ffp-contract=off, so the index arithmetic of
+// classification and deposit is plain IEEE and reproducible on any IEEE
+// implementation given the same positions.
+#pragma once
+#include "../../include/mucite.h"
+#include "mc_device.hpp"
+
+namespace mc {
+
+template <class T>
+struct PackPtrs {
+    T *x, *y, *z;      // position (high part in the two-float form)
+    T *xl, *yl, *zl;   // low parts (two-float form only)
+    T *vx, *vy, *vz;
+    T *e, *el;         // internal energy (high, low)
+    T *h;              // dissociation hazard H = integral k(T_eff) dt
+    double *w;         // weight [real ions]
+    int64_t *id, *q;   // pack id (random-stream key), charge [2^-32 e]
+    int32_t *tag, *status;
+};
+
+// int64 tally block.  Layout of cnt: class_n[6], class_w[6], n_cand, n_coll,
+// n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, exit_count.
+enum { TC_CLASS_N = 0, TC_CLASS_W = 6, TC_CAND = 12, TC_COLL = 13, TC_CAP = 14, TC_CLAMP = 15, TC_PACKSTEPS = 16,
+       TC_EXOVER = 17, TC_EXDROP = 18, TC_EXCOUNT = 19, TC_N = 20 };
+
+struct TallyPtrs {
+    unsigned long long *cnt, *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r;
+    mc_exit_rec *exits;
+    int64_t exit_cap;
+};
+
+// ---------------------------------------------------------------------------
+// Histogram bins: KE log10 bins over [1e-3, 1e3] eV, T_eff over [0, 5000] K,
+// exit radius over [0, r_det]; bin 0 = underflow, last = overflow.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int hbin_ke(double ke_ev) {
+    if (!(ke_ev > 0.0)) return 0;
+    const double u = (log10(ke_ev) + 3.0) * (200.0 / 6.0);
+    if (!(u >= 0.0)) return 0;
+    if (u >= 200.0) return 201;
+    return 1 + (int)floor(u);
+}
+__device__ __forceinline__ int hbin_teff(double t) {
+    const double u = t * (200.0 / 5000.0);
+    if (!(u >= 0.0)) return 0;
+    if (u >= 200.0) return 201;
+    return 1 + (int)floor(u);
+}
+__device__ __forceinline__ int hbin_r(double r, double rdet) {
+    const double u = r / rdet * 100.0;
+    if (!(u >= 0.0)) return 0;
+    if (u >= 100.0) return 101;
+    return 1 + (int)floor(u);
+}
+
+__device__ __forceinline__ void atom_add(unsigned long long *p, int64_t v) { atomicAdd(p, (unsigned long long)v); }
+
+__device__ __forceinline__ int64_t fx32(double v) { return (int64_t)rint(ldexp(v, 32)); }
+
+// ---------------------------------------------------------------------------
+// Emission.
+// ---------------------------------------------------------------------------
+template <class P, class Tab>
+struct EmitArgs {
+    PackPtrs<typename P::T> p;
+    const Tab *gtab;
+    float gsc[4];
+    const Species *sp;
+    int64_t slot0, count, id0, step;
+    double sigma_r, r_trunc, z_inj, w;
+    int64_t q;
+    double inv_dr, inv_dz;
+    int32_t nr, nz, ion;
+    uint32_t k0, k1;
+};
+
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_emit(EmitArgs<P, Tab> a) {
+    using T = typename P::T;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.count) return;
+    const int64_t id = a.id0 + k, s = a.slot0 + k;
+    const W4 wa = draw(id, a.step, kPurposeEmit, 0u, a.k0, a.k1);
+    const W4 wb = draw(id, a.step, kPurposeEmit, 1u, a.k0, a.k1);
+    const Species sp = a.sp[a.ion];
+    const T sg = (T)a.sigma_r, rt = (T)a.r_trunc;
+    const T r = sg * sqrt((T)-2 * log((T)1 - P::u01(wa.w0) * ((T)1 - exp(-rt * rt / ((T)2 * sg * sg)))));
+    T sph, cph;
+    sincos2pi(P::u01(wa.w1), &sph, &cph);
+    const T z = (T)a.z_inj;
+    const Cell<T> c = locate<T>(r, z, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
+    const Q4<T> g = gather4<T>(a.gtab, a.gsc, c, a.nr);
+    const T vth = sqrt((T)kB * g.d / (T)sp.m);
+    const T r1 = sqrt((T)-2 * log(P::u01(wa.w2))), r2 = sqrt((T)-2 * log(P::u01(wb.w0)));
+    T s1, c1, s2, c2;
+    sincos2pi(P::u01(wa.w3), &s1, &c1);
+    sincos2pi(P::u01(wb.w1), &s2, &c2);
+    a.p.x[s] = r * cph;
+    a.p.y[s] = r * sph;
+    a.p.z[s] = z;
+    const T ehi = (T)sp.e0;
+    a.p.e[s] = ehi;
+    if constexpr (P::kTwo) {
+        a.p.xl[s] = 0;
+        a.p.yl[s] = 0;
+        a.p.zl[s] = 0;
+        a.p.el[s] = (T)(sp.e0 - (double)ehi);
+    }
+    a.p.vx[s] = g.a * cph + vth * r1 * c1;
+    a.p.vy[s] = g.a * sph + vth * r1 * s1;
+    a.p.vz[s] = g.b + vth * r2 * c2;
+    a.p.h[s] = 0;
+    a.p.w[s] = a.w;
+    a.p.id[s] = id;
+    a.p.q[s] = a.q;
+    a.p.tag[s] = a.ion;
+    a.p.status[s] = ST_ACTIVE;
+}
+
+// ---------------------------------------------------------------------------
+// Fused step.
+// ---------------------------------------------------------------------------
+template <class P, class Tab>
+struct StepArgs {
+    PackPtrs<typename P::T> p;
+    const Tab *etab, *gtab;
+    float esc[4], gsc[4];
+    const uint8_t *hit;
+    const Species *sp;
+    TallyPtrs t;
+    int64_t n_slots, step;
+    double dt, t0, c0, ch, c1;      // c = V_RF cos(2 pi f t + phase) at t0, t0 + dt/2, t0 + dt
+    double z_det, r_det, R, inv_dr, inv_dz, mg, exit_bin_dt;
+    int32_t nr, nz, n_exit_bins, collisions_on;
+    uint32_t k0, k1;
+};
+
+template <class P, class Tab>
+__device__ __forceinline__ void efield(const StepArgs<P, Tab> &a, typename P::T x, typename P::T y,
+                                       typename P::T z, typename P::T c, typename P::T &ex, typename P::T &ey,
+                                       typename P::T &ez) {
+    using T = typename P::T;
+    const T r = sqrt(x * x + y * y);
+    const Cell<T> cl = locate<T>(r, z, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
+    const Q4<T> q = gather4<T>(a.etab, a.esc, cl, a.nr);
+    const T er = q.a + c * q.c;
+    ez = q.b + c * q.d;
+    if (r > (T)0) {
+        const T s = er / r;
+        ex = s * x;
+        ey = s * y;
+    } else {
+        ex = (T)0;
+        ey = (T)0;
+    }
+}
+
+template <class P, class Tab>
+__device__ __noinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s, int32_t cls, int32_t in, int32_t jn,
+                                         double x, double y, double z, double vx, double vy, double vz, double tc,
+                                         double rc, double eint, double h, const Species &sp) {
+    const double w = a.p.w[s];
+    const int64_t wfx = fx32(w);
+    atom_add(&a.t.cnt[TC_CLASS_N + cls], 1);
+    atom_add(&a.t.cnt[TC_CLASS_W + cls], wfx);
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    const double ke = 0.5 * sp.m * v2;
+    const double te = eint > 0.0 ? sp.theta / log1p(sp.skt / eint) : 0.0;
+    if (cls == ST_ELECTRODE) atom_add(&a.t.loss_map[(int64_t)jn * a.nr + in], wfx);
+    if (cls == ST_TRANSMITTED) {
+        const double u = tc / a.exit_bin_dt;
+        if (u >= 0.0 && u < (double)a.n_exit_bins) atom_add(&a.t.exit_bins[(int64_t)floor(u)], wfx);
+        else atom_add(&a.t.cnt[TC_EXOVER], wfx);
+        atom_add(&a.t.hist_ke[hbin_ke(ke / kQe)], wfx);
+        atom_add(&a.t.hist_teff[hbin_teff(te)], wfx);
+        atom_add(&a.t.hist_r[hbin_r(rc, a.r_det)], wfx);
+    }
+    const unsigned long long slot = atomicAdd(&a.t.cnt[TC_EXCOUNT], 1ull);
+    if ((int64_t)slot < a.t.exit_cap) {
+        mc_exit_rec r;
+        r.id = a.p.id[s];
+        r.step = a.step;
+        r.cls = cls;
+        r.inode = in;
+        r.jnode = jn;
+        r.tag = a.p.tag[s];
+        r.x = x; r.y = y; r.z = z;
+        r.vx = vx; r.vy = vy; r.vz = vz;
+        r.t_cross = tc;
+        r.r_cross = rc;
+        r.ke_ev = ke / kQe;
+        r.t_eff = te;
+        r.h = h;
+        r.w = w;
+        a.t.exits[slot] = r;
+    } else {
+        atom_add(&a.t.cnt[TC_EXDROP], 1);
+    }
+}
+
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
+    using T = typename P::T;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nact = 0;
+    if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
+        nact = 1;
+        const Species sp = a.sp[a.p.tag[s]];
+        const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
+        const T x0 = a.p.x[s], y0 = a.p.y[s], z0 = a.p.z[s];
+        T xl = 0, yl = 0, zl = 0;
+        if constexpr (P::kTwo) {
+            xl = a.p.xl[s];
+            yl = a.p.yl[s];
+            zl = a.p.zl[s];
+        }
+        const T vx0 = a.p.vx[s], vy0 = a.p.vy[s], vz0 = a.p.vz[s];
+
+        // ---- classical RK4 on (x, v); stages at t, t + dt/2, t + dt/2, t + dt ----
+        T ex, ey, ez;
+        efield(a, x0, y0, z0, (T)a.c0, ex, ey, ez);
+        T ax = qm * ex, ay = qm * ey, az = qm * ez;
+        T sxx = vx0, sxy = vy0, sxz = vz0, svx = ax, svy = ay, svz = az;
+        T kx = vx0 + hd * ax, ky = vy0 + hd * ay, kz = vz0 + hd * az;
+        efield(a, x0 + (xl + hd * vx0), y0 + (yl + hd * vy0), z0 + (zl + hd * vz0), (T)a.ch, ex, ey, ez);
+        ax = qm * ex; ay = qm * ey; az = qm * ez;
+        sxx += (T)2 * kx; sxy += (T)2 * ky; sxz += (T)2 * kz;
+        svx += (T)2 * ax; svy += (T)2 * ay; svz += (T)2 * az;
+        const T k2x = kx, k2y = ky, k2z = kz;
+        kx = vx0 + hd * ax; ky = vy0 + hd * ay; kz = vz0 + hd * az;
+        efield(a, x0 + (xl + hd * k2x), y0 + (yl + hd * k2y), z0 + (zl + hd * k2z), (T)a.ch, ex, ey, ez);
+        ax = qm * ex; ay = qm * ey; az = qm * ez;
+        sxx += (T)2 * kx; sxy += (T)2 * ky; sxz += (T)2 * kz;
+        svx += (T)2 * ax; svy += (T)2 * ay; svz += (T)2 * az;
+        const T k3x = kx, k3y = ky, k3z = kz;
+        kx = vx0 + dt * ax; ky = vy0 + dt * ay; kz = vz0 + dt * az;
+        efield(a, x0 + (xl + dt * k3x), y0 + (yl + dt * k3y), z0 + (zl + dt * k3z), (T)a.c1, ex, ey, ez);
+        ax = qm * ex; ay = qm * ey; az = qm * ez;
+        sxx += kx; sxy += ky; sxz += kz;
+        svx += ax; svy += ay; svz += az;
+        const T d6 = dt / (T)6;
+        T x1 = x0, y1 = y0, z1 = z0;
+        if constexpr (P::kTwo) {
+            acc2(x1, xl, d6 * sxx);
+            acc2(y1, yl, d6 * sxy);
+            acc2(z1, zl, d6 * sxz);
+        } else {
+            x1 = x0 + d6 * sxx;
+            y1 = y0 + d6 * sxy;
+            z1 = z0 + d6 * sxz;
+        }
+        T vx = vx0 + d6 * svx, vy = vy0 + d6 * svy, vz = vz0 + d6 * svz;
+        T e = a.p.e[s], el = P::kTwo ? a.p.el[s] : (T)0;
+
+        // ---- terminal classification at the new position ----
+        // (FP64 form: the same IEEE operations as any reference; the
+        // two-float form classifies its full-precision position in FP64)
+        const double X0 = (double)x0, Y0 = (double)y0, Zo = (double)z0 + (P::kTwo ? (double)a.p.zl[s] : 0.0);
+        const double X1 = (double)x1 + (double)xl, Y1 = (double)y1 + (double)yl, Z1 = (double)z1 + (double)zl;
+        int32_t cls = ST_ACTIVE, in = -1, jn = -1;
+        double tcross = 0.0, rcross = 0.0;
+        const double r1 = sqrt(X1 * X1 + Y1 * Y1);
+        const bool finite = isfinite(X1) && isfinite(Y1) && isfinite(Z1) && isfinite((double)vx) &&
+                            isfinite((double)vy) && isfinite((double)vz);
+        if (!finite) {
+            cls = ST_NUMERIC;
+        } else if (Z1 >= a.z_det || Z1 < 0.0) {
+            const double zp = Z1 >= a.z_det ? a.z_det : 0.0;
+            const double XA = X0 + (P::kTwo ? (double)a.p.xl[s] : 0.0), YA = Y0 + (P::kTwo ? (double)a.p.yl[s] : 0.0);
+            const double fr = (Z1 != Zo) ? (zp - Zo) / (Z1 - Zo) : 1.0;
+            const double xc = XA + fr * (X1 - XA), yc = YA + fr * (Y1 - YA);
+            rcross = sqrt(xc * xc + yc * yc);
+            tcross = a.t0 + fr * a.dt;
+            cls = (Z1 >= a.z_det && rcross <= a.r_det) ? ST_TRANSMITTED : ST_AXIAL;
+        } else if (r1 > a.R) {
+            cls = ST_RADIAL;
+        } else {
+            const int32_t ii = (int32_t)floor(r1 * a.inv_dr + 0.5), jj = (int32_t)floor(Z1 * a.inv_dz + 0.5);
+            if (ii < a.nr && jj < a.nz && a.hit[(int64_t)jj * a.nr + ii]) {
+                cls = ST_ELECTRODE;
+                in = ii;
+                jn = jj;
+            }
+        }
+
+        if (cls == ST_ACTIVE && a.collisions_on) {
+            // ---- collisions with the gas at the new position ----
+            const T rr = (T)r1;
+            const Cell<T> cl = locate<T>(rr, z1, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
+            const Q4<T> g = gather4<T>(a.gtab, a.gsc, cl, a.nr);
+            T ux = 0, uy = 0;
+            if (rr > (T)0) {
+                const T sr = g.a / rr;
+                ux = sr * x1;
+                uy = sr * y1;
+            }
+            const T uz = g.b;
+            const T tg = g.d;
+            const T m = (T)sp.m, mg = (T)a.mg;
+            const T ngs = tg > (T)0 ? g.c / ((T)kB * tg) * (T)sp.ccs : (T)0;  // n_gas * sigma
+            if (ngs > (T)0 && isfinite(ngs)) {
+                const T ag = sqrt((T)kB * tg / mg);
+                const T abar = ag * (T)1.5957691216057308;  // sqrt(8/pi)
+                const T M = m + mg, fm = mg / M, fi = m / M, mu = mg * fi;  // mu without the m*mg product (FP32 range)
+                const T alpha = (T)sp.alpha, skt = (T)sp.skt, theta = (T)sp.theta;
+                T rx = vx - ux, ry = vy - uy, rz = vz - uz;
+                T sv = sqrt(rx * rx + ry * ry + rz * rz);
+                T lam = ngs * (sv + abar);
+                // candidate cap; a non-finite rate ends the loop at once
+                const T nexp = lam * dt;
+                const int64_t cap = (nexp < (T)1e6) ? 64 + 8 * (int64_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
+                T tleft = dt;
+                const int64_t id = a.p.id[s];
+                for (int64_t c = 0;; ++c) {
+                    if (c == cap) {
+                        ++ncap;
+                        break;
+                    }
+                    const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), a.k0, a.k1);
+                    const T tau = -log(P::u01(wa.w0)) / lam;
+                    if (!(tau < tleft)) break;
+                    tleft -= tau;
+                    ++ncand;
+                    const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), a.k0, a.k1);
+                    T wx, wy, wz, wn;
+                    if (P::u01(wa.w1) < sv / (sv + abar)) {
+                        // Maxwellian partner by Box-Muller
+                        const T q1 = ag * sqrt((T)-2 * log(P::u01(wa.w2)));
+                        const T q2 = ag * sqrt((T)-2 * log(P::u01(wb.w0)));
+                        T s1, c1, s2, c2;
+                        sincos2pi(P::u01(wa.w3), &s1, &c1);
+                        sincos2pi(P::u01(wb.w1), &s2, &c2);
+                        wx = q1 * c1;
+                        wy = q1 * s1;
+                        wz = q2 * c2;
+                        wn = sqrt(wx * wx + wy * wy + wz * wz);
+                    } else {
+                        // flux-weighted partner: |w|^2 / 2 a^2 ~ Gamma(2, 1), isotropic
+                        wn = ag * sqrt((T)-2 * log(P::u01(wa.w2) * P::u01(wa.w3)));
+                        const T ct = (T)2 * P::u01(wb.w0) - (T)1;
+                        const T st = sqrt(fmax((T)0, (T)1 - ct * ct));
+                        T sp_, cp_;
+                        sincos2pi(P::u01(wb.w1), &sp_, &cp_);
+                        wx = wn * st * cp_;
+                        wy = wn * st * sp_;
+                        wz = wn * ct;
+                    }
+                    const T gx = rx - wx, gy = ry - wy, gz = rz - wz;
+                    const T g2 = gx * gx + gy * gy + gz * gz;
+                    const T gn = sqrt(g2);
+                    if (!(P::u01(wb.w2) * (sv + wn) < gn)) continue;
+                    ++nacc;
+                    const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), a.k0, a.k1);
+                    // centre of mass of the ion and the partner (lab velocity u + w)
+                    const T vcx = fi * vx + fm * (ux + wx), vcy = fi * vy + fm * (uy + wy), vcz = fi * vz + fm * (uz + wz);
+                    const T et = (T)0.5 * mu * g2;
+                    T etp = et;
+                    if (P::u01(wc.w1) < alpha) {
+                        const T te = einstein_t<T>(e + el, skt, theta);
+                        etp = -(T)kB * te * log(P::u01(wc.w2) * P::u01(wc.w3));
+                        const T de = et - etp;
+                        if (e + el + de < (T)0) {
+                            etp = e + el + et;
+                            e = 0;
+                            el = 0;
+                            ++nclamp;
+                        } else if constexpr (P::kTwo) {
+                            acc2(e, el, de);
+                        } else {
+                            e = e + de;
+                        }
+                    }
+                    const T cchi = (T)2 * P::u01(wb.w3) - (T)1;
+                    const T schi = sqrt(fmax((T)0, (T)1 - cchi * cchi));
+                    T sps, cps;
+                    sincos2pi(P::u01(wc.w0), &sps, &cps);
+                    const T f = fm * sqrt((T)2 * etp / mu);
+                    vx = vcx + f * schi * cps;
+                    vy = vcy + f * schi * sps;
+                    vz = vcz + f * cchi;
+                    rx = vx - ux;
+                    ry = vy - uy;
+                    rz = vz - uz;
+                    sv = sqrt(rx * rx + ry * ry + rz * rz);
+                    lam = ngs * (sv + abar);
+                }
+            }
+        }
+
+        if (cls == ST_ACTIVE) {
+            // ---- Eq. 7: hazard with the post-collision effective temperature ----
+            const T te = einstein_t<T>(e + el, (T)sp.skt, (T)sp.theta);
+            T h = a.p.h[s] + rate<T>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * dt;
+            a.p.h[s] = h;
+            a.p.e[s] = e;
+            if constexpr (P::kTwo) a.p.el[s] = el;
+        } else {
+            const double E = (double)e + (double)el;
+            record_exit(a, s, cls, in, jn, X1, Y1, Z1, (double)vx, (double)vy, (double)vz, tcross, rcross, E,
+                        (double)a.p.h[s], sp);
+            a.p.status[s] = cls;
+        }
+        a.p.x[s] = x1;
+        a.p.y[s] = y1;
+        a.p.z[s] = z1;
+        if constexpr (P::kTwo) {
+            a.p.xl[s] = xl;
+            a.p.yl[s] = yl;
+            a.p.zl[s] = zl;
+        }
+        a.p.vx[s] = vx;
+        a.p.vy[s] = vy;
+        a.p.vz[s] = vz;
+    }
+    // wavefront-aggregated counters
+    const uint64_t sc = wave_sum_u64(ncand), sa = wave_sum_u64(nacc);
+    const uint64_t sp_ = wave_sum_u64(ncap), sl = wave_sum_u64(nclamp), sn = wave_sum_u64(nact);
+    if ((threadIdx.x & 63) == 0) {
+        if (sn) atomicAdd(&a.t.cnt[TC_PACKSTEPS], (unsigned long long)sn);
+        if (sc) atomicAdd(&a.t.cnt[TC_CAND], (unsigned long long)sc);
+        if (sa) atomicAdd(&a.t.cnt[TC_COLL], (unsigned long long)sa);
+        if (sp_) atomicAdd(&a.t.cnt[TC_CAP], (unsigned long long)sp_);
+        if (sl) atomicAdd(&a.t.cnt[TC_CLAMP], (unsigned long long)sl);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CIC deposit: bilinear split of the int64 pack charge, exact per pack:
+//   a = rint(Q (1-f)), b = Q - a, a0 = rint(a (1-g)), a1 = a - a0,
+//   b0 = rint(b (1-g)), b1 = b - b0.
+// ---------------------------------------------------------------------------
+template <class T>
+struct DepositArgs {
+    PackPtrs<T> p;
+    unsigned long long *q;
+    int64_t n_slots;
+    double inv_dr, inv_dz;
+    int32_t nr, nz;
+};
+
+template <class P>
+__global__ __launch_bounds__(256) void k_deposit(DepositArgs<typename P::T> a) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= a.n_slots || a.p.status[s] != ST_ACTIVE) return;
+    double X = a.p.x[s], Y = a.p.y[s], Z = a.p.z[s];
+    if constexpr (P::kTwo) {
+        X += (double)a.p.xl[s];
+        Y += (double)a.p.yl[s];
+        Z += (double)a.p.zl[s];
+    }
+    if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) return;
+    const double r = sqrt(X * X + Y * Y);
+    const double ur = r * a.inv_dr, uz = Z * a.inv_dz;
+    double fi = floor(ur), fj = floor(uz);
+    if (fi > (double)(a.nr - 2)) fi = (double)(a.nr - 2);
+    if (fj > (double)(a.nz - 2)) fj = (double)(a.nz - 2);
+    if (fj < 0.0) fj = 0.0;
+    double f = ur - fi, g = uz - fj;
+    if (f > 1.0) f = 1.0;
+    if (g > 1.0) g = 1.0;
+    if (g < 0.0) g = 0.0;
+    const int64_t Q = a.p.q[s];
+    const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
+    const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
+    const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
+    const int64_t k = (int64_t)fj * a.nr + (int64_t)fi;
+    atom_add(&a.q[k], a0);
+    atom_add(&a.q[k + a.nr], a1);
+    atom_add(&a.q[k + 1], b0);
+    atom_add(&a.q[k + a.nr + 1], b1);
+}
+
+// ---------------------------------------------------------------------------
+// Poisson: unknowns Phi[i][j], 0 <= i <= nr-2, 1 <= j <= nz-2 (m = nz-2).
+// Right-hand side b = -rho/eps0 with rho = Q e 2^-32 / V_i, V_0 = pi dr^2 dz/3,
+// V_i = 2 pi r_i dr dz.  Forward DST-I per radial row (scaled 2/(m+1)), one
+// tridiagonal system per mode (coefficients precomputed), inverse DST-I.
+// Row-major work arrays bh[i][k], k contiguous.
+// ---------------------------------------------------------------------------
+template <class D>
+__global__ __launch_bounds__(256) void k_dst_rows(const unsigned long long *q, const double *sine, D *bh,
+                                                  int32_t nr, int32_t nz, double dr, double dz) {
+    extern __shared__ unsigned char smem_raw[];
+    D *row = reinterpret_cast<D *>(smem_raw);
+    const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
+    const double vol = (i == 0) ? kPi * dr * dr * dz / 3.0 : 2.0 * kPi * ((double)i * dr) * dr * dz;
+    const double scale = -kQe * 0x1p-32 / (vol * kEps0);
+    for (int32_t j = threadIdx.x; j < m; j += blockDim.x)
+        row[j] = (D)((double)(int64_t)q[(int64_t)(j + 1) * nr + i] * scale);
+    __syncthreads();
+    const D norm = (D)(2.0 / (double)(nz - 1));
+    for (int32_t k = 1 + threadIdx.x; k <= m; k += blockDim.x) {
+        D acc = 0;
+        int32_t idx = 0;
+        for (int32_t j = 1; j <= m; ++j) {
+            idx += k;
+            if (idx >= n2) idx -= n2;
+            acc += row[j - 1] * (D)sine[idx];
+        }
+        bh[(int64_t)i * m + (k - 1)] = acc * norm;
+    }
+}
+
+// Tridiagonal coefficients per (row i, mode k): cp = up / den, inv = 1 / den,
+// den_i = diag_i(k) - lo_i cp_{i-1}; diag = -(lo + up) + lambda_k,
+// lambda_k = -(4/dz^2) sin^2(pi k / (2 (nz-1))).
+__global__ __launch_bounds__(256) void k_thomas_coef(double *cp, double *inv, int32_t nr, int32_t nz, double dr,
+                                                     double dz) {
+    const int32_t m = nz - 2, nu = nr - 1;
+    const int32_t k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > m) return;
+    const double sk = sin(kPi * (double)k / (2.0 * (double)(nz - 1)));
+    const double lam = -(4.0 / (dz * dz)) * sk * sk;
+    double cprev = 0.0;
+    for (int32_t i = 0; i < nu; ++i) {
+        double lo, up, di;
+        if (i == 0) {
+            lo = 0.0;
+            di = -4.0 / (dr * dr) + lam;
+            up = 4.0 / (dr * dr);
+        } else {
+            const double ri = (double)i * dr;
+            lo = (ri - 0.5 * dr) / (ri * dr * dr);
+            up = (ri + 0.5 * dr) / (ri * dr * dr);
+            di = -(lo + up) + lam;
+        }
+        const double den = (i == 0) ? di : di - lo * cprev;
+        cprev = up / den;
+        cp[(int64_t)i * m + (k - 1)] = cprev;
+        inv[(int64_t)i * m + (k - 1)] = 1.0 / den;
+    }
+}
+
+template <class D>
+__global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const double *inv, int32_t nr, int32_t nz,
+                                                double dr) {
+    const int32_t m = nz - 2, nu = nr - 1;
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    // forward sweep in FP64
+    double dprev = 0.0;
+    for (int32_t i = 0; i < nu; ++i) {
+        const int64_t o = (int64_t)i * m + k;
+        double lo = 0.0;
+        if (i > 0) {
+            const double ri = (double)i * dr;
+            lo = (ri - 0.5 * dr) / (ri * dr * dr);
+        }
+        dprev = ((double)bh[o] - lo * dprev) * inv[o];
+        bh[o] = (D)dprev;
+    }
+    double x = 0.0;
+    for (int32_t i = nu - 1; i >= 0; --i) {
+        const int64_t o = (int64_t)i * m + k;
+        x = (i == nu - 1) ? (double)bh[o] : (double)bh[o] - cp[o] * x;
+        bh[o] = (D)x;
+    }
+}
+
+template <class D>
+__global__ __launch_bounds__(256) void k_idst_rows(const D *ph, const double *sine, double *phi, int32_t nr,
+                                                   int32_t nz) {
+    extern __shared__ unsigned char smem_raw[];
+    D *row = reinterpret_cast<D *>(smem_raw);
+    const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
+    for (int32_t k = threadIdx.x; k < m; k += blockDim.x) row[k] = ph[(int64_t)i * m + k];
+    __syncthreads();
+    for (int32_t j = 1 + threadIdx.x; j <= m; j += blockDim.x) {
+        D acc = 0;
+        int32_t idx = 0;
+        for (int32_t k = 1; k <= m; ++k) {
+            idx += j;
+            if (idx >= n2) idx -= n2;
+            acc += row[k - 1] * (D)sine[idx];
+        }
+        phi[(int64_t)j * nr + i] = (double)acc;
+    }
+}
+
+// E = -grad(phi) on nodes: central differences, one-sided at the outer
+// edges, E_r = 0 on the axis.
+__global__ __launch_bounds__(256) void k_bake(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
+                                              double dz) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)nr * nz) return;
+    const int32_t i = (int32_t)(n % nr), j = (int32_t)(n / nr);
+    double vr, vz;
+    if (i == 0) vr = 0.0;
+    else if (i == nr - 1) vr = -(phi[n] - phi[n - 1]) / dr;
+    else vr = -(phi[n + 1] - phi[n - 1]) / (2.0 * dr);
+    if (j == 0) vz = -(phi[n + nr] - phi[n]) / dz;
+    else if (j == nz - 1) vz = -(phi[n] - phi[n - nr]) / dz;
+    else vz = -(phi[n + nr] - phi[n - nr]) / (2.0 * dz);
+    e[n] = make_double2(vr, vz);
+}
+
+// Folded static table: (E_DC + V_off E_OFF + E_SC, E_RF), converted to the
+// table format with per-channel scales.
+__device__ __forceinline__ void put4(double4 *t, int64_t n, double a, double b, double c, double d, const float *) {
+    t[n] = make_double4(a, b, c, d);
+}
+__device__ __forceinline__ void put4(float4 *t, int64_t n, double a, double b, double c, double d, const float *) {
+    t[n] = make_float4((float)a, (float)b, (float)c, (float)d);
+}
+__device__ __forceinline__ uint16_t f_to_bf16(float f) {
+    // round to nearest even on the upper 16 bits
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ void put4(bf16x4 *t, int64_t n, double a, double b, double c, double d, const float *sc) {
+    t[n] = bf16x4{f_to_bf16((float)(a / sc[0])), f_to_bf16((float)(b / sc[1])), f_to_bf16((float)(c / sc[2])),
+                  f_to_bf16((float)(d / sc[3]))};
+}
+
+template <class Tab>
+__global__ __launch_bounds__(256) void k_fold(Tab *etab, const double2 *edc, const double2 *eoff, const double2 *esc,
+                                              const double2 *erf, double v_off, int64_t nn, float s0, float s1,
+                                              float s2, float s3) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const double2 d = edc[n], o = eoff[n], c = esc[n], r = erf[n];
+    const float sc[4] = {s0, s1, s2, s3};
+    put4(etab, n, d.x + v_off * o.x + c.x, d.y + v_off * o.y + c.y, r.x, r.y, sc);
+}
+
+template <class Tab>
+__global__ __launch_bounds__(256) void k_gas(Tab *gtab, const double *ur, const double *uz, const double *p,
+                                             const double *t, int64_t nn, float s0, float s1, float s2, float s3) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    const float sc[4] = {s0, s1, s2, s3};
+    put4(gtab, n, ur[n], uz[n], p[n], t[n], sc);
+}
+
+// Electrode hit table: metal node, or a metal node within d_hit + h/2.
+__global__ __launch_bounds__(256) void k_hit(const uint8_t *mask, uint8_t *hit, int32_t nr, int32_t nz, double dr,
+                                             double dz, double reach, int32_t wi, int32_t wj) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)nr * nz) return;
+    const int32_t i = (int32_t)(n % nr), j = (int32_t)(n / nr);
+    uint8_t h = mask[n];
+    for (int32_t b = -wj; b <= wj && !h; ++b)
+        for (int32_t a = -wi; a <= wi && !h; ++a) {
+            const int32_t ii = i + a, jj = j + b;
+            if (ii < 0 || jj < 0 || ii >= nr || jj >= nz) continue;
+            if (!mask[(int64_t)jj * nr + ii]) continue;
+            const double dx = a * dr, dy = b * dz;
+            if (dx * dx + dy * dy <= reach * reach) h = 1;
+        }
+    hit[n] = h;
+}
+
+// Snapshot pack initialisation after a host write: charge from the ion
+// charge and weight, status active.
+template <class T>
+__global__ __launch_bounds__(256) void k_init_written(PackPtrs<T> p, const Species *sp, const int32_t *charge,
+                                                      int64_t n) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    p.q[s] = fx32((double)charge[p.tag[s]] * p.w[s]);
+    p.status[s] = ST_ACTIVE;
+}
+
+// ---------------------------------------------------------------------------
+// Read-time tallies: active count/weight and histograms (int64 atomics), and
+// FP64 sums reduced per block in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *sp, int64_t n_slots,
+                                                  unsigned long long *act, unsigned long long *hke,
+                                                  unsigned long long *hte, double *partial) {
+    __shared__ double red[3][256];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    if (s < n_slots) {
+        const Species S = sp[p.tag[s]];
+        const double w = p.w[s];
+        const double e = (double)p.e[s] + (p.el ? (double)p.el[s] : 0.0);
+        if (p.status[s] == ST_ACTIVE) {
+            const double vx = p.vx[s], vy = p.vy[s], vz = p.vz[s];
+            const double ke = 0.5 * S.m * (vx * vx + vy * vy + vz * vz);
+            const double te = e > 0.0 ? S.theta / log1p(S.skt / e) : 0.0;
+            const int64_t wfx = fx32(w);
+            atom_add(&act[0], 1);
+            atom_add(&act[1], wfx);
+            atom_add(&hke[hbin_ke(ke / kQe)], wfx);
+            atom_add(&hte[hbin_teff(te)], wfx);
+            a0 = w * ke;
+            a1 = w * e;
+        } else {
+            a2 = w * (-expm1(-(double)p.h[s]));
+        }
+    }
+    red[0][threadIdx.x] = a0;
+    red[1][threadIdx.x] = a1;
+    red[2][threadIdx.x] = a2;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + o];
+            red[1][threadIdx.x] += red[1][threadIdx.x + o];
+            red[2][threadIdx.x] += red[2][threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        partial[3 * (int64_t)blockIdx.x + 0] = red[0][0];
+        partial[3 * (int64_t)blockIdx.x + 1] = red[1][0];
+        partial[3 * (int64_t)blockIdx.x + 2] = red[2][0];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, int64_t nb, double *out) {
+    __shared__ double red[3][256];
+    double a[3] = {0.0, 0.0, 0.0};
+    for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
+        for (int c = 0; c < 3; ++c) a[c] += partial[3 * b + c];
+    for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = a[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) out[c] = red[c][0];
+}
+
+// Small utilities.
+__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void k_sine_table(double *s, int32_t nz) {
+    const int32_t n2 = 2 * (nz - 1);
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n2) s[q] = sin(kPi * (double)q / (double)(nz - 1));
+}
+
+}  // namespace mc

@@ -1,0 +1,999 @@
+// mc_runtime.hip -- host runtime and C ABI of the ion-pack library (gfx950).
+//
+// One context = one simulation on one GPU: baked field tables, ion species,
+// sources, an operating point, a structure-of-arrays pack store, int64
+// tallies and an exit-record buffer.  Every per-step operation is a kernel
+// from mc_kernels.hpp enqueued on the context stream; the host only keeps
+// integer bookkeeping (step counter, slot count, the Eq. 5 emission
+// accumulators) and computes the three RF stage coefficients per step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "mc_kernels.hpp"
+
+using namespace mc;
+
+namespace {
+
+constexpr int kBlock = 256;
+
+struct Src {
+    mc_source in;
+    double w;
+    int64_t w_fx, q_fx, n_real_fx, acc_fx, emitted;
+};
+
+struct EvPair {
+    hipEvent_t a, b;
+    int kind;
+};
+
+inline int64_t fx32_host(double v) { return (int64_t)std::llrint(std::ldexp(v, 32)); }
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+struct mc_ctx {
+    mc_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    int64_t device_bytes = 0;
+    std::vector<std::pair<void *, size_t>> allocs;
+
+    bool has_fields = false, has_op = false;
+    int32_t nr = 0, nz = 0;
+    double dr = 0, dz = 0, inv_dr = 0, inv_dz = 0, R = 0;
+
+    double2 *e_dc = nullptr, *e_off = nullptr, *e_rf = nullptr, *e_sc = nullptr;
+    double *phi_sc = nullptr;
+    void *etab = nullptr, *gtab = nullptr;
+    float esc[4] = {1, 1, 1, 1}, gsc[4] = {1, 1, 1, 1};
+    uint8_t *mask = nullptr, *hit = nullptr;
+
+    unsigned long long *qgrid = nullptr;
+    double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
+    void *bh = nullptr;
+
+    std::vector<mc_ion> ions;
+    std::vector<Species> sp_host;
+    std::vector<int32_t> charge_host;
+    Species *sp_dev = nullptr;
+    int32_t *charge_dev = nullptr;
+
+    std::vector<Src> srcs;
+    mc_operating op{};
+
+    int64_t cap = 0, n_slots = 0;
+    PackPtrs<double> p64{};
+    PackPtrs<float> p32{};
+
+    unsigned long long *tal = nullptr;  // cnt | exit_bins | loss_map | hist_ke | hist_teff | hist_r
+    TallyPtrs tp{};
+    int64_t tal_len = 0;
+    unsigned long long *snap = nullptr;  // act[2] | act_hist_ke | act_hist_teff
+    double *partial = nullptr, *sums = nullptr;
+    int64_t partial_len = 0;
+
+    int64_t emitted_n = 0, emitted_w = 0;
+    int64_t step = 0;
+
+    std::vector<EvPair> ev_used;
+    std::vector<hipEvent_t> ev_pool;
+    double t_ms[MC_NKERNEL] = {0};
+    int64_t t_launch[MC_NKERNEL] = {0};
+
+    bool fp32() const { return opt.precision == MC_PREC_FP32; }
+    bool bf16() const { return fp32() && !opt.fp32_tables; }
+};
+
+// ---------------------------------------------------------------------------
+// Errors, allocation, timing.
+// ---------------------------------------------------------------------------
+static int32_t fail(mc_ctx *c, int32_t code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(ctx, MC_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCHCHK()                                                                            \
+    do {                                                                                       \
+        hipError_t e_ = hipGetLastError();                                                     \
+        if (e_ != hipSuccess) return fail(ctx, MC_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+static int32_t dalloc(mc_ctx *ctx, void **out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (ctx->opt.hbm_budget > 0 && ctx->device_bytes + (int64_t)bytes > ctx->opt.hbm_budget)
+        return fail(ctx, MC_EBUDGET, "device-memory budget exceeded (" + std::to_string(ctx->device_bytes + bytes) +
+                                         " > " + std::to_string(ctx->opt.hbm_budget) + " bytes)");
+    void *p = nullptr;
+    if (ctx->opt.alloc) {
+        p = ctx->opt.alloc(bytes, ctx->stream, ctx->opt.alloc_user);
+        if (!p) return fail(ctx, MC_ENOMEM, "allocator callback returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) return fail(ctx, MC_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    ctx->allocs.emplace_back(p, bytes);
+    ctx->device_bytes += (int64_t)bytes;
+    *out = p;
+    return MC_OK;
+}
+
+template <class T>
+static int32_t dalloc_t(mc_ctx *ctx, T **out, size_t n) {
+    void *p = nullptr;
+    int32_t rc = dalloc(ctx, &p, n * sizeof(T));
+    *out = static_cast<T *>(p);
+    return rc;
+}
+
+static void dfree_all(mc_ctx *ctx) {
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &a : ctx->allocs) {
+        if (ctx->opt.free) ctx->opt.free(a.first, ctx->stream, ctx->opt.alloc_user);
+        else (void)hipFree(a.first);
+    }
+    ctx->allocs.clear();
+    ctx->device_bytes = 0;
+}
+
+static hipEvent_t ev_get(mc_ctx *ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+struct Timer {
+    mc_ctx *ctx;
+    int kind;
+    hipEvent_t a = nullptr;
+    Timer(mc_ctx *c, int k) : ctx(c), kind(k) {
+        if (ctx->opt.timing) {
+            a = ev_get(ctx);
+            (void)hipEventRecord(a, ctx->stream);
+        }
+    }
+    ~Timer() {
+        if (a) {
+            hipEvent_t b = ev_get(ctx);
+            (void)hipEventRecord(b, ctx->stream);
+            ctx->ev_used.push_back(EvPair{a, b, kind});
+        }
+    }
+};
+
+static void resolve_timing(mc_ctx *ctx) {
+    for (auto &p : ctx->ev_used) {
+        float ms = 0.f;
+        (void)hipEventSynchronize(p.b);
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) ctx->t_ms[p.kind] += ms;
+        ctx->t_launch[p.kind]++;
+        ctx->ev_pool.push_back(p.a);
+        ctx->ev_pool.push_back(p.b);
+    }
+    ctx->ev_used.clear();
+}
+
+// ---------------------------------------------------------------------------
+// Device views.
+// ---------------------------------------------------------------------------
+static TallyPtrs tally_ptrs(mc_ctx *ctx) { return ctx->tp; }
+
+template <class Tab>
+static const Tab *etab_as(mc_ctx *ctx) { return static_cast<const Tab *>(ctx->etab); }
+template <class Tab>
+static const Tab *gtab_as(mc_ctx *ctx) { return static_cast<const Tab *>(ctx->gtab); }
+
+static int32_t upload_species(mc_ctx *ctx) {
+    const size_t n = ctx->sp_host.size();
+    if (n == 0) return MC_OK;
+    HIPCHK(hipMemcpyAsync(ctx->sp_dev, ctx->sp_host.data(), n * sizeof(Species), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->charge_dev, ctx->charge_host.data(), n * sizeof(int32_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+static void species_alpha(mc_ctx *ctx, size_t k) {
+    const mc_ion &in = ctx->ions[k];
+    Species &S = ctx->sp_host[k];
+    const double mg = ctx->op.gas_mass_da * kDa, ma = S.m / in.n_atoms;
+    S.alpha = in.alpha >= 0.0 ? in.alpha : 4.0 * mg * ma / ((mg + ma) * (mg + ma));
+}
+
+// ---------------------------------------------------------------------------
+// Kernels launches.
+// ---------------------------------------------------------------------------
+template <class Tab>
+static int32_t fold_table(mc_ctx *ctx) {
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    k_fold<Tab><<<grid_for(nn), kBlock, 0, ctx->stream>>>(static_cast<Tab *>(ctx->etab), ctx->e_dc, ctx->e_off,
+                                                           ctx->e_sc, ctx->e_rf, ctx->op.v_off, nn, ctx->esc[0],
+                                                           ctx->esc[1], ctx->esc[2], ctx->esc[3]);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
+static int32_t fold(mc_ctx *ctx) {
+    if (!ctx->fp32()) return fold_table<double4>(ctx);
+    if (ctx->bf16()) return fold_table<bf16x4>(ctx);
+    return fold_table<float4>(ctx);
+}
+
+template <class P, class Tab>
+static int32_t launch_emit(mc_ctx *ctx, int si, int64_t count, PackPtrs<typename P::T> p) {
+    Src &S = ctx->srcs[si];
+    EmitArgs<P, Tab> a{};
+    a.p = p;
+    a.gtab = gtab_as<Tab>(ctx);
+    std::memcpy(a.gsc, ctx->gsc, sizeof(a.gsc));
+    a.sp = ctx->sp_dev;
+    a.slot0 = ctx->n_slots;
+    a.count = count;
+    a.id0 = ((int64_t)si << 32) | S.emitted;
+    a.step = ctx->step;
+    a.sigma_r = S.in.sigma_r;
+    a.r_trunc = S.in.r_trunc;
+    a.z_inj = S.in.z_inj;
+    a.w = S.w;
+    a.q = S.q_fx;
+    a.inv_dr = ctx->inv_dr;
+    a.inv_dz = ctx->inv_dz;
+    a.nr = ctx->nr;
+    a.nz = ctx->nz;
+    a.ion = S.in.ion;
+    a.k0 = (uint32_t)ctx->opt.seed;
+    a.k1 = (uint32_t)(ctx->opt.seed >> 32);
+    Timer t(ctx, MC_K_EMIT);
+    k_emit<P, Tab><<<grid_for(count), kBlock, 0, ctx->stream>>>(a);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
+static int32_t emit(mc_ctx *ctx, int si, int64_t count) {
+    if (count <= 0) return MC_OK;
+    if (ctx->n_slots + count > ctx->cap)
+        return fail(ctx, MC_ENOMEM, "pack capacity exceeded (" + std::to_string(ctx->n_slots + count) + " > " +
+                                        std::to_string(ctx->cap) + ")");
+    int32_t rc;
+    if (!ctx->fp32()) rc = launch_emit<P64, double4>(ctx, si, count, ctx->p64);
+    else if (ctx->bf16()) rc = launch_emit<P32, bf16x4>(ctx, si, count, ctx->p32);
+    else rc = launch_emit<P32, float4>(ctx, si, count, ctx->p32);
+    if (rc) return rc;
+    Src &S = ctx->srcs[si];
+    ctx->n_slots += count;
+    S.emitted += count;
+    ctx->emitted_n += count;
+    ctx->emitted_w += count * S.w_fx;
+    return MC_OK;
+}
+
+// Eq. 5 source accumulator in integer units of 2^-32 real ions.
+static int64_t due(Src &S, int64_t step) {
+    if (step < S.in.step_start || S.in.kind == 0) return 0;
+    const int64_t left = S.in.n_total - S.emitted;
+    if (left <= 0) return 0;
+    int64_t k;
+    if (S.in.kind == 1) {
+        k = S.in.packs_per_step;
+    } else {
+        S.acc_fx += S.n_real_fx;
+        k = S.w_fx > 0 ? S.acc_fx / S.w_fx : 0;
+        S.acc_fx -= k * S.w_fx;
+    }
+    return std::min(k, left);
+}
+
+template <class P, class Tab>
+static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
+    if (ctx->n_slots == 0) return MC_OK;
+    StepArgs<P, Tab> a{};
+    a.p = p;
+    a.etab = etab_as<Tab>(ctx);
+    a.gtab = gtab_as<Tab>(ctx);
+    std::memcpy(a.esc, ctx->esc, sizeof(a.esc));
+    std::memcpy(a.gsc, ctx->gsc, sizeof(a.gsc));
+    a.hit = ctx->hit;
+    a.sp = ctx->sp_dev;
+    a.t = tally_ptrs(ctx);
+    a.n_slots = ctx->n_slots;
+    a.step = ctx->step;
+    const mc_operating &op = ctx->op;
+    a.dt = op.dt;
+    a.t0 = (double)ctx->step * op.dt;
+    const double w2 = 2.0 * kPi * op.f_rf, t0 = a.t0;
+    a.c0 = op.v_rf * std::cos(w2 * t0 + op.phase_rf);
+    a.ch = op.v_rf * std::cos(w2 * (t0 + 0.5 * op.dt) + op.phase_rf);
+    a.c1 = op.v_rf * std::cos(w2 * (t0 + op.dt) + op.phase_rf);
+    a.z_det = op.z_det;
+    a.r_det = op.r_det;
+    a.R = ctx->R;
+    a.inv_dr = ctx->inv_dr;
+    a.inv_dz = ctx->inv_dz;
+    a.mg = op.gas_mass_da * kDa;
+    a.exit_bin_dt = op.exit_bin_dt;
+    a.nr = ctx->nr;
+    a.nz = ctx->nz;
+    a.n_exit_bins = op.n_exit_bins;
+    a.collisions_on = op.collisions_on;
+    a.k0 = (uint32_t)ctx->opt.seed;
+    a.k1 = (uint32_t)(ctx->opt.seed >> 32);
+    Timer t(ctx, MC_K_STEP);
+    k_step<P, Tab><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
+static int32_t step_once(mc_ctx *ctx) {
+    if (!ctx->fp32()) return launch_step<P64, double4>(ctx, ctx->p64);
+    if (ctx->bf16()) return launch_step<P32, bf16x4>(ctx, ctx->p32);
+    return launch_step<P32, float4>(ctx, ctx->p32);
+}
+
+template <class P, class D>
+static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    const int32_t m = ctx->nz - 2, nu = ctx->nr - 1;
+    {
+        Timer t(ctx, MC_K_DEPOSIT);
+        k_zero_u64<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->qgrid, nn);
+        LAUNCHCHK();
+        if (ctx->n_slots > 0) {
+            DepositArgs<typename P::T> a{};
+            a.p = p;
+            a.q = ctx->qgrid;
+            a.n_slots = ctx->n_slots;
+            a.inv_dr = ctx->inv_dr;
+            a.inv_dz = ctx->inv_dz;
+            a.nr = ctx->nr;
+            a.nz = ctx->nz;
+            k_deposit<P><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a);
+            LAUNCHCHK();
+        }
+    }
+    {
+        Timer t(ctx, MC_K_POISSON);
+        D *bh = static_cast<D *>(ctx->bh);
+        k_dst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(ctx->qgrid, ctx->sine, bh, ctx->nr, ctx->nz,
+                                                                  ctx->dr, ctx->dz);
+        LAUNCHCHK();
+        k_thomas<D><<<grid_for(m), kBlock, 0, ctx->stream>>>(bh, ctx->tcp, ctx->tinv, ctx->nr, ctx->nz, ctx->dr);
+        LAUNCHCHK();
+        k_idst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(bh, ctx->sine, ctx->phi_sc, ctx->nr, ctx->nz);
+        LAUNCHCHK();
+    }
+    {
+        Timer t(ctx, MC_K_FIELD);
+        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->phi_sc, ctx->e_sc, ctx->nr, ctx->nz, ctx->dr, ctx->dz);
+        LAUNCHCHK();
+        int32_t rc = fold(ctx);
+        if (rc) return rc;
+    }
+    return MC_OK;
+}
+
+static int32_t pic_update(mc_ctx *ctx) {
+    if (!ctx->fp32()) return pic_update_t<P64, double>(ctx, ctx->p64);
+    return pic_update_t<P32, float>(ctx, ctx->p32);
+}
+
+template <class T>
+static int32_t snapshot_t(mc_ctx *ctx, PackPtrs<T> p) {
+    const int64_t ns = 2 + MC_HIST_KE + MC_HIST_TEFF;
+    Timer t(ctx, MC_K_TALLY);
+    k_zero_u64<<<grid_for(ns), kBlock, 0, ctx->stream>>>(ctx->snap, ns);
+    LAUNCHCHK();
+    const int64_t nb = std::max<int64_t>(1, (ctx->n_slots + kBlock - 1) / kBlock);
+    if (ctx->n_slots > 0) {
+        k_snapshot<T><<<(unsigned)nb, kBlock, 0, ctx->stream>>>(p, ctx->sp_dev, ctx->n_slots, ctx->snap,
+                                                               ctx->snap + 2, ctx->snap + 2 + MC_HIST_KE, ctx->partial);
+        LAUNCHCHK();
+        k_reduce_partials<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, nb, ctx->sums);
+        LAUNCHCHK();
+    } else {
+        HIPCHK(hipMemsetAsync(ctx->sums, 0, 4 * sizeof(double), ctx->stream));
+    }
+    return MC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ABI.
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t mc_abi_version(void) { return MC_ABI_VERSION; }
+
+const char *mc_last_error(const mc_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t mc_create(const mc_options *o, mc_ctx **out) {
+    if (!o || !out) return MC_EINVAL;
+    *out = nullptr;
+    if (o->pack_capacity <= 0 || (o->precision != MC_PREC_FP64 && o->precision != MC_PREC_FP32) ||
+        (!o->alloc) != (!o->free))
+        return MC_EINVAL;
+    mc_ctx *ctx = new (std::nothrow) mc_ctx();
+    if (!ctx) return MC_ENOMEM;
+    ctx->opt = *o;
+    hipError_t e = hipSetDevice(o->device);
+    if (e != hipSuccess) {
+        delete ctx;
+        return MC_EDEVICE;
+    }
+    if (o->stream) {
+        ctx->stream = static_cast<hipStream_t>(o->stream);
+    } else {
+        e = hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete ctx;
+            return MC_EDEVICE;
+        }
+        ctx->own_stream = true;
+    }
+    ctx->cap = o->pack_capacity;
+    const int64_t cap = ctx->cap;
+    int32_t rc = MC_OK;
+    if (ctx->fp32()) {
+        PackPtrs<float> &p = ctx->p32;
+        float **fl[] = {&p.x, &p.y, &p.z, &p.xl, &p.yl, &p.zl, &p.vx, &p.vy, &p.vz, &p.e, &p.el, &p.h};
+        for (auto f : fl)
+            if (!rc) rc = dalloc_t(ctx, f, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.w, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.id, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.q, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.tag, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.status, cap);
+    } else {
+        PackPtrs<double> &p = ctx->p64;
+        double **fl[] = {&p.x, &p.y, &p.z, &p.vx, &p.vy, &p.vz, &p.e, &p.h, &p.w};
+        for (auto f : fl)
+            if (!rc) rc = dalloc_t(ctx, f, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.id, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.q, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.tag, cap);
+        if (!rc) rc = dalloc_t(ctx, &p.status, cap);
+    }
+    const int64_t ecap = o->exit_capacity > 0 ? o->exit_capacity : cap;
+    ctx->tp.exit_cap = ecap;
+    if (!rc) rc = dalloc_t(ctx, &ctx->tp.exits, ecap);
+    if (!rc) rc = dalloc_t(ctx, &ctx->sp_dev, 64);
+    if (!rc) rc = dalloc_t(ctx, &ctx->charge_dev, 64);
+    ctx->partial_len = (cap + kBlock - 1) / kBlock;
+    if (!rc) rc = dalloc_t(ctx, &ctx->partial, 3 * ctx->partial_len);
+    if (!rc) rc = dalloc_t(ctx, &ctx->sums, 4);
+    if (!rc) rc = dalloc_t(ctx, &ctx->snap, 2 + MC_HIST_KE + MC_HIST_TEFF);
+    if (rc) {
+        std::string msg = ctx->err;
+        mc_destroy(ctx);
+        std::fprintf(stderr, "mc_create: %s\n", msg.c_str());
+        return rc;
+    }
+    *out = ctx;
+    return MC_OK;
+}
+
+void mc_destroy(mc_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->opt.device);
+    dfree_all(ctx);
+    for (auto &p : ctx->ev_used) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+static double absmax(const double *a, int64_t n) {
+    double m = 0.0;
+    if (!a) return 0.0;
+    for (int64_t k = 0; k < n; ++k) m = std::max(m, std::fabs(a[k]));
+    return m;
+}
+
+static float scale_of(double m) { return m > 0.0 ? (float)m : 1.0f; }
+
+int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) {
+    if (!ctx) return MC_EINVAL;
+    if (!g || !t || !t->phi_dc || !t->gas_p || !t->gas_t) return fail(ctx, MC_EINVAL, "missing grid or tables");
+    if (g->nr < 3 || g->nz < 3 || !(g->dr > 0) || !(g->dz > 0)) return fail(ctx, MC_EINVAL, "bad grid");
+    if (ctx->has_fields) return fail(ctx, MC_ESTATE, "fields already loaded");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    ctx->nr = g->nr;
+    ctx->nz = g->nz;
+    ctx->dr = g->dr;
+    ctx->dz = g->dz;
+    ctx->inv_dr = 1.0 / g->dr;
+    ctx->inv_dz = 1.0 / g->dz;
+    ctx->R = (g->nr - 1) * g->dr;
+    const int64_t nn = (int64_t)g->nr * g->nz;
+    const int32_t m = g->nz - 2, nu = g->nr - 1;
+    int32_t rc = MC_OK;
+    double *tmp = nullptr;
+    if (!rc) rc = dalloc_t(ctx, &ctx->e_dc, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->e_off, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->e_rf, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->e_sc, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->phi_sc, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->mask, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->hit, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->qgrid, nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->sine, 2 * (int64_t)(g->nz - 1));
+    if (!rc) rc = dalloc_t(ctx, &ctx->tcp, (int64_t)nu * m);
+    if (!rc) rc = dalloc_t(ctx, &ctx->tinv, (int64_t)nu * m);
+    if (!rc) rc = dalloc(ctx, &ctx->bh, (size_t)nu * m * (ctx->fp32() ? sizeof(float) : sizeof(double)));
+    const size_t node_bytes = !ctx->fp32() ? sizeof(double4) : (ctx->bf16() ? sizeof(bf16x4) : sizeof(float4));
+    if (!rc) rc = dalloc(ctx, &ctx->etab, nn * node_bytes);
+    if (!rc) rc = dalloc(ctx, &ctx->gtab, nn * node_bytes);
+    // tallies: counters, exit bins (allocated at set_operating), loss map, histograms
+    if (!rc) rc = dalloc_t(ctx, &tmp, 4 * nn);  // staging for the raw tables, released below
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(ctx->e_sc, 0, nn * sizeof(double2), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->phi_sc, 0, nn * sizeof(double), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->e_off, 0, nn * sizeof(double2), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->e_rf, 0, nn * sizeof(double2), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->qgrid, 0, nn * sizeof(unsigned long long), ctx->stream));
+    // bake E = -grad(phi) for the three potentials
+    const double *phis[3] = {t->phi_dc, t->phi_off, t->phi_rf};
+    double2 *outs[3] = {ctx->e_dc, ctx->e_off, ctx->e_rf};
+    for (int k = 0; k < 3; ++k) {
+        if (!phis[k]) continue;
+        HIPCHK(hipMemcpyAsync(tmp, phis[k], nn * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(tmp, outs[k], g->nr, g->nz, g->dr, g->dz);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    // gas table (u_r, u_z, p, T)
+    const double *gas[4] = {t->gas_ur, t->gas_uz, t->gas_p, t->gas_t};
+    for (int k = 0; k < 4; ++k) {
+        if (gas[k]) HIPCHK(hipMemcpyAsync(tmp + k * nn, gas[k], nn * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+        else HIPCHK(hipMemsetAsync(tmp + k * nn, 0, nn * sizeof(double), ctx->stream));
+        ctx->gsc[k] = scale_of(absmax(gas[k], nn));
+    }
+    if (!ctx->fp32())
+        k_gas<double4><<<grid_for(nn), kBlock, 0, ctx->stream>>>(static_cast<double4 *>(ctx->gtab), tmp, tmp + nn,
+                                                                  tmp + 2 * nn, tmp + 3 * nn, nn, 1, 1, 1, 1);
+    else if (ctx->bf16())
+        k_gas<bf16x4><<<grid_for(nn), kBlock, 0, ctx->stream>>>(static_cast<bf16x4 *>(ctx->gtab), tmp, tmp + nn,
+                                                                 tmp + 2 * nn, tmp + 3 * nn, nn, ctx->gsc[0],
+                                                                 ctx->gsc[1], ctx->gsc[2], ctx->gsc[3]);
+    else
+        k_gas<float4><<<grid_for(nn), kBlock, 0, ctx->stream>>>(static_cast<float4 *>(ctx->gtab), tmp, tmp + nn,
+                                                                 tmp + 2 * nn, tmp + 3 * nn, nn, 1, 1, 1, 1);
+    LAUNCHCHK();
+    if (!ctx->bf16()) std::fill(ctx->gsc, ctx->gsc + 4, 1.0f);
+    if (t->mask) HIPCHK(hipMemcpyAsync(ctx->mask, t->mask, nn, hipMemcpyHostToDevice, ctx->stream));
+    else HIPCHK(hipMemsetAsync(ctx->mask, 0, nn, ctx->stream));
+    k_sine_table<<<grid_for(2 * (g->nz - 1)), kBlock, 0, ctx->stream>>>(ctx->sine, g->nz);
+    LAUNCHCHK();
+    k_thomas_coef<<<grid_for(m), kBlock, 0, ctx->stream>>>(ctx->tcp, ctx->tinv, g->nr, g->nz, g->dr, g->dz);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    // the staging buffer is returned at once
+    for (size_t k = 0; k < ctx->allocs.size(); ++k)
+        if (ctx->allocs[k].first == tmp) {
+            if (ctx->opt.free) ctx->opt.free(tmp, ctx->stream, ctx->opt.alloc_user);
+            else HIPCHK(hipFree(tmp));
+            ctx->device_bytes -= (int64_t)ctx->allocs[k].second;
+            ctx->allocs.erase(ctx->allocs.begin() + k);
+            break;
+        }
+    // E-table scales for the BF16 form: the largest magnitude of each static channel
+    if (ctx->bf16()) {
+        std::vector<double2> h(nn);
+        double mx[4] = {0, 0, 0, 0};
+        HIPCHK(hipMemcpy(h.data(), ctx->e_dc, nn * sizeof(double2), hipMemcpyDeviceToHost));
+        for (auto &v : h) { mx[0] = std::max(mx[0], std::fabs(v.x)); mx[1] = std::max(mx[1], std::fabs(v.y)); }
+        HIPCHK(hipMemcpy(h.data(), ctx->e_rf, nn * sizeof(double2), hipMemcpyDeviceToHost));
+        for (auto &v : h) { mx[2] = std::max(mx[2], std::fabs(v.x)); mx[3] = std::max(mx[3], std::fabs(v.y)); }
+        for (int k = 0; k < 4; ++k) ctx->esc[k] = scale_of(mx[k]);
+    }
+    ctx->has_fields = true;
+    return MC_OK;
+}
+
+static Species make_species(const mc_ion *in) {
+    Species S{};
+    S.m = in->mass_da * kDa;
+    S.qm = in->charge_z * kQe / S.m;
+    S.ccs = in->ccs_m2;
+    S.theta = in->theta_e;
+    S.skt = (3.0 * in->n_atoms - 6.0) * kB * in->theta_e;
+    S.e0 = in->t_eff0 > 0.0 ? S.skt / std::expm1(in->theta_e / in->t_eff0) : 0.0;
+    S.n_atoms = in->n_atoms;
+    S.act_kind = in->act_kind;
+    const double R = kNA * kB;
+    if (in->act_kind == 1) {
+        S.act_a = kB / kH * std::exp(in->act_p2 / R);
+        S.act_b = in->act_p1 / R;
+    } else if (in->act_kind == 2) {
+        S.act_a = in->act_p1;
+        S.act_b = in->act_p2 * kQe / kB;
+    }
+    S.alpha = in->alpha;
+    return S;
+}
+
+int32_t mc_define_ion(mc_ctx *ctx, const mc_ion *ion, int32_t *ion_id) {
+    if (!ctx) return MC_EINVAL;
+    if (!ion || ion->n_atoms < 3 || !(ion->mass_da > 0) || ion->charge_z == 0 || !(ion->ccs_m2 >= 0) ||
+        !(ion->theta_e > 0) || ion->act_kind < 0 || ion->act_kind > 2)
+        return fail(ctx, MC_EINVAL, "invalid ion template");
+    if (ctx->ions.size() >= 64) return fail(ctx, MC_ENOMEM, "at most 64 ion templates");
+    ctx->ions.push_back(*ion);
+    ctx->sp_host.push_back(make_species(ion));
+    ctx->charge_host.push_back(ion->charge_z);
+    if (ctx->has_op) species_alpha(ctx, ctx->ions.size() - 1);
+    if (ion_id) *ion_id = (int32_t)ctx->ions.size() - 1;
+    return upload_species(ctx);
+}
+
+int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
+    if (!ctx) return MC_EINVAL;
+    if (!op || !(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1 || !(op->exit_bin_dt > 0) ||
+        !(op->gas_mass_da > 0) || !(op->r_det > 0) || !(op->d_hit >= 0))
+        return fail(ctx, MC_EINVAL, "invalid operating point");
+    if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "load fields first");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    const bool first = !ctx->has_op;
+    if (!first && op->n_exit_bins != ctx->op.n_exit_bins)
+        return fail(ctx, MC_ESTATE, "the number of exit bins is fixed by the first operating point");
+    ctx->op = *op;
+    ctx->has_op = true;
+    for (size_t k = 0; k < ctx->ions.size(); ++k) species_alpha(ctx, k);
+    int32_t rc = upload_species(ctx);
+    if (rc) return rc;
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    if (first) {
+        ctx->tal_len = TC_N + op->n_exit_bins + nn + MC_HIST_KE + MC_HIST_TEFF + MC_HIST_R;
+        rc = dalloc_t(ctx, &ctx->tal, ctx->tal_len);
+        if (rc) return rc;
+        HIPCHK(hipMemsetAsync(ctx->tal, 0, ctx->tal_len * sizeof(unsigned long long), ctx->stream));
+        unsigned long long *p = ctx->tal;
+        ctx->tp.cnt = p;
+        p += TC_N;
+        ctx->tp.exit_bins = p;
+        p += op->n_exit_bins;
+        ctx->tp.loss_map = p;
+        p += nn;
+        ctx->tp.hist_ke = p;
+        p += MC_HIST_KE;
+        ctx->tp.hist_teff = p;
+        p += MC_HIST_TEFF;
+        ctx->tp.hist_r = p;
+    }
+    const double reach = op->d_hit + 0.5 * std::min(ctx->dr, ctx->dz);
+    const int32_t wi = (int32_t)std::ceil(reach / ctx->dr), wj = (int32_t)std::ceil(reach / ctx->dz);
+    k_hit<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->mask, ctx->hit, ctx->nr, ctx->nz, ctx->dr, ctx->dz, reach, wi,
+                                                    wj);
+    LAUNCHCHK();
+    rc = fold(ctx);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+int32_t mc_define_source(mc_ctx *ctx, const mc_source *src, int32_t *src_id) {
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->has_op) return fail(ctx, MC_ESTATE, "set the operating point first");
+    if (!src || src->ion < 0 || src->ion >= (int32_t)ctx->ions.size() || src->kind < 0 || src->kind > 2 ||
+        !(src->sigma_r > 0) || !(src->r_trunc > 0) || src->n_total < 0 ||
+        (src->kind == 1 && src->packs_per_step <= 0) || (src->kind != 1 && !(src->weight > 0)))
+        return fail(ctx, MC_EINVAL, "invalid source");
+    if (ctx->srcs.size() >= 1024) return fail(ctx, MC_ENOMEM, "too many sources");
+    Src S{};
+    S.in = *src;
+    const double z = (double)ctx->ions[src->ion].charge_z;
+    const double n_real = src->current_a * ctx->op.dt / (z * kQe);
+    S.w = src->kind == 1 ? n_real / (double)src->packs_per_step : src->weight;
+    S.w_fx = fx32_host(S.w);
+    S.q_fx = fx32_host(z * S.w);
+    S.n_real_fx = fx32_host(n_real);
+    ctx->srcs.push_back(S);
+    if (src_id) *src_id = (int32_t)ctx->srcs.size() - 1;
+    return MC_OK;
+}
+
+int32_t mc_inject(mc_ctx *ctx, int32_t src_id, int64_t n) {
+    if (!ctx) return MC_EINVAL;
+    if (src_id < 0 || src_id >= (int32_t)ctx->srcs.size() || n < 0) return fail(ctx, MC_EINVAL, "invalid inject");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    return emit(ctx, src_id, n);
+}
+
+int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
+    if (n_steps < 0) return fail(ctx, MC_EINVAL, "negative step count");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    for (int64_t it = 0; it < n_steps; ++it) {
+        int32_t rc;
+        if (ctx->op.sc_on && ctx->step % ctx->op.sc_every == 0) {
+            rc = pic_update(ctx);
+            if (rc) return rc;
+        }
+        for (size_t si = 0; si < ctx->srcs.size(); ++si) {
+            rc = emit(ctx, (int)si, due(ctx->srcs[si], ctx->step));
+            if (rc) return rc;
+        }
+        rc = step_once(ctx);
+        if (rc) return rc;
+        ctx->step++;
+    }
+    return MC_OK;
+}
+
+int32_t mc_pic_update(mc_ctx *ctx) {
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    return pic_update(ctx);
+}
+
+int32_t mc_synchronize(mc_ctx *ctx) {
+    if (!ctx) return MC_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+int32_t mc_get_info(const mc_ctx *ctx, mc_info *info) {
+    if (!ctx || !info) return MC_EINVAL;
+    info->step = ctx->step;
+    info->n_slots = ctx->n_slots;
+    info->capacity = ctx->cap;
+    info->exit_capacity = ctx->tp.exit_cap;
+    info->device_bytes = ctx->device_bytes;
+    info->nr = ctx->nr;
+    info->nz = ctx->nz;
+    info->n_exit_bins = ctx->has_op ? ctx->op.n_exit_bins : 0;
+    info->precision = ctx->opt.precision;
+    info->n_ions = (int32_t)ctx->ions.size();
+    info->n_sources = (int32_t)ctx->srcs.size();
+    return MC_OK;
+}
+
+int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out) {
+    if (!ctx || !out) return MC_EINVAL;
+    if (!ctx->has_op) return fail(ctx, MC_ESTATE, "no operating point");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    int32_t rc = ctx->fp32() ? snapshot_t<float>(ctx, ctx->p32) : snapshot_t<double>(ctx, ctx->p64);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::vector<unsigned long long> cnt(TC_N), snap(2 + MC_HIST_KE + MC_HIST_TEFF);
+    double sums[3];
+    HIPCHK(hipMemcpy(cnt.data(), ctx->tp.cnt, TC_N * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(snap.data(), ctx->snap, snap.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sums, ctx->sums, 3 * sizeof(double), hipMemcpyDeviceToHost));
+    out->emitted_n = ctx->emitted_n;
+    out->emitted_w = ctx->emitted_w;
+    for (int c = 0; c < MC_NCLASS; ++c) {
+        out->class_n[c] = (int64_t)cnt[TC_CLASS_N + c];
+        out->class_w[c] = (int64_t)cnt[TC_CLASS_W + c];
+    }
+    out->class_n[MC_ACTIVE] = (int64_t)snap[0];
+    out->class_w[MC_ACTIVE] = (int64_t)snap[1];
+    out->n_cand = (int64_t)cnt[TC_CAND];
+    out->n_coll = (int64_t)cnt[TC_COLL];
+    out->n_cap = (int64_t)cnt[TC_CAP];
+    out->n_clamp = (int64_t)cnt[TC_CLAMP];
+    out->pack_steps = (int64_t)cnt[TC_PACKSTEPS];
+    out->exit_overflow = (int64_t)cnt[TC_EXOVER];
+    out->exit_dropped = (int64_t)cnt[TC_EXDROP];
+    out->sum_w_ke_active = sums[0];
+    out->sum_w_eint_active = sums[1];
+    out->sum_w_dissoc_terminal = sums[2];
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    if (out->exit_bins)
+        HIPCHK(hipMemcpy(out->exit_bins, ctx->tp.exit_bins, ctx->op.n_exit_bins * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (out->loss_map) HIPCHK(hipMemcpy(out->loss_map, ctx->tp.loss_map, nn * sizeof(int64_t), hipMemcpyDeviceToHost));
+    if (out->hist_ke) HIPCHK(hipMemcpy(out->hist_ke, ctx->tp.hist_ke, MC_HIST_KE * 8, hipMemcpyDeviceToHost));
+    if (out->hist_teff) HIPCHK(hipMemcpy(out->hist_teff, ctx->tp.hist_teff, MC_HIST_TEFF * 8, hipMemcpyDeviceToHost));
+    if (out->hist_r) HIPCHK(hipMemcpy(out->hist_r, ctx->tp.hist_r, MC_HIST_R * 8, hipMemcpyDeviceToHost));
+    if (out->act_hist_ke) std::memcpy(out->act_hist_ke, snap.data() + 2, MC_HIST_KE * 8);
+    if (out->act_hist_teff) std::memcpy(out->act_hist_teff, snap.data() + 2 + MC_HIST_KE, MC_HIST_TEFF * 8);
+    return MC_OK;
+}
+
+int32_t mc_read_exits(mc_ctx *ctx, mc_exit_rec *buf, int64_t cap, int64_t *n) {
+    if (!ctx || !n || cap < 0) return MC_EINVAL;
+    if (!ctx->has_op) return fail(ctx, MC_ESTATE, "no operating point");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    unsigned long long count = 0;
+    HIPCHK(hipMemcpy(&count, ctx->tp.cnt + TC_EXCOUNT, sizeof(count), hipMemcpyDeviceToHost));
+    *n = (int64_t)count;
+    if (!buf || cap == 0) return MC_OK;
+    const int64_t have = std::min<int64_t>((int64_t)count, ctx->tp.exit_cap);
+    std::vector<mc_exit_rec> all(have);
+    if (have > 0) HIPCHK(hipMemcpy(all.data(), ctx->tp.exits, have * sizeof(mc_exit_rec), hipMemcpyDeviceToHost));
+    std::sort(all.begin(), all.end(), [](const mc_exit_rec &a, const mc_exit_rec &b) { return a.id < b.id; });
+    std::memcpy(buf, all.data(), std::min(have, cap) * sizeof(mc_exit_rec));
+    return MC_OK;
+}
+
+int32_t mc_read_packs(mc_ctx *ctx, mc_packs *o) {
+    if (!ctx || !o) return MC_EINVAL;
+    if (o->n < ctx->n_slots) return fail(ctx, MC_EINVAL, "buffer shorter than the slot count");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int64_t n = ctx->n_slots;
+    o->n = n;
+    if (n == 0) return MC_OK;
+    auto cp = [&](void *dst, const void *src, size_t b) -> hipError_t {
+        return dst ? hipMemcpy(dst, src, b, hipMemcpyDeviceToHost) : hipSuccess;
+    };
+    if (!ctx->fp32()) {
+        const PackPtrs<double> &p = ctx->p64;
+        double *dsts[] = {o->x, o->y, o->z, o->vx, o->vy, o->vz, o->e_int, o->h, o->w};
+        double *srcs[] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.e, p.h, p.w};
+        for (int k = 0; k < 9; ++k) HIPCHK(cp(dsts[k], srcs[k], n * sizeof(double)));
+        HIPCHK(cp(o->id, p.id, n * 8));
+        HIPCHK(cp(o->q, p.q, n * 8));
+        HIPCHK(cp(o->tag, p.tag, n * 4));
+        HIPCHK(cp(o->status, p.status, n * 4));
+    } else {
+        const PackPtrs<float> &p = ctx->p32;
+        std::vector<float> hi(n), lo(n);
+        double *dsts[] = {o->x, o->y, o->z, o->e_int};
+        float *shi[] = {p.x, p.y, p.z, p.e}, *slo[] = {p.xl, p.yl, p.zl, p.el};
+        for (int k = 0; k < 4; ++k) {
+            if (!dsts[k]) continue;
+            HIPCHK(hipMemcpy(hi.data(), shi[k], n * 4, hipMemcpyDeviceToHost));
+            HIPCHK(hipMemcpy(lo.data(), slo[k], n * 4, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) dsts[k][i] = (double)hi[i] + (double)lo[i];
+        }
+        double *d1[] = {o->vx, o->vy, o->vz, o->h};
+        float *s1[] = {p.vx, p.vy, p.vz, p.h};
+        for (int k = 0; k < 4; ++k) {
+            if (!d1[k]) continue;
+            HIPCHK(hipMemcpy(hi.data(), s1[k], n * 4, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < n; ++i) d1[k][i] = (double)hi[i];
+        }
+        HIPCHK(cp(o->w, p.w, n * 8));
+        HIPCHK(cp(o->id, p.id, n * 8));
+        HIPCHK(cp(o->q, p.q, n * 8));
+        HIPCHK(cp(o->tag, p.tag, n * 4));
+        HIPCHK(cp(o->status, p.status, n * 4));
+    }
+    return MC_OK;
+}
+
+int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in) {
+    if (!ctx || !in) return MC_EINVAL;
+    if (in->n < 0 || in->n > ctx->cap) return fail(ctx, MC_ENOMEM, "snapshot larger than the pack capacity");
+    if (!in->x || !in->y || !in->z || !in->vx || !in->vy || !in->vz || !in->e_int || !in->h || !in->w || !in->id ||
+        !in->tag)
+        return fail(ctx, MC_EINVAL, "snapshot field missing");
+    for (int64_t k = 0; k < in->n; ++k) {
+        if (in->tag[k] < 0 || in->tag[k] >= (int32_t)ctx->ions.size()) return fail(ctx, MC_EINVAL, "bad ion tag");
+        if (!std::isfinite(in->x[k]) || !std::isfinite(in->y[k]) || !std::isfinite(in->z[k]) ||
+            !std::isfinite(in->vx[k]) || !std::isfinite(in->vy[k]) || !std::isfinite(in->vz[k]) ||
+            !std::isfinite(in->e_int[k]) || !std::isfinite(in->w[k]) || !std::isfinite(in->h[k]))
+            return fail(ctx, MC_EINVAL, "non-finite snapshot state");
+    }
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int64_t n = in->n;
+    if (n > 0) {
+        if (!ctx->fp32()) {
+            const PackPtrs<double> &p = ctx->p64;
+            const double *s[] = {in->x, in->y, in->z, in->vx, in->vy, in->vz, in->e_int, in->h, in->w};
+            double *d[] = {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.e, p.h, p.w};
+            for (int k = 0; k < 9; ++k) HIPCHK(hipMemcpy(d[k], s[k], n * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(p.id, in->id, n * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(p.tag, in->tag, n * 4, hipMemcpyHostToDevice));
+            k_init_written<double><<<grid_for(n), kBlock, 0, ctx->stream>>>(p, ctx->sp_dev, ctx->charge_dev, n);
+        } else {
+            const PackPtrs<float> &p = ctx->p32;
+            std::vector<float> hi(n), lo(n);
+            const double *s2[] = {in->x, in->y, in->z, in->e_int};
+            float *dh[] = {p.x, p.y, p.z, p.e}, *dl[] = {p.xl, p.yl, p.zl, p.el};
+            for (int k = 0; k < 4; ++k) {
+                for (int64_t i = 0; i < n; ++i) {
+                    hi[i] = (float)s2[k][i];
+                    lo[i] = (float)(s2[k][i] - (double)hi[i]);
+                }
+                HIPCHK(hipMemcpy(dh[k], hi.data(), n * 4, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(dl[k], lo.data(), n * 4, hipMemcpyHostToDevice));
+            }
+            const double *s1[] = {in->vx, in->vy, in->vz, in->h};
+            float *d1[] = {p.vx, p.vy, p.vz, p.h};
+            for (int k = 0; k < 4; ++k) {
+                for (int64_t i = 0; i < n; ++i) hi[i] = (float)s1[k][i];
+                HIPCHK(hipMemcpy(d1[k], hi.data(), n * 4, hipMemcpyHostToDevice));
+            }
+            HIPCHK(hipMemcpy(p.w, in->w, n * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(p.id, in->id, n * 8, hipMemcpyHostToDevice));
+            HIPCHK(hipMemcpy(p.tag, in->tag, n * 4, hipMemcpyHostToDevice));
+            k_init_written<float><<<grid_for(n), kBlock, 0, ctx->stream>>>(p, ctx->sp_dev, ctx->charge_dev, n);
+        }
+        LAUNCHCHK();
+    }
+    ctx->n_slots = n;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+int32_t mc_read_charge(mc_ctx *ctx, int64_t *q) {
+    if (!ctx || !q) return MC_EINVAL;
+    if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "no fields");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(q, ctx->qgrid, (int64_t)ctx->nr * ctx->nz * 8, hipMemcpyDeviceToHost));
+    return MC_OK;
+}
+
+int32_t mc_read_sc(mc_ctx *ctx, double *phi, double *er, double *ez) {
+    if (!ctx) return MC_EINVAL;
+    if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "no fields");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    if (phi) HIPCHK(hipMemcpy(phi, ctx->phi_sc, nn * 8, hipMemcpyDeviceToHost));
+    if (er || ez) {
+        std::vector<double2> e(nn);
+        HIPCHK(hipMemcpy(e.data(), ctx->e_sc, nn * sizeof(double2), hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < nn; ++k) {
+            if (er) er[k] = e[k].x;
+            if (ez) ez[k] = e[k].y;
+        }
+    }
+    return MC_OK;
+}
+
+int32_t mc_read_hit(mc_ctx *ctx, uint8_t *hit) {
+    if (!ctx || !hit) return MC_EINVAL;
+    if (!ctx->has_op) return fail(ctx, MC_ESTATE, "no operating point");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpy(hit, ctx->hit, (int64_t)ctx->nr * ctx->nz, hipMemcpyDeviceToHost));
+    return MC_OK;
+}
+
+int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out) {
+    if (!ctx || !out) return MC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    resolve_timing(ctx);
+    for (int k = 0; k < MC_NKERNEL; ++k) {
+        out->ms[k] = ctx->t_ms[k];
+        out->launches[k] = ctx->t_launch[k];
+    }
+    unsigned long long ps = 0;
+    if (ctx->tp.cnt) HIPCHK(hipMemcpy(&ps, ctx->tp.cnt + TC_PACKSTEPS, 8, hipMemcpyDeviceToHost));
+    out->pack_steps = (int64_t)ps;
+    return MC_OK;
+}
+
+int32_t mc_reset_timing(mc_ctx *ctx) {
+    if (!ctx) return MC_EINVAL;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    resolve_timing(ctx);
+    for (int k = 0; k < MC_NKERNEL; ++k) {
+        ctx->t_ms[k] = 0;
+        ctx->t_launch[k] = 0;
+    }
+    return MC_OK;
+}
+
+}  // extern "C"

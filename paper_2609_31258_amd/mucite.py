@@ -1,0 +1,370 @@
+"""ctypes binding of the HIP ion-pack library (include/mucite.h).
+
+Argument marshalling only: every step of the path runs in the library's
+kernels.  PyTorch is used for device memory (the library's allocator
+callbacks draw from torch's caching allocator) and for the stream the
+library enqueues on.  The library must have been built
+(``python -m paper_2609_31258_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmucite.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mucite.h")
+
+I32, I64, U64, F64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+PD, PI64, PI32, PU8 = C.POINTER(F64), C.POINTER(I64), C.POINTER(I32), C.POINTER(C.c_uint8)
+
+MC_OK, MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE, MC_ENUMERIC, MC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+PREC_FP64, PREC_FP32 = 0, 1
+NCLASS = 6
+HIST_KE, HIST_TEFF, HIST_R = 202, 202, 102
+K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY = range(6)
+KERNEL_NAMES = ("emit", "step", "deposit", "poisson", "field", "tally")
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", I32), ("device", I32), ("seed", U64), ("pack_capacity", I64), ("exit_capacity", I64),
+                ("hbm_budget", I64), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p), ("timing", I32), ("fp32_tables", I32)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("nr", I32), ("nz", I32), ("dr", F64), ("dz", F64)]
+
+
+class FieldTables(C.Structure):
+    _fields_ = [(f, PD) for f in ("phi_dc", "phi_off", "phi_rf", "gas_ur", "gas_uz", "gas_p", "gas_t")] + \
+               [("mask", PU8)]
+
+
+class Ion(C.Structure):
+    _fields_ = [("mass_da", F64), ("charge_z", I32), ("ccs_m2", F64), ("n_atoms", I32), ("theta_e", F64),
+                ("alpha", F64), ("t_eff0", F64), ("act_kind", I32), ("act_p1", F64), ("act_p2", F64)]
+
+
+class Source(C.Structure):
+    _fields_ = [("kind", I32), ("ion", I32), ("current_a", F64), ("weight", F64), ("packs_per_step", I64),
+                ("n_total", I64), ("sigma_r", F64), ("r_trunc", F64), ("z_inj", F64), ("step_start", I64)]
+
+
+class Operating(C.Structure):
+    _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
+                ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
+                ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32)]
+
+
+class Packs(C.Structure):
+    _fields_ = [("n", I64)] + [(f, PD) for f in ("x", "y", "z", "vx", "vy", "vz", "e_int", "h", "w")] + \
+               [("id", PI64), ("q", PI64), ("tag", PI32), ("status", PI32)]
+
+
+class Tallies(C.Structure):
+    _fields_ = [("emitted_n", I64), ("emitted_w", I64), ("class_n", I64 * NCLASS), ("class_w", I64 * NCLASS),
+                ("n_cand", I64), ("n_coll", I64), ("n_cap", I64), ("n_clamp", I64), ("pack_steps", I64),
+                ("exit_overflow", I64), ("exit_dropped", I64),
+                ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
+                ("exit_bins", PI64), ("loss_map", PI64), ("hist_ke", PI64), ("hist_teff", PI64), ("hist_r", PI64),
+                ("act_hist_ke", PI64), ("act_hist_teff", PI64)]
+
+
+class ExitRec(C.Structure):
+    _fields_ = [("id", I64), ("step", I64), ("cls", I32), ("inode", I32), ("jnode", I32), ("tag", I32)] + \
+               [(f, F64) for f in ("x", "y", "z", "vx", "vy", "vz", "t_cross", "r_cross", "ke_ev", "t_eff",
+                                   "h", "w")]
+
+
+class Info(C.Structure):
+    _fields_ = [("step", I64), ("n_slots", I64), ("capacity", I64), ("exit_capacity", I64), ("device_bytes", I64),
+                ("nr", I32), ("nz", I32), ("n_exit_bins", I32), ("precision", I32), ("n_ions", I32),
+                ("n_sources", I32)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", F64 * 6), ("launches", I64 * 6), ("pack_steps", I64)]
+
+
+EXIT_DTYPE = np.dtype([(f, np.int64 if t is I64 else (np.int32 if t is I32 else np.float64))
+                       for f, t in ExitRec._fields_])
+assert EXIT_DTYPE.itemsize == C.sizeof(ExitRec)
+
+_SIGS = {
+    "mc_abi_version": (I32, []),
+    "mc_create": (I32, [C.POINTER(Options), C.POINTER(C.c_void_p)]),
+    "mc_destroy": (None, [C.c_void_p]),
+    "mc_last_error": (C.c_char_p, [C.c_void_p]),
+    "mc_load_fields": (I32, [C.c_void_p, C.POINTER(Grid), C.POINTER(FieldTables)]),
+    "mc_define_ion": (I32, [C.c_void_p, C.POINTER(Ion), PI32]),
+    "mc_set_operating": (I32, [C.c_void_p, C.POINTER(Operating)]),
+    "mc_define_source": (I32, [C.c_void_p, C.POINTER(Source), PI32]),
+    "mc_inject": (I32, [C.c_void_p, I32, I64]),
+    "mc_step": (I32, [C.c_void_p, I64]),
+    "mc_pic_update": (I32, [C.c_void_p]),
+    "mc_synchronize": (I32, [C.c_void_p]),
+    "mc_get_info": (I32, [C.c_void_p, C.POINTER(Info)]),
+    "mc_read_tallies": (I32, [C.c_void_p, C.POINTER(Tallies)]),
+    "mc_read_exits": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
+    "mc_read_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
+    "mc_write_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
+    "mc_read_charge": (I32, [C.c_void_p, PI64]),
+    "mc_read_sc": (I32, [C.c_void_p, PD, PD, PD]),
+    "mc_read_hit": (I32, [C.c_void_p, PU8]),
+    "mc_read_timing": (I32, [C.c_void_p, C.POINTER(Timing)]),
+    "mc_reset_timing": (I32, [C.c_void_p]),
+}
+
+_LIB = None
+
+
+def load_library():
+    """Load libmucite.so; raise if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library {LIB_PATH} is not built; run `python -m paper_2609_31258_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    if L.mc_abi_version() != 1:
+        raise RuntimeError("ABI version mismatch")
+    _LIB = L
+    return L
+
+
+class MucateError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _struct(cls, obj):
+    s = cls()
+    for name, _ in cls._fields_:
+        setattr(s, name, getattr(obj, name))
+    return s
+
+
+class _TorchMemory:
+    """Device memory from torch's caching allocator, one stream."""
+
+    def __init__(self, device: int):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.stream = torch.cuda.Stream(device=device)
+        self.live: Dict[int, int] = {}
+        self.alloc_cb = ALLOC_FN(self._alloc)
+        self.free_cb = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, stream, user):
+        try:
+            ptr = self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, self.stream)
+        except Exception:
+            return None
+        self.live[int(ptr)] = int(nbytes)
+        return ptr
+
+    def _free(self, ptr, stream, user):
+        if ptr and int(ptr) in self.live:
+            del self.live[int(ptr)]
+            self.torch.cuda.caching_allocator_delete(int(ptr))
+
+
+class Sim:
+    """One simulation context on one GPU (see include/mucite.h)."""
+
+    def __init__(self, *, seed: int = 7, pack_capacity: int, precision: int = PREC_FP64, device: int = 0,
+                 exit_capacity: int = 0, hbm_budget: int = 0, timing: bool = False, fp32_tables: bool = False,
+                 use_torch: bool = True):
+        self.L = load_library()
+        self._mem = _TorchMemory(device) if use_torch else None
+        o = Options()
+        o.precision = precision
+        o.device = device
+        o.seed = seed
+        o.pack_capacity = pack_capacity
+        o.exit_capacity = exit_capacity
+        o.hbm_budget = hbm_budget
+        o.timing = int(timing)
+        o.fp32_tables = int(fp32_tables)
+        if self._mem is not None:
+            o.stream = self._mem.stream.cuda_stream
+            o.alloc = self._mem.alloc_cb
+            o.free = self._mem.free_cb
+        self._h = C.c_void_p()
+        rc = self.L.mc_create(C.byref(o), C.byref(self._h))
+        if rc != MC_OK:
+            raise MucateError(rc, "mc_create", "context creation failed")
+        self.precision = precision
+        self.nr = self.nz = 0
+        self.n_exit_bins = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.L.mc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, rc: int, where: str) -> None:
+        if rc != MC_OK:
+            raise MucateError(rc, where, (self.L.mc_last_error(self._h) or b"").decode())
+
+    # -- setup --------------------------------------------------------------
+    def load_fields(self, f) -> None:
+        g = f.grid
+        self.nr, self.nz = g.nr, g.nz
+        arrs = [_f64(a) for a in (f.phi_dc, f.phi_off, f.phi_rf, f.gas_ur, f.gas_uz, f.gas_p, f.gas_t)]
+        mask = np.ascontiguousarray(f.mask, dtype=np.uint8)
+        t = FieldTables(*[_p(a, F64) for a in arrs], _p(mask, C.c_uint8))
+        self._chk(self.L.mc_load_fields(self._h, C.byref(Grid(g.nr, g.nz, g.dr, g.dz)), C.byref(t)), "mc_load_fields")
+
+    def define_ion(self, ion) -> int:
+        out = I32()
+        self._chk(self.L.mc_define_ion(self._h, C.byref(_struct(Ion, ion)), C.byref(out)), "mc_define_ion")
+        return out.value
+
+    def set_operating(self, op) -> None:
+        self.n_exit_bins = op.n_exit_bins
+        self._chk(self.L.mc_set_operating(self._h, C.byref(_struct(Operating, op))), "mc_set_operating")
+
+    def define_source(self, src) -> int:
+        out = I32()
+        self._chk(self.L.mc_define_source(self._h, C.byref(_struct(Source, src)), C.byref(out)), "mc_define_source")
+        return out.value
+
+    def setup(self, fields, ions, sources, op) -> None:
+        self.load_fields(fields)
+        for i in ions:
+            self.define_ion(i)
+        self.set_operating(op)
+        for s in sources:
+            self.define_source(s)
+
+    # -- run ----------------------------------------------------------------
+    def inject(self, src: int, n: int) -> None:
+        self._chk(self.L.mc_inject(self._h, src, n), "mc_inject")
+
+    def step(self, n: int = 1) -> None:
+        self._chk(self.L.mc_step(self._h, n), "mc_step")
+
+    def pic_update(self) -> None:
+        self._chk(self.L.mc_pic_update(self._h), "mc_pic_update")
+
+    def synchronize(self) -> None:
+        self._chk(self.L.mc_synchronize(self._h), "mc_synchronize")
+
+    def info(self) -> Dict[str, int]:
+        i = Info()
+        self._chk(self.L.mc_get_info(self._h, C.byref(i)), "mc_get_info")
+        return {f: getattr(i, f) for f, _ in Info._fields_}
+
+    # -- read/write ------------------------------------------------------------
+    def read_packs(self) -> Dict[str, np.ndarray]:
+        n = self.info()["n_slots"]
+        out = {f: np.zeros(n) for f in ("x", "y", "z", "vx", "vy", "vz", "e_int", "h", "w")}
+        out.update(id=np.zeros(n, np.int64), q=np.zeros(n, np.int64), tag=np.zeros(n, np.int32),
+                   status=np.zeros(n, np.int32))
+        P = Packs()
+        P.n = n
+        for k, a in out.items():
+            setattr(P, k, _p(a, {np.float64: F64, np.int64: I64, np.int32: I32}[a.dtype.type]))
+        self._chk(self.L.mc_read_packs(self._h, C.byref(P)), "mc_read_packs")
+        return out
+
+    def write_packs(self, snap: Dict[str, np.ndarray]) -> None:
+        n = len(snap["x"])
+        arrs = {f: _f64(snap[f]) for f in ("x", "y", "z", "vx", "vy", "vz", "e_int", "h", "w")}
+        arrs["id"] = np.ascontiguousarray(snap["id"], dtype=np.int64)
+        arrs["tag"] = np.ascontiguousarray(snap["tag"], dtype=np.int32)
+        P = Packs()
+        P.n = n
+        for k, a in arrs.items():
+            setattr(P, k, _p(a, {np.float64: F64, np.int64: I64, np.int32: I32}[a.dtype.type]))
+        self._chk(self.L.mc_write_packs(self._h, C.byref(P)), "mc_write_packs")
+
+    def read_tallies(self) -> Dict[str, object]:
+        T = Tallies()
+        bufs = dict(exit_bins=np.zeros(self.n_exit_bins, np.int64), loss_map=np.zeros((self.nz, self.nr), np.int64),
+                    hist_ke=np.zeros(HIST_KE, np.int64), hist_teff=np.zeros(HIST_TEFF, np.int64),
+                    hist_r=np.zeros(HIST_R, np.int64), act_hist_ke=np.zeros(HIST_KE, np.int64),
+                    act_hist_teff=np.zeros(HIST_TEFF, np.int64))
+        for k, a in bufs.items():
+            setattr(T, k, _p(a, I64))
+        self._chk(self.L.mc_read_tallies(self._h, C.byref(T)), "mc_read_tallies")
+        out = dict(bufs)
+        for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "pack_steps", "exit_overflow",
+                  "exit_dropped", "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
+            out[k] = getattr(T, k)
+        out["class_n"] = np.array(list(T.class_n), np.int64)
+        out["class_w"] = np.array(list(T.class_w), np.int64)
+        return out
+
+    def read_exits(self) -> np.ndarray:
+        n = I64()
+        self._chk(self.L.mc_read_exits(self._h, None, 0, C.byref(n)), "mc_read_exits")
+        buf = np.zeros(max(n.value, 1), dtype=EXIT_DTYPE)
+        self._chk(self.L.mc_read_exits(self._h, buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(n)),
+                  "mc_read_exits")
+        return buf[: min(n.value, buf.size)]
+
+    def read_charge(self) -> np.ndarray:
+        q = np.zeros((self.nz, self.nr), np.int64)
+        self._chk(self.L.mc_read_charge(self._h, _p(q, I64)), "mc_read_charge")
+        return q
+
+    def read_sc(self):
+        phi, er, ez = (np.zeros((self.nz, self.nr)) for _ in range(3))
+        self._chk(self.L.mc_read_sc(self._h, _p(phi, F64), _p(er, F64), _p(ez, F64)), "mc_read_sc")
+        return phi, er, ez
+
+    def read_hit(self) -> np.ndarray:
+        h = np.zeros((self.nz, self.nr), np.uint8)
+        self._chk(self.L.mc_read_hit(self._h, _p(h, C.c_uint8)), "mc_read_hit")
+        return h
+
+    def read_timing(self) -> Dict[str, object]:
+        t = Timing()
+        self._chk(self.L.mc_read_timing(self._h, C.byref(t)), "mc_read_timing")
+        return {"ms": dict(zip(KERNEL_NAMES, list(t.ms))), "launches": dict(zip(KERNEL_NAMES, list(t.launches))),
+                "pack_steps": t.pack_steps}
+
+    def reset_timing(self) -> None:
+        self._chk(self.L.mc_reset_timing(self._h), "mc_reset_timing")
+
+
+def declared_symbols(header: str = HEADER):
+    """Names of the functions declared in include/mucite.h."""
+    import re
+    text = open(header).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|void|const char \*)\s*\*?\s*(mc_[a-z_0-9]+)\s*\(", text, re.M)))

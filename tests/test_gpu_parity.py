@@ -1,0 +1,330 @@
+"""GPU (HIP, gfx950) against the CPU FP64 oracle, through the C ABI.
+
+Bars: bit-exact for integer work (hit table, deposit grid, loss indices,
+emission counts, int64 tallies on identical positions); per-pack single-step
+state within 1e-6 relative; statistics within stated bounds.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_31258_amd import synth
+from tests.parity_util import by_id, frac_bound, make_pair, step_errors, thermal_speed
+
+pytestmark = pytest.mark.gpu
+
+KB, DA = 1.380649e-23, 1.66053906892e-27
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _c1(n=10_000):
+    return synth.config_c1(n)
+
+
+def _c2_like(n=100_000):
+    f, ions, srcs, op, meta = synth.config_c2(n_packs=n)
+    return f, ions, srcs, op, meta
+
+
+# ---------------------------------------------------------------------------
+# Setup tables
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("cfg,d_hit", [("c1", 1e-5), ("c2", 1e-5), ("c2", 6e-5), ("c1t", 4e-5)])
+def test_hit_table_bit_exact(cfg, d_hit):
+    _say("hit table", cfg, d_hit)
+    f, ions, srcs, op, _ = {"c1": synth.config_c1, "c2": synth.config_c2, "c1t": synth.config_c1t}[cfg]()
+    op.d_hit = d_hit
+    g, o = make_pair(f, ions, srcs, op, cap=16)
+    hg, ho = g.read_hit(), o.read_hit()
+    assert hg.sum() > 0
+    assert np.array_equal(hg, ho)
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Emission
+# ---------------------------------------------------------------------------
+
+def test_burst_injection_matches_oracle():
+    _say("burst injection C1")
+    f, ions, srcs, op, _ = _c1()
+    g, o = make_pair(f, ions, srcs, op, cap=10_000)
+    g.inject(0, 10_000)
+    o.inject(0, 10_000)
+    a, b = by_id(g.read_packs()), by_id(o.read_packs())
+    assert np.array_equal(a["id"], b["id"]) and np.array_equal(a["q"], b["q"]) and np.array_equal(a["tag"], b["tag"])
+    for k in ("x", "y", "vx", "vy", "vz"):
+        err = np.abs(a[k] - b[k]) / (np.abs(b[k]).max())
+        assert err.max() < 1e-12, (k, err.max())
+    assert np.array_equal(a["z"], b["z"])
+    assert np.allclose(a["e_int"], b["e_int"], rtol=1e-13)
+    g.close()
+
+
+def test_rate_source_counts_and_weights_exact():
+    _say("rate source C2")
+    f, ions, srcs, op, _ = _c2_like(n=1700)
+    op.collisions_on = 0
+    g, o = make_pair(f, ions, srcs, op, cap=2000)
+    g.step(4)
+    o.step(4)
+    ta, tb = g.read_tallies(), o.read_tallies()
+    assert ta["emitted_n"] == tb["emitted_n"] == 1700
+    assert ta["emitted_w"] == tb["emitted_w"]
+    a, b = by_id(g.read_packs()), by_id(o.read_packs())
+    assert np.array_equal(a["id"], b["id"]) and np.array_equal(a["q"], b["q"]) and np.array_equal(a["w"], b["w"])
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Single step from a shared snapshot
+# ---------------------------------------------------------------------------
+
+def _snapshot_case(cfg, n):
+    if cfg == "c1":
+        f, ions, srcs, op, _ = _c1()
+        snap = synth.pack_snapshot(n, f, seed=11, e_lo=1.2e-19, e_hi=6e-19)
+    elif cfg == "c1t":
+        f, ions, srcs, op, _ = synth.config_c1t()
+        snap = synth.pack_snapshot(n, f, seed=12, v_sigma=400.0, e_lo=1.2e-19, e_hi=6e-19)
+    else:
+        f, ions, _, op, _ = _c2_like()
+        srcs = []  # no continuous emission into a snapshot
+        op.sc_on = 0
+        snap = synth.pack_snapshot(n, f, seed=13, v_sigma=60.0, e_lo=1.5e-18, e_hi=4e-18)
+    snap["h"] = np.random.default_rng(3).uniform(0, 1e-3, n)
+    return f, ions, srcs, op, snap
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c1t", "c2"])
+def test_single_step_fp64_within_1e6(cfg):
+    n = 20_011  # ragged: not a multiple of the block size
+    _say("single step fp64", cfg, n)
+    f, ions, srcs, op, snap = _snapshot_case(cfg, n)
+    g, o = make_pair(f, ions, srcs, op, cap=n)
+    g.write_packs(snap)
+    o.write_packs(snap)
+    g.step(1)
+    o.step(1)
+    r = step_errors(g.read_packs(), o.read_packs(), f.grid.dr, thermal_speed(), snap["h"])
+    _say(f"  max dx {r['max_dx']:.2e} dv {r['max_dv']:.2e} de {r['max_de']:.2e} dh {r['max_dh']:.2e} "
+         f"status flips {int((~r['same_status']).sum())}")
+    assert r["same_status"].all()
+    assert r["ok"].sum() >= n - max(1, n // 10_000)
+    ta, tb = g.read_tallies(), o.read_tallies()
+    assert np.array_equal(ta["class_n"], tb["class_n"])
+    assert np.array_equal(ta["class_w"], tb["class_w"])
+    assert np.array_equal(ta["loss_map"], tb["loss_map"])
+    assert abs(ta["n_cand"] - tb["n_cand"]) <= max(2, tb["n_cand"] // 100_000)
+    ea, eb = g.read_exits(), o.read_exits()
+    assert np.array_equal(ea["id"], eb["id"]) and np.array_equal(ea["cls"], eb["cls"])
+    assert np.array_equal(ea["inode"], eb["inode"]) and np.array_equal(ea["jnode"], eb["jnode"])
+    g.close()
+
+
+def test_multi_step_fp64_pathwise():
+    _say("multi step fp64 C1, 25 steps")
+    f, ions, srcs, op, _ = _c1(3000)
+    g, o = make_pair(f, ions, srcs, op, cap=3000)
+    g.inject(0, 3000)
+    o.inject(0, 3000)
+    g.step(25)
+    o.step(25)
+    a, b = by_id(g.read_packs()), by_id(o.read_packs())
+    dv = np.linalg.norm(np.stack([a[k] - b[k] for k in ("vx", "vy", "vz")], 1), axis=1)
+    good = np.mean(dv <= 1e-6 * (np.linalg.norm(np.stack([b[k] for k in ("vx", "vy", "vz")], 1), axis=1) +
+                                 thermal_speed()))
+    _say(f"  fraction pathwise-identical after 25 steps: {good:.5f}")
+    assert good >= 0.99
+    ta, tb = g.read_tallies(), o.read_tallies()
+    assert abs(ta["n_cand"] - tb["n_cand"]) <= 1e-3 * tb["n_cand"]
+    assert abs(ta["n_coll"] - tb["n_coll"]) <= 1e-3 * tb["n_coll"]
+    assert ta["emitted_w"] == tb["emitted_w"]
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Space charge: bit-exact deposit, Poisson, field
+# ---------------------------------------------------------------------------
+
+def _edge_packs(f, n0):
+    g = f.grid
+    xs = [0.0, g.dr, 3 * g.dr, 0.5 * g.dr, g.R * 0.999, 0.0, 7 * g.dr]
+    zs = [0.0, g.dz, 10 * g.dz, 0.5 * g.dz, g.L * 0.5, g.L * 0.9999, 13.5 * g.dz]
+    k = len(xs)
+    return dict(x=np.array(xs), y=np.zeros(k), z=np.array(zs), vx=np.zeros(k), vy=np.zeros(k), vz=np.zeros(k),
+                e_int=np.full(k, 2e-18), h=np.zeros(k), w=np.linspace(0.3, 3.0, k),
+                id=np.arange(n0, n0 + k, dtype=np.int64), tag=np.zeros(k, np.int32))
+
+
+def test_pic_update_bit_exact_deposit_and_poisson():
+    n = 200_000
+    _say("pic update C2 grid", n)
+    f, ions, srcs, op, _ = _c2_like()
+    snap = synth.pack_snapshot(n, f, seed=21, z_hi=f.grid.L * 0.3, r_hi=1.5e-3, weight=0.012483)
+    edge = _edge_packs(f, n)
+    snap = {k: np.concatenate([snap[k], edge[k]]) for k in snap}
+    g, o = make_pair(f, ions, srcs, op, cap=len(snap["x"]))
+    g.write_packs(snap)
+    o.write_packs(snap)
+    g.pic_update()
+    o.pic_update()
+    qa, qb = g.read_charge(), o.read_charge()
+    assert np.array_equal(qa, qb)
+    assert qa.sum() == by_id(o.read_packs())["q"].sum()
+    pa, era, eza = g.read_sc()
+    pb, erb, ezb = o.read_sc()
+    scale = np.abs(pb).max()
+    assert scale > 0
+    _say(f"  phi max rel err {np.abs(pa - pb).max() / scale:.2e}")
+    assert np.abs(pa - pb).max() <= 1e-10 * scale
+    es = max(np.abs(erb).max(), np.abs(ezb).max())
+    assert np.abs(era - erb).max() <= 1e-8 * es and np.abs(eza - ezb).max() <= 1e-8 * es
+    g.close()
+
+
+def test_pic_update_empty_population():
+    _say("pic update, no packs")
+    f, ions, _, op, _ = _c2_like()
+    g, o = make_pair(f, ions, [], op, cap=8)
+    g.pic_update()
+    assert not g.read_charge().any()
+    phi, er, ez = g.read_sc()
+    assert not phi.any() and not er.any() and not ez.any()
+    g.step(3)  # empty steps are no-ops
+    t = g.read_tallies()
+    assert t["class_n"].sum() == 0 and t["pack_steps"] == 0
+    g.close()
+
+
+def test_full_size_c2_sampled_step():
+    """The 256x1024 grid at its full 1e6-pack population, space charge on, in
+    the launch configuration the benchmark times: deposit grid bit-exact at
+    full size, and 2000 sampled packs stepped by the oracle one by one."""
+    n = 1_000_000
+    _say("full-size C2 sampled", n)
+    f, ions, srcs, op, _ = synth.config_c2()
+    snap = synth.pack_snapshot(n, f, seed=31, z_hi=3e-3, r_hi=6e-4, v_sigma=40.0, v_drift=250.0,
+                               e_lo=1.5e-18, e_hi=3e-18, weight=0.012483)
+    from oracle.binding import OracleSim
+    from paper_2609_31258_amd import mucite
+    g = mucite.Sim(seed=synth.SEED, pack_capacity=n)
+    g.setup(f, ions, [], op)
+    g.write_packs(snap)
+    g.step(1)  # step 0: space-charge update from all packs, then the step
+    o = OracleSim(synth.SEED)
+    o.setup(f, ions, [], op)
+    o.write_packs(snap)
+    o.pic_update()
+    assert np.array_equal(g.read_charge(), o.read_charge())
+    op2 = synth.Operating(**{**op.__dict__, "sc_on": 0})
+    o.set_operating(op2)
+    pick = np.sort(np.random.default_rng(5).choice(n, 2000, replace=False))
+    sub = {k: v[pick] for k, v in snap.items()}
+    o.write_packs(sub)
+    o.step(1)
+    a = g.read_packs()
+    a = {k: v[pick] for k, v in a.items()}  # slots are in snapshot order
+    r = step_errors(a, o.read_packs(), f.grid.dr, thermal_speed(), sub["h"])
+    _say(f"  max dx {r['max_dx']:.2e} dv {r['max_dv']:.2e} de {r['max_de']:.2e}")
+    assert r["ok"].sum() >= 1999
+    g.close()
+
+
+# ---------------------------------------------------------------------------
+# Statistics over a run that transmits and loses packs
+# ---------------------------------------------------------------------------
+
+def test_loss_and_transmission_statistics():
+    _say("C1T-like run with losses")
+    f, ions, srcs, op, _ = synth.config_c1t(4000)
+    srcs[0].z_inj = 2.0e-3
+    op.v_rf = 300.0
+    g, o = make_pair(f, ions, srcs, op, cap=4000)
+    g.inject(0, 4000)
+    o.inject(0, 4000)
+    g.step(1500)
+    o.step(1500)
+    ta, tb = g.read_tallies(), o.read_tallies()
+    _say("  gpu classes", ta["class_n"].tolist(), "oracle", tb["class_n"].tolist())
+    assert ta["emitted_w"] == tb["emitted_w"] == ta["class_w"].sum() == tb["class_w"].sum()
+    n = 4000
+    for c in range(5):
+        fa, fb = ta["class_n"][c] / n, tb["class_n"][c] / n
+        assert abs(fa - fb) <= frac_bound(fa, fb, n, n) + 2.0 / n, c
+    assert ta["class_n"][2] > 0  # the run does lose packs on electrodes
+    # loss map compared per ring: electrode weights summed over z windows
+    la, lb = ta["loss_map"].sum(axis=1), tb["loss_map"].sum(axis=1)
+    L = f.grid.nz
+    for k in range(8):
+        zk = int(round((k + 1) * (L - 1) / 9))
+        wa, wb = la[zk - 8: zk + 9].sum() / 2 ** 32, lb[zk - 8: zk + 9].sum() / 2 ** 32
+        assert abs(wa - wb) <= 4 * math.sqrt(max(wa, wb, 1.0)) + 2, k
+    g.close()
+
+
+def test_gpu_run_is_deterministic():
+    _say("determinism")
+    f, ions, srcs, op, _ = synth.config_c1t(2000)
+    srcs[0].z_inj = 2.0e-3
+    op.v_rf = 300.0
+    from paper_2609_31258_amd import mucite
+    outs = []
+    for _ in range(2):
+        g = mucite.Sim(seed=synth.SEED, pack_capacity=2000)
+        g.setup(f, ions, srcs, op)
+        g.inject(0, 2000)
+        g.step(300)
+        outs.append((g.read_packs(), g.read_tallies(), g.read_exits()))
+        g.close()
+    (p0, t0, e0), (p1, t1, e1) = outs
+    for k in p0:
+        assert np.array_equal(p0[k], p1[k]), k
+    for k in t0:
+        assert np.array_equal(np.asarray(t0[k]), np.asarray(t1[k])), k
+    assert np.array_equal(e0, e1)
+
+
+# ---------------------------------------------------------------------------
+# Precision form: error report against the FP64 oracle
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fp32_tables", [False, True])
+def test_fp32_form_single_step_error(fp32_tables):
+    n = 20_000
+    _say("fp32 form single step, fp32 tables" if fp32_tables else "fp32 form single step, bf16 tables")
+    f, ions, srcs, op, snap = _snapshot_case("c2", n)
+    g, o = make_pair(f, ions, srcs, op, cap=n, precision=1, fp32_tables=fp32_tables)
+    g.write_packs(snap)
+    o.write_packs(snap)
+    g.step(1)
+    o.step(1)
+    r = step_errors(g.read_packs(), o.read_packs(), f.grid.dr, thermal_speed(), snap["h"])
+    flips = int((~r["same_status"]).sum())
+    _say(f"  median dv {np.median(r['dv']):.2e} p99 dv {np.quantile(r['dv'], 0.99):.2e} "
+         f"median dx {np.median(r['dx']):.2e} median de {np.median(r['de']):.2e} flips {flips}")
+    assert flips <= max(2, n // 1000)
+    assert np.median(r["dv"]) < 1e-3
+    assert np.median(r["dx"]) < 1e-5
+    g.close()
+
+
+def test_timing_and_pack_step_counter():
+    _say("timing")
+    f, ions, srcs, op, _ = _c1(4000)
+    from paper_2609_31258_amd import mucite
+    g = mucite.Sim(seed=synth.SEED, pack_capacity=4000, timing=True)
+    g.setup(f, ions, srcs, op)
+    g.inject(0, 4000)
+    g.step(10)
+    t = g.read_timing()
+    assert t["launches"]["step"] == 10 and t["ms"]["step"] > 0
+    assert t["pack_steps"] == g.read_tallies()["pack_steps"] == 40_000
+    g.close()
