@@ -132,6 +132,12 @@ def load_library():
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built; run `python -m paper_2609_31258_amd.build`")
+    try:
+        # torch carries its own HIP runtime under the same soname; loading it
+        # first makes the library bind to that one copy instead of a second
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(L, name)
