@@ -1,0 +1,227 @@
+"""Benchmark: ion-pack steps per second on one MI355X.
+
+Workload (the space-charge configuration on the 256 x 1024 grid): ring
+electrode fields at 0.05 mm spacing, 1e6 packs injected at 500 per step and
+weighted to a 10 nA current, ion m = 5000 Da, z = +5, CCS 1500 A^2, N2 gas at
+1e5 -> 200 Pa, collisions on, CIC deposit + Poisson every 10 steps,
+dt = 0.5 ns.  A step is one pass of the whole path (emission, RK4 push,
+classification, collisions, dissociation, tallies, and the space-charge
+update every 10th step).  `warmup` steps run untimed first (the default
+fills the population to 1e6 packs); then exactly `steps` steps are timed
+with the device synchronised on both sides.  value = active pack-steps
+advanced in the timed window / wall seconds, FP64 path; the FP32 form
+(FP32 math, BF16 tables, two-float positions) is timed the same way and
+reported beside it.
+
+Also reported: the dominant kernel's roofline (HIP events around every
+launch of the fused step kernel), and the CPU oracle's rate on a bounded
+sample of the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "ion-pack steps/s (push+collision+PIC) FP32 vs FP64 GPU; serving p50/p99 latency"
+WORKLOAD = ("256x1024 ring-electrode grid (0.05 mm), 1e6 packs injected at 500/step weighted to 10 nA, "
+            "m=5000 Da z=+5 CCS 1500 A^2 N2, CIC+Poisson every 10 steps, dt=0.5 ns; timed window at full occupancy")
+
+# Peak vector rate of MI355X for the arithmetic this kernel issues: 256 CUs x
+# 64 lanes x 2.4 GHz, an FMA counted as two operations (the FP64 vector peak,
+# 78.6 TFLOP/s; unpacked FP32 issues at the same rate -- packed FP32 is not
+# used).
+PEAK_OPS = 256 * 64 * 2 * 2.4e9
+
+# Algorithmic operation counts of the fused step kernel: each add, multiply,
+# compare/select, integer xor/add/multiply half, conversion and elementary
+# function evaluation of the method counts as one operation (a Philox4x32-10
+# block is 104).  Per event:
+OPS_PACK_STEP = 567       # RK4 with four bilinear field gathers, classification, gas gather and
+                          # collision setup, the final wait that ends the step, dissociation
+OPS_CANDIDATE = 276       # every candidate inside the step: two Philox blocks, wait, partner draw, test
+OPS_ACCEPTED = 161        # accepted candidate: third block, impulsive update, scattering
+OPS_EXCHANGE = 18         # internal-energy exchange (taken with probability alpha)
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_traffic.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_31258_amd", "csrc", f) for f in ("mc_kernels.hpp", "mc_device.hpp")]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    or None when the kernels changed after the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    v = kv.get(f"{precision}_hbm_bytes_per_launch")
+    return float(v) if v else None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--precision", choices=["fp64", "fp32", "both"], default="both")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-packs", type=int, default=400_000)
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    return ap.parse_args()
+
+
+def run_gpu(precision: int, steps: int, warmup: int):
+    import torch
+    from paper_2609_31258_amd import mucite, synth
+    f, ions, srcs, op, _ = synth.config_c2()
+    sim = mucite.Sim(seed=synth.SEED, pack_capacity=srcs[0].n_total, precision=precision, timing=True)
+    sim.setup(f, ions, srcs, op)
+    t0 = time.time()
+    done = 0
+    while done < warmup:  # progress lines come from the work itself
+        k = min(500, warmup - done)
+        sim.step(k)
+        sim.synchronize()
+        done += k
+        print(f"[bench] {'fp64' if precision == 0 else 'fp32'} warmup {done}/{warmup} "
+              f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    sim.reset_timing()
+    before = sim.read_tallies()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    after = sim.read_tallies()
+    tim = sim.read_timing()
+    info = sim.info()
+    sim.close()
+    wall = t2 - t1
+    ps = after["pack_steps"] - before["pack_steps"]
+    cand = after["n_cand"] - before["n_cand"]
+    coll = after["n_coll"] - before["n_coll"]
+    return dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim, slots=info["n_slots"],
+                active=int(after["class_n"][0]), classes=after["class_n"].tolist())
+
+
+def roofline(r, precision: str, alpha: float):
+    ms = r["timing"]["ms"]["step"]
+    launches = max(r["timing"]["launches"]["step"], 1)
+    avg_s = ms / 1e3 / launches
+    ops = (r["pack_steps"] * OPS_PACK_STEP + r["cand"] * OPS_CANDIDATE +
+           r["coll"] * (OPS_ACCEPTED + alpha * OPS_EXCHANGE))
+    ops_per_launch = ops / launches
+    achieved = ops_per_launch / avg_s
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12, "unit": "Top/s",
+            "frac": achieved / PEAK_OPS, "traffic": measured_traffic(precision),
+            "kernel": "k_step (fused push/classify/collide)", "avg_launch_ms": avg_s * 1e3, "launches": launches,
+            "ops_per_launch": ops_per_launch}
+
+
+def default_alpha() -> float:
+    """Internal-exchange probability of the workload's ion (default rule
+    4 mg ma / (mg + ma)^2, ma = m / n_atoms)."""
+    from paper_2609_31258_amd import synth
+    _, ions, _, _, _ = synth.config_c2()
+    mg, ma = synth.M_N2_DA, ions[0].mass_da / ions[0].n_atoms
+    return 4 * mg * ma / (mg + ma) ** 2
+
+
+def cpu_baseline(n_packs: int, n_steps: int):
+    """The oracle as it stands, on this host's cores, on a bounded sample:
+    n_packs packs in the full-occupancy state of the same workload (packs
+    within 0.3 mm of the injection plane, thermal about the gas flow),
+    n_steps steps including the space-charge updates."""
+    from oracle.binding import OracleSim, num_threads
+    from paper_2609_31258_amd import synth
+    f, ions, srcs, op, _ = synth.config_c2()
+    snap = synth.pack_snapshot(n_packs, f, seed=synth.SEED, z_hi=3e-4, r_hi=3e-4, v_sigma=22.0, v_drift=300.0,
+                               e_lo=1.7e-18, e_hi=1.9e-18, weight=srcs[0].current_a * op.dt / (5 * 1.602176634e-19) / 500)
+    o = OracleSim(synth.SEED)
+    o.setup(f, ions, [], op)
+    o.write_packs(snap)
+    t0 = time.perf_counter()
+    o.step(n_steps)
+    wall = time.perf_counter() - t0
+    T = o.read_tallies()
+    cores = num_threads()
+    return {"value": n_packs * n_steps / wall, "unit": "pack-steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n_packs} packs at full-occupancy state of the same workload, {n_steps} steps "
+                      f"({(n_steps + 9) // 10} space-charge updates), {wall:.1f} s",
+            "collisions_per_s": T["n_coll"] / wall}
+
+
+def copy_calibration():
+    import torch
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"[bench] copy calibration: {n} bytes read, {n} bytes written", file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it"}))
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    if args.copy_calibration:
+        copy_calibration()
+    res = {}
+    if args.precision in ("fp64", "both"):
+        res["fp64"] = run_gpu(0, args.steps, args.warmup)
+    if args.precision in ("fp32", "both"):
+        res["fp32"] = run_gpu(1, args.steps, args.warmup)
+    main_key = "fp64" if "fp64" in res else "fp32"
+    r = res[main_key]
+    value = r["pack_steps"] / r["wall"]
+    out = {
+        "metric": METRIC, "value": value, "unit": "pack-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["wall"] * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if main_key == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "grid": [256, 1024], "packs": r["slots"], "active": r["active"],
+                   "sc_every": 10, "dt_s": 0.5e-9, "precision": main_key},
+        "roofline": roofline(r, main_key, default_alpha()),
+        "collisions_per_s": r["coll"] / r["wall"],
+        "candidates_per_pack_step": r["cand"] / max(r["pack_steps"], 1),
+        "kernel_ms": r["timing"]["ms"],
+    }
+    if "fp32" in res and main_key == "fp64":
+        q = res["fp32"]
+        out["fp32_form"] = {"value": q["pack_steps"] / q["wall"], "unit": "pack-steps/s",
+                            "ms_per_step": q["wall"] * 1e3 / args.steps, "dtype": "f32 (BF16 tables)",
+                            "speedup_vs_fp64": (q["pack_steps"] / q["wall"]) / value,
+                            "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"]}
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_packs, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -77,7 +77,7 @@ def lib():
         "orc_poisson": (None, [I32, I32, F64, F64, PD, PD]),
         "orc_poisson_residual": (F64, [I32, I32, F64, F64, PD, PD]),
         "orc_rho_from_charge": (None, [I32, I32, F64, F64, PI64, PD]),
-        "orc_iict_update": (None, [F64, F64, PD, PD, F64, F64, F64, C.POINTER(U32), PD, PD, PD, PI32]),
+        "orc_iict_update": (None, [F64, F64, PD, PD, F64, F64, F64, PD, PD, PD, PD, PI32]),
         "orc_collision_probe": (I32, [F64, F64, F64, F64, F64, PD, PD, F64, I64, U64, C.POINTER(Probe)]),
         "orc_create": (C.c_void_p, [U64]),
         "orc_destroy": (None, [C.c_void_p]),
@@ -88,6 +88,7 @@ def lib():
         "orc_inject": (I32, [C.c_void_p, I32, I64]),
         "orc_step": (I32, [C.c_void_p, I64]),
         "orc_num_packs": (I64, [C.c_void_p]),
+        "orc_num_threads": (I32, []),
         "orc_current_step": (I64, [C.c_void_p]),
         "orc_read_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
         "orc_write_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
@@ -138,6 +139,10 @@ def gather(tab: np.ndarray, dr: float, dz: float, r: float, z: float) -> float:
     return lib().orc_gather(_p(tab, F64), nr, nz, dr, dz, r, z)
 
 
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
 def einstein_u(t, n_atoms, theta=1100.0):
     return lib().orc_einstein_u(float(t), int(n_atoms), float(theta))
 
@@ -179,11 +184,11 @@ def rho_from_charge(q: np.ndarray, dr: float, dz: float) -> np.ndarray:
     return rho
 
 
-def iict_update(m, mg, v, vgas, e_int, t_eff, alpha, words):
+def iict_update(m, mg, v, vgas, e_int, t_eff, alpha, uniforms):
     v, vg = _f64(v), _f64(vgas)
-    w = np.asarray(words, dtype=np.uint32).copy()
+    w = _f64(uniforms).copy()
     vo, vgo, eo, cl = np.zeros(3), np.zeros(3), np.zeros(1), np.zeros(1, dtype=np.int32)
-    lib().orc_iict_update(m, mg, _p(v, F64), _p(vg, F64), e_int, t_eff, alpha, _p(w, U32), _p(vo, F64),
+    lib().orc_iict_update(m, mg, _p(v, F64), _p(vg, F64), e_int, t_eff, alpha, _p(w, F64), _p(vo, F64),
                           _p(vgo, F64), _p(eo, F64), _p(cl, I32))
     return vo, vgo, float(eo[0]), int(cl[0])
 

@@ -321,13 +321,14 @@ double orc_poisson_residual(int32_t nr, int32_t nz, double dr, double dz, const 
 /*    internal energy takes the difference (energy-conserving clamp at 0);    */
 /*    otherwise Et' = Et (elastic);                                           */
 /*  - isotropic scattering of the relative velocity, |g'| = sqrt(2 Et'/mu).   */
-/* Words: w[0] cos(chi), w[1] azimuth, w[2] exchange select, w[3], w[4] Gamma.*/
+/* Uniforms: u[0] cos(chi), u[1] azimuth, u[2] exchange select, u[3], u[4]   */
+/* the Gamma(2) draw.                                                       */
 /* Pinned: momentum and total (kinetic + internal) energy conservation, and  */
 /* thermalisation of T_eff to the gas temperature; the partition against the */
 /* paper's own adapter is parity unpinned.                                   */
 /* ------------------------------------------------------------------------ */
 void orc_iict_update(double m, double mg, const double v[3], const double vgas[3], double e_int, double t_eff,
-                     double alpha, const uint32_t w[5], double v_out[3], double vgas_out[3], double *e_int_out,
+                     double alpha, const double u[5], double v_out[3], double vgas_out[3], double *e_int_out,
                      int32_t *clamped) {
     double M = m + mg, mu = m * mg / M;
     double vcm[3], g[3];
@@ -338,8 +339,8 @@ void orc_iict_update(double m, double mg, const double v[3], const double vgas[3
     double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
     double et = 0.5 * mu * g2, etp = et;
     *clamped = 0;
-    if (u01(w[2]) < alpha) {
-        etp = -KB * t_eff * log(u01(w[3]) * u01(w[4]));
+    if (u[2] < alpha) {
+        etp = -KB * t_eff * log(u[3] * u[4]);
         double e_new = e_int + et - etp;
         if (e_new < 0.0) {
             etp = e_int + et;
@@ -348,9 +349,9 @@ void orc_iict_update(double m, double mg, const double v[3], const double vgas[3
         }
         e_int = e_new;
     }
-    double cchi = 2.0 * u01(w[0]) - 1.0;
+    double cchi = 2.0 * u[0] - 1.0;
     double schi = sqrt(fmax(0.0, 1.0 - cchi * cchi));
-    double psi = 2.0 * PI * u01(w[1]);
+    double psi = 2.0 * PI * u[1];
     double gp = sqrt(2.0 * etp / mu);
     double dir[3] = {schi * cos(psi), schi * sin(psi), cchi};
     for (int a = 0; a < 3; ++a) {
@@ -376,7 +377,14 @@ void orc_iict_update(double m, double mg, const double v[3], const double vgas[3
 /* when lambda dt << 1.  Pinned: accepted rate against the closed form       */
 /* n sigma [a_g sqrt(2/pi) exp(-s^2/2a_g^2) + (s + a_g^2/s) erf(s/(sqrt2 a_g))],*/
 /* the partner law, thermalisation and mobility.                            */
-/* Words per candidate c: blocks 3c (w0..w3), 3c+1 (w4..w7), 3c+2 (w8..w11). */
+/* Partner draw: speed from E = |w|^2 / (2 a_g^2) and an isotropic          */
+/* direction; E ~ Gamma(3/2) = -ln u_a - ln u_b cos^2(2 pi u_c) (exponential */
+/* plus half a squared normal) for the Maxwellian, E ~ Gamma(2) =            */
+/* -ln u_a - ln u_b for the flux-weighted form.                             */
+/* Words per candidate c: block 3c = (wait, branch, u_a, u_b), block 3c+1 =  */
+/* (u_c, cos theta, azimuth, accept), block 3c+2 = (cos chi, psi, Gamma,     */
+/* Gamma), drawn on acceptance; the exchange select is the acceptance        */
+/* residual u_acc (s + |w|) / |g|, uniform given acceptance.               */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     double m, mg, sigma, alpha, theta;
@@ -413,27 +421,17 @@ static void collide(const coll_env_t *E, const uint32_t key[2], int64_t id, int6
         t_left -= tau;
         cnt->n_cand++;
         draw(key, id, step, PURPOSE_COLLIDE, (uint32_t)(3 * c + 1), wb);
-        double w[3], wn;
-        if (u01(wa[1]) < s / (s + E->abar)) {
-            /* Maxwellian partner: three normals by Box-Muller */
-            double r1 = sqrt(-2.0 * log(u01(wa[2]))), p1 = 2.0 * PI * u01(wa[3]);
-            double r2 = sqrt(-2.0 * log(u01(wb[0]))), p2 = 2.0 * PI * u01(wb[1]);
-            w[0] = E->a_g * r1 * cos(p1);
-            w[1] = E->a_g * r1 * sin(p1);
-            w[2] = E->a_g * r2 * cos(p2);
-            wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-        } else {
-            /* flux-weighted partner: |w|^2/(2 a_g^2) ~ Gamma(2,1), isotropic direction */
-            wn = E->a_g * sqrt(-2.0 * log(u01(wa[2]) * u01(wa[3])));
-            double ct = 2.0 * u01(wb[0]) - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
-            double ph = 2.0 * PI * u01(wb[1]);
-            w[0] = wn * st * cos(ph);
-            w[1] = wn * st * sin(ph);
-            w[2] = wn * ct;
-        }
+        int maxw = u01(wa[1]) < s / (s + E->abar);
+        double cc = cos(2.0 * PI * u01(wb[0]));
+        double en = -log(u01(wa[2])) - log(u01(wa[3])) * (maxw ? cc * cc : 1.0);
+        double wn = E->a_g * sqrt(2.0 * en);
+        double ct = 2.0 * u01(wb[1]) - 1.0, st = sqrt(fmax(0.0, 1.0 - ct * ct));
+        double ph = 2.0 * PI * u01(wb[2]);
+        double w[3] = {wn * st * cos(ph), wn * st * sin(ph), wn * ct};
         double g[3] = {rel[0] - w[0], rel[1] - w[1], rel[2] - w[2]};
         double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
-        if (!(u01(wb[2]) * (s + wn) < gn)) continue;
+        double uacc = u01(wb[3]);
+        if (!(uacc * (s + wn) < gn)) continue;
         cnt->n_acc++;
         cnt->sum_g += gn;
         cnt->sum_g2 += gn * gn;
@@ -441,10 +439,10 @@ static void collide(const coll_env_t *E, const uint32_t key[2], int64_t id, int6
         draw(key, id, step, PURPOSE_COLLIDE, (uint32_t)(3 * c + 2), wc);
         double vgas[3] = {E->u[0] + w[0], E->u[1] + w[1], E->u[2] + w[2]};
         double t_eff = orc_einstein_t(*e_int, E->n_atoms, E->theta);
-        uint32_t wi[5] = {wb[3], wc[0], wc[1], wc[2], wc[3]};
+        double ui[5] = {u01(wc[0]), u01(wc[1]), uacc * (s + wn) / gn, u01(wc[2]), u01(wc[3])};
         double vo[3], vgo[3], eo;
         int32_t clamped;
-        orc_iict_update(E->m, E->mg, v, vgas, *e_int, t_eff, E->alpha, wi, vo, vgo, &eo, &clamped);
+        orc_iict_update(E->m, E->mg, v, vgas, *e_int, t_eff, E->alpha, ui, vo, vgo, &eo, &clamped);
         v[0] = vo[0]; v[1] = vo[1]; v[2] = vo[2];
         *e_int = eo;
         cnt->n_clamp += clamped;
@@ -942,6 +940,14 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
 }
 
 int64_t orc_num_packs(const orc_sim *s) { return s->n; }
+
+int32_t orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 int64_t orc_current_step(const orc_sim *s) { return s->step; }
 
 int32_t orc_read_packs(const orc_sim *s, orc_packs *o) {

@@ -101,7 +101,7 @@ void orc_poisson(int32_t nr, int32_t nz, double dr, double dz, const double *rho
 double orc_poisson_residual(int32_t nr, int32_t nz, double dr, double dz, const double *rho, const double *phi);
 void orc_rho_from_charge(int32_t nr, int32_t nz, double dr, double dz, const int64_t *q, double *rho);
 void orc_iict_update(double m, double mg, const double v[3], const double vgas[3], double e_int, double t_eff,
-                     double alpha, const uint32_t w[5], double v_out[3], double vgas_out[3], double *e_int_out,
+                     double alpha, const double u[5], double v_out[3], double vgas_out[3], double *e_int_out,
                      int32_t *clamped);
 int32_t orc_collision_probe(double m_da, double ccs, double mg_da, double p, double t_gas, const double u[3],
                             const double v[3], double dt, int64_t n_steps, uint64_t seed, orc_probe *out);
@@ -118,6 +118,7 @@ int32_t orc_set_operating(orc_sim *s, const orc_operating *op);
 int32_t orc_inject(orc_sim *s, int32_t src, int64_t n);
 int32_t orc_step(orc_sim *s, int64_t n_steps);
 int64_t orc_num_packs(const orc_sim *s);
+int32_t orc_num_threads(void);
 int64_t orc_current_step(const orc_sim *s);
 int32_t orc_read_packs(const orc_sim *s, orc_packs *out);
 int32_t orc_write_packs(orc_sim *s, const orc_packs *in);

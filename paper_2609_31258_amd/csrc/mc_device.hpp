@@ -66,18 +66,34 @@ struct P64 {
     static constexpr bool kTwo = false;
     // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double
     static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+    static __device__ __forceinline__ double ln(double x) { return log(x); }
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double exp_(double x) { return exp(x); }
+    static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+    // sin(2 pi u), cos(2 pi u) without a large-argument reduction
+    static __device__ __forceinline__ void sc2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
+    static __device__ __forceinline__ double cos2pi(double u) { return cospi(2.0 * u); }
 };
 
+// FP32 form: the hardware transcendental instructions (v_log_f32 = log2,
+// v_exp_f32 = 2^x, v_sin/cos_f32 take revolutions, v_sqrt_f32, v_rcp_f32).
 struct P32 {
     using T = float;
     static constexpr bool kTwo = true;
     // the top 24 bits of the same word: ((w >> 8) + 1/2) 2^-24, exact in float
     static __device__ __forceinline__ float u01(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 0x1p-24f; }
+    static __device__ __forceinline__ float ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }
+    static __device__ __forceinline__ float log1p_(float x) { return ln(1.0f + x); }
+    static __device__ __forceinline__ void sc2pi(float u, float *s, float *c) {
+        *s = __builtin_amdgcn_sinf(u);
+        *c = __builtin_amdgcn_cosf(u);
+    }
+    static __device__ __forceinline__ float cos2pi(float u) { return __builtin_amdgcn_cosf(u); }
 };
-
-// sin(2 pi u), cos(2 pi u) without a large-argument reduction.
-__device__ __forceinline__ void sincos2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
-__device__ __forceinline__ void sincos2pi(float u, float *s, float *c) { sincospif(2.0f * u, s, c); }
 
 // Error-free sum a + b = s + e (Knuth), for two-float accumulation.
 __device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
@@ -163,17 +179,19 @@ __device__ __forceinline__ Q4<T> gather4(const Tab *tab, const float *sc, const 
 }
 
 // Einstein model inverse: T = theta / ln(1 + s kB theta / U).
-template <class T>
-__device__ __forceinline__ T einstein_t(T e, T skt, T theta) {
-    return e > (T)0 ? theta / log1p(skt / e) : (T)0;
+template <class P>
+__device__ __forceinline__ typename P::T einstein_t(typename P::T e, typename P::T skt, typename P::T theta) {
+    using T = typename P::T;
+    return e > (T)0 ? P::div(theta, P::log1p_(P::div(skt, e))) : (T)0;
 }
 
 // Dissociation rate k(T) = A T^p exp(-B / T): Eyring (p = 1, A = kB/h e^{dS/R},
 // B = dH/R) or Arrhenius (p = 0, A, B = Ea/kB).
-template <class T>
-__device__ __forceinline__ T rate(int32_t kind, T a, T b, T t) {
+template <class P>
+__device__ __forceinline__ typename P::T rate(int32_t kind, typename P::T a, typename P::T b, typename P::T t) {
+    using T = typename P::T;
     if (kind == 0 || !(t > (T)0)) return (T)0;
-    const T e = exp(-b / t);
+    const T e = P::exp_(-P::div(b, t));
     return kind == 1 ? a * t * e : a * e;
 }
 

@@ -99,18 +99,20 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs<P, Tab> a) {
     const W4 wa = draw(id, a.step, kPurposeEmit, 0u, a.k0, a.k1);
     const W4 wb = draw(id, a.step, kPurposeEmit, 1u, a.k0, a.k1);
     const Species sp = a.sp[a.ion];
+    // radius of a Gaussian truncated at r_trunc by inversion, uniform azimuth
     const T sg = (T)a.sigma_r, rt = (T)a.r_trunc;
-    const T r = sg * sqrt((T)-2 * log((T)1 - P::u01(wa.w0) * ((T)1 - exp(-rt * rt / ((T)2 * sg * sg)))));
+    const T r = sg * P::sqrt_((T)-2 * P::ln((T)1 - P::u01(wa.w0) * ((T)1 - P::exp_(-P::div(rt * rt, (T)2 * sg * sg)))));
     T sph, cph;
-    sincos2pi(P::u01(wa.w1), &sph, &cph);
+    P::sc2pi(P::u01(wa.w1), &sph, &cph);
     const T z = (T)a.z_inj;
     const Cell<T> c = locate<T>(r, z, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
     const Q4<T> g = gather4<T>(a.gtab, a.gsc, c, a.nr);
-    const T vth = sqrt((T)kB * g.d / (T)sp.m);
-    const T r1 = sqrt((T)-2 * log(P::u01(wa.w2))), r2 = sqrt((T)-2 * log(P::u01(wb.w0)));
+    // gas flow plus the ion's Maxwellian at the local gas temperature
+    const T vth = P::sqrt_(P::div((T)kB * g.d, (T)sp.m));
+    const T r1 = P::sqrt_((T)-2 * P::ln(P::u01(wa.w2))), r2 = P::sqrt_((T)-2 * P::ln(P::u01(wb.w0)));
     T s1, c1, s2, c2;
-    sincos2pi(P::u01(wa.w3), &s1, &c1);
-    sincos2pi(P::u01(wb.w1), &s2, &c2);
+    P::sc2pi(P::u01(wa.w3), &s1, &c1);
+    P::sc2pi(P::u01(wb.w1), &s2, &c2);
     a.p.x[s] = r * cph;
     a.p.y[s] = r * sph;
     a.p.z[s] = z;
@@ -151,36 +153,34 @@ struct StepArgs {
     uint32_t k0, k1;
 };
 
+// Total field of Eq. 4 at (x, y, z), radial part projected by Eq. 3.
 template <class P, class Tab>
 __device__ __forceinline__ void efield(const StepArgs<P, Tab> &a, typename P::T x, typename P::T y,
                                        typename P::T z, typename P::T c, typename P::T &ex, typename P::T &ey,
                                        typename P::T &ez) {
     using T = typename P::T;
-    const T r = sqrt(x * x + y * y);
+    const T r = P::sqrt_(x * x + y * y);
     const Cell<T> cl = locate<T>(r, z, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
     const Q4<T> q = gather4<T>(a.etab, a.esc, cl, a.nr);
     const T er = q.a + c * q.c;
     ez = q.b + c * q.d;
-    if (r > (T)0) {
-        const T s = er / r;
-        ex = s * x;
-        ey = s * y;
-    } else {
-        ex = (T)0;
-        ey = (T)0;
-    }
+    const T s = r > (T)0 ? P::div(er, r) : (T)0;
+    ex = s * x;
+    ey = s * y;
 }
 
+// Terminal event: int64 tallies (class weights, Eq. 8 exit-current bins,
+// loss map, histograms) and one exit record.
 template <class P, class Tab>
-__device__ __noinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s, int32_t cls, int32_t in, int32_t jn,
-                                         double x, double y, double z, double vx, double vy, double vz, double tc,
-                                         double rc, double eint, double h, const Species &sp) {
+__device__ __forceinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s, int32_t cls, int32_t in,
+                                            int32_t jn, double x, double y, double z, double vx, double vy,
+                                            double vz, double tc, double rc, double eint, double h,
+                                            const Species &sp) {
     const double w = a.p.w[s];
     const int64_t wfx = fx32(w);
     atom_add(&a.t.cnt[TC_CLASS_N + cls], 1);
     atom_add(&a.t.cnt[TC_CLASS_W + cls], wfx);
-    const double v2 = vx * vx + vy * vy + vz * vz;
-    const double ke = 0.5 * sp.m * v2;
+    const double ke = 0.5 * sp.m * (vx * vx + vy * vy + vz * vz);
     const double te = eint > 0.0 ? sp.theta / log1p(sp.skt / eint) : 0.0;
     if (cls == ST_ELECTRODE) atom_add(&a.t.loss_map[(int64_t)jn * a.nr + in], wfx);
     if (cls == ST_TRANSMITTED) {
@@ -193,22 +193,21 @@ __device__ __noinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s, i
     }
     const unsigned long long slot = atomicAdd(&a.t.cnt[TC_EXCOUNT], 1ull);
     if ((int64_t)slot < a.t.exit_cap) {
-        mc_exit_rec r;
-        r.id = a.p.id[s];
-        r.step = a.step;
-        r.cls = cls;
-        r.inode = in;
-        r.jnode = jn;
-        r.tag = a.p.tag[s];
-        r.x = x; r.y = y; r.z = z;
-        r.vx = vx; r.vy = vy; r.vz = vz;
-        r.t_cross = tc;
-        r.r_cross = rc;
-        r.ke_ev = ke / kQe;
-        r.t_eff = te;
-        r.h = h;
-        r.w = w;
-        a.t.exits[slot] = r;
+        mc_exit_rec *r = &a.t.exits[slot];
+        r->id = a.p.id[s];
+        r->step = a.step;
+        r->cls = cls;
+        r->inode = in;
+        r->jnode = jn;
+        r->tag = a.p.tag[s];
+        r->x = x; r->y = y; r->z = z;
+        r->vx = vx; r->vy = vy; r->vz = vz;
+        r->t_cross = tc;
+        r->r_cross = rc;
+        r->ke_ev = ke / kQe;
+        r->t_eff = te;
+        r->h = h;
+        r->w = w;
     } else {
         atom_add(&a.t.cnt[TC_EXDROP], 1);
     }
@@ -230,6 +229,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
             yl = a.p.yl[s];
             zl = a.p.zl[s];
         }
+        const T xl0 = xl, yl0 = yl, zl0 = zl;
         const T vx0 = a.p.vx[s], vy0 = a.p.vy[s], vz0 = a.p.vz[s];
 
         // ---- classical RK4 on (x, v); stages at t, t + dt/2, t + dt/2, t + dt ----
@@ -256,22 +256,17 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
         svx += ax; svy += ay; svz += az;
         const T d6 = dt / (T)6;
         T x1 = x0, y1 = y0, z1 = z0;
-        if constexpr (P::kTwo) {
-            acc2(x1, xl, d6 * sxx);
-            acc2(y1, yl, d6 * sxy);
-            acc2(z1, zl, d6 * sxz);
-        } else {
-            x1 = x0 + d6 * sxx;
-            y1 = y0 + d6 * sxy;
-            z1 = z0 + d6 * sxz;
-        }
+        acc2(x1, xl, d6 * sxx);
+        acc2(y1, yl, d6 * sxy);
+        acc2(z1, zl, d6 * sxz);
         T vx = vx0 + d6 * svx, vy = vy0 + d6 * svy, vz = vz0 + d6 * svz;
-        T e = a.p.e[s], el = P::kTwo ? a.p.el[s] : (T)0;
+        T e = a.p.e[s], el = (T)0;
+        if constexpr (P::kTwo) el = a.p.el[s];
 
         // ---- terminal classification at the new position ----
-        // (FP64 form: the same IEEE operations as any reference; the
-        // two-float form classifies its full-precision position in FP64)
-        const double X0 = (double)x0, Y0 = (double)y0, Zo = (double)z0 + (P::kTwo ? (double)a.p.zl[s] : 0.0);
+        // (the FP64 form performs exactly the IEEE operations of its reference;
+        // the two-float form classifies its full-precision position in FP64)
+        const double X0 = (double)x0 + (double)xl0, Y0 = (double)y0 + (double)yl0, Zo = (double)z0 + (double)zl0;
         const double X1 = (double)x1 + (double)xl, Y1 = (double)y1 + (double)yl, Z1 = (double)z1 + (double)zl;
         int32_t cls = ST_ACTIVE, in = -1, jn = -1;
         double tcross = 0.0, rcross = 0.0;
@@ -282,9 +277,8 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
             cls = ST_NUMERIC;
         } else if (Z1 >= a.z_det || Z1 < 0.0) {
             const double zp = Z1 >= a.z_det ? a.z_det : 0.0;
-            const double XA = X0 + (P::kTwo ? (double)a.p.xl[s] : 0.0), YA = Y0 + (P::kTwo ? (double)a.p.yl[s] : 0.0);
             const double fr = (Z1 != Zo) ? (zp - Zo) / (Z1 - Zo) : 1.0;
-            const double xc = XA + fr * (X1 - XA), yc = YA + fr * (Y1 - YA);
+            const double xc = X0 + fr * (X1 - X0), yc = Y0 + fr * (Y1 - Y0);
             rcross = sqrt(xc * xc + yc * yc);
             tcross = a.t0 + fr * a.dt;
             cls = (Z1 >= a.z_det && rcross <= a.r_det) ? ST_TRANSMITTED : ST_AXIAL;
@@ -304,23 +298,17 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
             const T rr = (T)r1;
             const Cell<T> cl = locate<T>(rr, z1, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
             const Q4<T> g = gather4<T>(a.gtab, a.gsc, cl, a.nr);
-            T ux = 0, uy = 0;
-            if (rr > (T)0) {
-                const T sr = g.a / rr;
-                ux = sr * x1;
-                uy = sr * y1;
-            }
-            const T uz = g.b;
-            const T tg = g.d;
+            const T sr = rr > (T)0 ? P::div(g.a, rr) : (T)0;
+            const T ux = sr * x1, uy = sr * y1, uz = g.b, tg = g.d;
             const T m = (T)sp.m, mg = (T)a.mg;
-            const T ngs = tg > (T)0 ? g.c / ((T)kB * tg) * (T)sp.ccs : (T)0;  // n_gas * sigma
+            const T ngs = tg > (T)0 ? P::div(g.c, (T)kB * tg) * (T)sp.ccs : (T)0;  // n_gas * sigma
             if (ngs > (T)0 && isfinite(ngs)) {
-                const T ag = sqrt((T)kB * tg / mg);
+                const T ag = P::sqrt_(P::div((T)kB * tg, mg));
                 const T abar = ag * (T)1.5957691216057308;  // sqrt(8/pi)
-                const T M = m + mg, fm = mg / M, fi = m / M, mu = mg * fi;  // mu without the m*mg product (FP32 range)
+                const T M = m + mg, fm = P::div(mg, M), fi = P::div(m, M), mu = mg * fi;  // no m*mg product (FP32 range)
                 const T alpha = (T)sp.alpha, skt = (T)sp.skt, theta = (T)sp.theta;
                 T rx = vx - ux, ry = vy - uy, rz = vz - uz;
-                T sv = sqrt(rx * rx + ry * ry + rz * rz);
+                T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
                 T lam = ngs * (sv + abar);
                 // candidate cap; a non-finite rate ends the loop at once
                 const T nexp = lam * dt;
@@ -333,71 +321,59 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
                         break;
                     }
                     const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), a.k0, a.k1);
-                    const T tau = -log(P::u01(wa.w0)) / lam;
+                    const T tau = -P::div(P::ln(P::u01(wa.w0)), lam);
                     if (!(tau < tleft)) break;
                     tleft -= tau;
                     ++ncand;
                     const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), a.k0, a.k1);
-                    T wx, wy, wz, wn;
-                    if (P::u01(wa.w1) < sv / (sv + abar)) {
-                        // Maxwellian partner by Box-Muller
-                        const T q1 = ag * sqrt((T)-2 * log(P::u01(wa.w2)));
-                        const T q2 = ag * sqrt((T)-2 * log(P::u01(wb.w0)));
-                        T s1, c1, s2, c2;
-                        sincos2pi(P::u01(wa.w3), &s1, &c1);
-                        sincos2pi(P::u01(wb.w1), &s2, &c2);
-                        wx = q1 * c1;
-                        wy = q1 * s1;
-                        wz = q2 * c2;
-                        wn = sqrt(wx * wx + wy * wy + wz * wz);
-                    } else {
-                        // flux-weighted partner: |w|^2 / 2 a^2 ~ Gamma(2, 1), isotropic
-                        wn = ag * sqrt((T)-2 * log(P::u01(wa.w2) * P::u01(wa.w3)));
-                        const T ct = (T)2 * P::u01(wb.w0) - (T)1;
-                        const T st = sqrt(fmax((T)0, (T)1 - ct * ct));
-                        T sp_, cp_;
-                        sincos2pi(P::u01(wb.w1), &sp_, &cp_);
-                        wx = wn * st * cp_;
-                        wy = wn * st * sp_;
-                        wz = wn * ct;
-                    }
+                    // partner thermal velocity: E = |w|^2/(2 a^2) ~ Gamma(3/2) (Maxwellian branch)
+                    // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
+                    const bool maxw = P::u01(wa.w1) < P::div(sv, sv + abar);
+                    const T cc = P::cos2pi(P::u01(wb.w0));
+                    const T en = -P::ln(P::u01(wa.w2)) - P::ln(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
+                    const T wn = ag * P::sqrt_((T)2 * en);
+                    const T ct = (T)2 * P::u01(wb.w1) - (T)1;
+                    const T st = P::sqrt_(fmax((T)0, (T)1 - ct * ct));
+                    T sph, cph;
+                    P::sc2pi(P::u01(wb.w2), &sph, &cph);
+                    const T wx = wn * st * cph, wy = wn * st * sph, wz = wn * ct;
                     const T gx = rx - wx, gy = ry - wy, gz = rz - wz;
                     const T g2 = gx * gx + gy * gy + gz * gz;
-                    const T gn = sqrt(g2);
-                    if (!(P::u01(wb.w2) * (sv + wn) < gn)) continue;
+                    const T gn = P::sqrt_(g2);
+                    const T uacc = P::u01(wb.w3);
+                    if (!(uacc * (sv + wn) < gn)) continue;
                     ++nacc;
                     const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), a.k0, a.k1);
                     // centre of mass of the ion and the partner (lab velocity u + w)
                     const T vcx = fi * vx + fm * (ux + wx), vcy = fi * vy + fm * (uy + wy), vcz = fi * vz + fm * (uz + wz);
                     const T et = (T)0.5 * mu * g2;
                     T etp = et;
-                    if (P::u01(wc.w1) < alpha) {
-                        const T te = einstein_t<T>(e + el, skt, theta);
-                        etp = -(T)kB * te * log(P::u01(wc.w2) * P::u01(wc.w3));
+                    // exchange select: the acceptance residual, uniform given acceptance
+                    if (P::div(uacc * (sv + wn), gn) < alpha) {
+                        const T te = einstein_t<P>(e + el, skt, theta);
+                        etp = -(T)kB * te * P::ln(P::u01(wc.w2) * P::u01(wc.w3));
                         const T de = et - etp;
                         if (e + el + de < (T)0) {
                             etp = e + el + et;
                             e = 0;
                             el = 0;
                             ++nclamp;
-                        } else if constexpr (P::kTwo) {
-                            acc2(e, el, de);
                         } else {
-                            e = e + de;
+                            acc2(e, el, de);
                         }
                     }
-                    const T cchi = (T)2 * P::u01(wb.w3) - (T)1;
-                    const T schi = sqrt(fmax((T)0, (T)1 - cchi * cchi));
+                    const T cchi = (T)2 * P::u01(wc.w0) - (T)1;
+                    const T schi = P::sqrt_(fmax((T)0, (T)1 - cchi * cchi));
                     T sps, cps;
-                    sincos2pi(P::u01(wc.w0), &sps, &cps);
-                    const T f = fm * sqrt((T)2 * etp / mu);
+                    P::sc2pi(P::u01(wc.w1), &sps, &cps);
+                    const T f = fm * P::sqrt_(P::div((T)2 * etp, mu));
                     vx = vcx + f * schi * cps;
                     vy = vcy + f * schi * sps;
                     vz = vcz + f * cchi;
                     rx = vx - ux;
                     ry = vy - uy;
                     rz = vz - uz;
-                    sv = sqrt(rx * rx + ry * ry + rz * rz);
+                    sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
                     lam = ngs * (sv + abar);
                 }
             }
@@ -405,15 +381,13 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
 
         if (cls == ST_ACTIVE) {
             // ---- Eq. 7: hazard with the post-collision effective temperature ----
-            const T te = einstein_t<T>(e + el, (T)sp.skt, (T)sp.theta);
-            T h = a.p.h[s] + rate<T>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * dt;
-            a.p.h[s] = h;
+            const T te = einstein_t<P>(e + el, (T)sp.skt, (T)sp.theta);
+            a.p.h[s] = a.p.h[s] + rate<P>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * dt;
             a.p.e[s] = e;
             if constexpr (P::kTwo) a.p.el[s] = el;
         } else {
-            const double E = (double)e + (double)el;
-            record_exit(a, s, cls, in, jn, X1, Y1, Z1, (double)vx, (double)vy, (double)vz, tcross, rcross, E,
-                        (double)a.p.h[s], sp);
+            record_exit(a, s, cls, in, jn, X1, Y1, Z1, (double)vx, (double)vy, (double)vz, tcross, rcross,
+                        (double)e + (double)el, (double)a.p.h[s], sp);
             a.p.status[s] = cls;
         }
         a.p.x[s] = x1;
@@ -454,36 +428,70 @@ struct DepositArgs {
     int32_t nr, nz;
 };
 
+// Block-local aggregation: each block sums its packs' node contributions in
+// an LDS hash table (open addressing) and flushes one global atomic per
+// distinct node.  Packs concentrate in a few cells near the source, so this
+// removes almost all contention on the global grid; integer sums make the
+// result independent of the order.
+constexpr int kDepHash = 2048;
+
+__device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
+                                           int32_t node, int64_t v) {
+    if (v == 0) return;
+    uint32_t h = ((uint32_t)node * 2654435761u) >> (32 - 11);
+    for (int probe = 0; probe < 8; ++probe) {
+        const int32_t old = atomicCAS(&keys[h], -1, node);
+        if (old == -1 || old == node) {
+            atomicAdd(&vals[h], (unsigned long long)v);
+            return;
+        }
+        h = (h + 1) & (kDepHash - 1);
+    }
+    atom_add(&grid[node], v);  // table crowded: go straight to the grid
+}
+
 template <class P>
 __global__ __launch_bounds__(256) void k_deposit(DepositArgs<typename P::T> a) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= a.n_slots || a.p.status[s] != ST_ACTIVE) return;
-    double X = a.p.x[s], Y = a.p.y[s], Z = a.p.z[s];
-    if constexpr (P::kTwo) {
-        X += (double)a.p.xl[s];
-        Y += (double)a.p.yl[s];
-        Z += (double)a.p.zl[s];
+    __shared__ int32_t keys[kDepHash];
+    __shared__ unsigned long long vals[kDepHash];
+    for (int k = threadIdx.x; k < kDepHash; k += blockDim.x) {
+        keys[k] = -1;
+        vals[k] = 0ull;
     }
-    if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) return;
-    const double r = sqrt(X * X + Y * Y);
-    const double ur = r * a.inv_dr, uz = Z * a.inv_dz;
-    double fi = floor(ur), fj = floor(uz);
-    if (fi > (double)(a.nr - 2)) fi = (double)(a.nr - 2);
-    if (fj > (double)(a.nz - 2)) fj = (double)(a.nz - 2);
-    if (fj < 0.0) fj = 0.0;
-    double f = ur - fi, g = uz - fj;
-    if (f > 1.0) f = 1.0;
-    if (g > 1.0) g = 1.0;
-    if (g < 0.0) g = 0.0;
-    const int64_t Q = a.p.q[s];
-    const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
-    const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
-    const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
-    const int64_t k = (int64_t)fj * a.nr + (int64_t)fi;
-    atom_add(&a.q[k], a0);
-    atom_add(&a.q[k + a.nr], a1);
-    atom_add(&a.q[k + 1], b0);
-    atom_add(&a.q[k + a.nr + 1], b1);
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_slots; s += stride) {
+        if (a.p.status[s] != ST_ACTIVE) continue;
+        double X = a.p.x[s], Y = a.p.y[s], Z = a.p.z[s];
+        if constexpr (P::kTwo) {
+            X += (double)a.p.xl[s];
+            Y += (double)a.p.yl[s];
+            Z += (double)a.p.zl[s];
+        }
+        if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) continue;
+        const double r = sqrt(X * X + Y * Y);
+        const double ur = r * a.inv_dr, uz = Z * a.inv_dz;
+        double fi = floor(ur), fj = floor(uz);
+        if (fi > (double)(a.nr - 2)) fi = (double)(a.nr - 2);
+        if (fj > (double)(a.nz - 2)) fj = (double)(a.nz - 2);
+        if (fj < 0.0) fj = 0.0;
+        double f = ur - fi, g = uz - fj;
+        if (f > 1.0) f = 1.0;
+        if (g > 1.0) g = 1.0;
+        if (g < 0.0) g = 0.0;
+        const int64_t Q = a.p.q[s];
+        const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
+        const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
+        const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
+        const int32_t k = (int32_t)fj * a.nr + (int32_t)fi;
+        dep_insert(keys, vals, a.q, k, a0);
+        dep_insert(keys, vals, a.q, k + a.nr, a1);
+        dep_insert(keys, vals, a.q, k + 1, b0);
+        dep_insert(keys, vals, a.q, k + a.nr + 1, b1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < kDepHash; k += blockDim.x)
+        if (keys[k] >= 0 && vals[k] != 0ull) atomicAdd(&a.q[keys[k]], vals[k]);
 }
 
 // ---------------------------------------------------------------------------
@@ -687,9 +695,14 @@ __global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *
                                                   unsigned long long *act, unsigned long long *hke,
                                                   unsigned long long *hte, double *partial) {
     __shared__ double red[3][256];
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ unsigned long long lke[MC_HIST_KE], lte[MC_HIST_TEFF], lact[2];
+    for (int k = threadIdx.x; k < MC_HIST_KE; k += blockDim.x) lke[k] = 0ull;
+    for (int k = threadIdx.x; k < MC_HIST_TEFF; k += blockDim.x) lte[k] = 0ull;
+    if (threadIdx.x < 2) lact[threadIdx.x] = 0ull;
+    __syncthreads();
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    if (s < n_slots) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_slots; s += stride) {
         const Species S = sp[p.tag[s]];
         const double w = p.w[s];
         const double e = (double)p.e[s] + (p.el ? (double)p.el[s] : 0.0);
@@ -698,14 +711,14 @@ __global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *
             const double ke = 0.5 * S.m * (vx * vx + vy * vy + vz * vz);
             const double te = e > 0.0 ? S.theta / log1p(S.skt / e) : 0.0;
             const int64_t wfx = fx32(w);
-            atom_add(&act[0], 1);
-            atom_add(&act[1], wfx);
-            atom_add(&hke[hbin_ke(ke / kQe)], wfx);
-            atom_add(&hte[hbin_teff(te)], wfx);
-            a0 = w * ke;
-            a1 = w * e;
+            atomicAdd(&lact[0], 1ull);
+            atomicAdd(&lact[1], (unsigned long long)wfx);
+            atomicAdd(&lke[hbin_ke(ke / kQe)], (unsigned long long)wfx);
+            atomicAdd(&lte[hbin_teff(te)], (unsigned long long)wfx);
+            a0 += w * ke;
+            a1 += w * e;
         } else {
-            a2 = w * (-expm1(-(double)p.h[s]));
+            a2 += w * (-expm1(-(double)p.h[s]));
         }
     }
     red[0][threadIdx.x] = a0;
@@ -725,6 +738,11 @@ __global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *
         partial[3 * (int64_t)blockIdx.x + 1] = red[1][0];
         partial[3 * (int64_t)blockIdx.x + 2] = red[2][0];
     }
+    for (int k = threadIdx.x; k < MC_HIST_KE; k += blockDim.x)
+        if (lke[k]) atomicAdd(&hke[k], lke[k]);
+    for (int k = threadIdx.x; k < MC_HIST_TEFF; k += blockDim.x)
+        if (lte[k]) atomicAdd(&hte[k], lte[k]);
+    if (threadIdx.x < 2 && lact[threadIdx.x]) atomicAdd(&act[threadIdx.x], lact[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, int64_t nb, double *out) {

@@ -22,6 +22,9 @@ using namespace mc;
 namespace {
 
 constexpr int kBlock = 256;
+// blocks of the grid-stride aggregation kernels (deposit, snapshot): a few
+// per CU, so each block's LDS table absorbs many packs
+constexpr int64_t kAggBlocks = 1024;
 
 struct Src {
     mc_source in;
@@ -367,7 +370,8 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
             a.inv_dz = ctx->inv_dz;
             a.nr = ctx->nr;
             a.nz = ctx->nz;
-            k_deposit<P><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a);
+            const unsigned nb = (unsigned)std::min<int64_t>(grid_for(ctx->n_slots), kAggBlocks);
+            k_deposit<P><<<nb, kBlock, 0, ctx->stream>>>(a);
             LAUNCHCHK();
         }
     }
@@ -403,7 +407,7 @@ static int32_t snapshot_t(mc_ctx *ctx, PackPtrs<T> p) {
     Timer t(ctx, MC_K_TALLY);
     k_zero_u64<<<grid_for(ns), kBlock, 0, ctx->stream>>>(ctx->snap, ns);
     LAUNCHCHK();
-    const int64_t nb = std::max<int64_t>(1, (ctx->n_slots + kBlock - 1) / kBlock);
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((ctx->n_slots + kBlock - 1) / kBlock, kAggBlocks));
     if (ctx->n_slots > 0) {
         k_snapshot<T><<<(unsigned)nb, kBlock, 0, ctx->stream>>>(p, ctx->sp_dev, ctx->n_slots, ctx->snap,
                                                                ctx->snap + 2, ctx->snap + 2 + MC_HIST_KE, ctx->partial);

@@ -276,8 +276,8 @@ def test_iict_update_conserves_momentum_and_energy():
             v = rng.normal(0, 300, 3)
             vg = rng.normal(0, 300, 3)
             e_int = rng.uniform(1e-20, 1e-18)
-            words = rng.integers(0, 2 ** 32, 5, dtype=np.uint64).astype(np.uint32)
-            vo, vgo, eo, cl = O.iict_update(m, mg, v, vg, e_int, 450.0, alpha, words)
+            uni = rng.uniform(0, 1, 5)
+            vo, vgo, eo, cl = O.iict_update(m, mg, v, vg, e_int, 450.0, alpha, uni)
             assert np.allclose(m * vo + mg * vgo, m * v + mg * vg, rtol=1e-12, atol=1e-30)
             ke0 = 0.5 * m * v @ v + 0.5 * mg * vg @ vg + e_int
             ke1 = 0.5 * m * vo @ vo + 0.5 * mg * vgo @ vgo + eo
