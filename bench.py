@@ -87,6 +87,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packs", type=int, default=400_000)
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--serving-queries", type=int, default=256)
+    ap.add_argument("--serving-rate", type=float, default=20.0)
+    ap.add_argument("--serving-steps", type=int, default=2000)
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -174,6 +179,59 @@ def cpu_baseline(n_packs: int, n_steps: int):
             "collisions_per_s": T["n_coll"] / wall}
 
 
+def serving_query(f, q, steps: int):
+    """One design query of the serving workload: emission over the first half of
+    the horizon at the query's current, space charge every 10 steps."""
+    from paper_2609_31258_amd import synth
+    ion = synth.Ion(q["mass_da"], q["charge_z"], q["ccs_m2"], max(3, q["n_atoms"]), act_kind=1, act_p1=100e3,
+                    act_p2=-80.0)
+    pps = max(1, int(round(q["n_packs"] / (steps // 2))))
+    src = synth.Source(kind=1, current_a=q["current_a"], packs_per_step=pps, n_total=q["n_packs"], sigma_r=1e-4,
+                       r_trunc=3e-4)
+    op = synth.Operating(dt=0.5e-9, v_rf=q["v_rf"], f_rf=1e6, v_off=q["v_off"], sc_on=1, sc_every=10,
+                         z_det=f.grid.L, r_det=f.grid.R, exit_bin_dt=1e-7, n_exit_bins=100)
+    return ion, src, op
+
+
+def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budget_gib: float, max_resident: int):
+    """Poisson arrivals of design queries into one server (shared 256x1024 field
+    set, FP32 form); latency = completion - submission on the server clock."""
+    from paper_2609_31258_amd import mucite, synth
+    f = synth.ring_fields(256, 1024)
+    qs = synth.serving_queries(n_queries, rate_hz=rate_hz)
+    srv = mucite.Server(f, hbm_budget=int(budget_gib * (1 << 30)), precision=precision, max_resident=max_resident,
+                        steps_per_sync=20)
+    t0 = time.perf_counter()
+    ids = []
+    for k, q in enumerate(qs):
+        delay = q["arrival_s"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        ion, src, op = serving_query(f, q, steps)
+        ids.append(srv.submit(ion, src, op, n_steps=steps, seed=q["seed"]))
+        if (k + 1) % 64 == 0:
+            print(f"[bench] serving submitted {k + 1}/{n_queries}", file=sys.stderr, flush=True)
+    res = []
+    for k, i in enumerate(ids):
+        res.append(srv.wait(i, 3600.0))
+        if (k + 1) % 64 == 0:
+            print(f"[bench] serving completed {k + 1}/{n_queries} ({time.perf_counter() - t0:.1f} s)",
+                  file=sys.stderr, flush=True)
+    st = srv.stats()
+    srv.close()
+    lat = [r["t_done"] - r["t_submit"] for r in res if r["state"] == mucite.Q_DONE]
+    lat.sort()
+    pct = lambda p: lat[min(len(lat) - 1, int(math.ceil(p * len(lat))) - 1)] if lat else None
+    span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
+    ps = sum(r["tallies"]["pack_steps"] for r in res if r["state"] == mucite.Q_DONE)
+    return {"queries": n_queries, "completed": len(lat), "arrival_rate_hz": rate_hz, "steps_per_query": steps,
+            "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "mean_latency_s": sum(lat) / len(lat),
+            "throughput_pack_steps_per_s": ps / span, "pack_steps": ps, "span_s": span,
+            "offered_load": (ps / (ps / st["busy_s"])) / (qs[-1]["arrival_s"] + 1e-9) if st["busy_s"] > 0 else None,
+            "max_resident_seen": st["max_resident_seen"], "pool_peak_bytes": st["pool_peak"],
+            "dtype": "f32 (BF16 tables)" if precision == 1 else "f64"}
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -219,6 +277,9 @@ def main():
                             "ms_per_step": q["wall"] * 1e3 / args.steps, "dtype": "f32 (BF16 tables)",
                             "speedup_vs_fp64": (q["pack_steps"] / q["wall"]) / value,
                             "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"]}
+    if not args.no_serving:
+        out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
+                                     args.serving_budget_gib, 64)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_packs, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -254,6 +254,86 @@ int32_t mc_read_hit(mc_ctx *ctx, uint8_t *hit);
 int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out);
 int32_t mc_reset_timing(mc_ctx *ctx);
 
+/* ------------------------------------------------------------------------- */
+/* Serving: continuous batching of design queries over shared field tables.   */
+/*                                                                           */
+/* A server owns one field set (grid, potentials, gas, mask, hit distance and */
+/* gas species shared by all queries) and a device pool of hbm_budget bytes.  */
+/* Each query is a complete simulation (its own ion, source, operating point, */
+/* seed, step count): its packs, space-charge grids, folded field table and   */
+/* tallies stay resident in one pool block from admission to completion.     */
+/* A worker thread admits pending queries in arrival order while their block  */
+/* fits in the pool and fewer than max_resident are resident, advances every  */
+/* resident query by one step per co-step (one launch of the step kernel for  */
+/* all of them; emission likewise; space-charge updates per query), and      */
+/* retires finished queries into host results.  A query's arithmetic does   */
+/* not depend on which others share its launches: its result is the same     */
+/* alone and in any mix.  submit/poll/wait/stats are thread-safe.            */
+/* ------------------------------------------------------------------------- */
+typedef struct mc_server_options {
+    int32_t precision;       /* MC_PREC_FP64 or MC_PREC_FP32 */
+    int32_t device;
+    int64_t hbm_budget;      /* bytes of the query pool (> 0) */
+    int32_t max_resident;    /* queries co-stepped at once, 1..4096 */
+    int32_t steps_per_sync;  /* co-steps enqueued between host synchronisations, >= 1 */
+    void *stream;            /* hipStream_t, NULL = server-owned */
+    mc_alloc_fn alloc;       /* optional allocator for the pool and shared tables */
+    mc_free_fn free;
+    void *alloc_user;
+    int32_t fp32_tables;     /* FP32 form: FP32 instead of BF16 field tables */
+    int32_t reserved;
+    double d_hit;            /* electrode hit distance shared by all queries [m] */
+    double gas_mass_da;      /* gas molecule mass shared by all queries [Da] */
+} mc_server_options;
+
+/* A design query.  source.ion is ignored (the query's own ion); op.d_hit and
+ * op.gas_mass_da are ignored (the server's).  kind 0 sources emit n_total
+ * packs at the query's first step.  exit_capacity: exit records kept (0 = none). */
+typedef struct mc_query {
+    mc_ion ion;
+    mc_source source;
+    mc_operating op;
+    int64_t n_steps;
+    uint64_t seed;
+    int64_t exit_capacity;
+} mc_query;
+
+enum { MC_Q_PENDING = 0, MC_Q_RUNNING = 1, MC_Q_DONE = 2, MC_Q_FAILED = 3 };
+
+/* Result of a query.  Before polling, set the tally array pointers you want
+ * (sizes as for mc_read_tallies with the query's n_exit_bins) or NULL.
+ * Times are seconds on the server clock (0 at creation). */
+typedef struct mc_query_result {
+    int32_t state, error;
+    double t_submit, t_admit, t_done;
+    int64_t device_bytes;
+    mc_tallies tallies;
+} mc_query_result;
+
+typedef struct mc_server_stats {
+    int64_t submitted, admitted, completed, failed, resident, pending;
+    int64_t pool_bytes, pool_in_use, pool_peak, shared_bytes;
+    int64_t co_steps, pack_steps, max_resident_seen;
+    double busy_s, wall_s;
+} mc_server_stats;
+
+typedef struct mc_server mc_server;
+
+int32_t mc_server_create(const mc_server_options *options, const mc_grid *grid, const mc_field_tables *tables,
+                         mc_server **out);
+/* Stop the worker (resident and pending queries are abandoned) and free everything. */
+void mc_server_destroy(mc_server *server);
+const char *mc_server_last_error(const mc_server *server);
+/* Queue a query; *qid receives its id.  MC_EBUDGET if its memory exceeds the pool. */
+int32_t mc_server_submit(mc_server *server, const mc_query *query, uint64_t *qid);
+/* Copy the query's state and, once done, its result.  MC_EINVAL for an unknown id. */
+int32_t mc_server_poll(mc_server *server, uint64_t qid, mc_query_result *out);
+/* Block until the query is done (or failed) or timeout_s passes, then poll. */
+int32_t mc_server_wait(mc_server *server, uint64_t qid, double timeout_s, mc_query_result *out);
+/* Forget a finished query's host result. */
+int32_t mc_server_release(mc_server *server, uint64_t qid);
+int32_t mc_server_get_stats(mc_server *server, mc_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

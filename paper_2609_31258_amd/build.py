@@ -2,7 +2,8 @@
 
     python -m paper_2609_31258_amd.build
 
-compiles csrc/mc_runtime.hip (which includes the kernels) with hipcc into
+compiles csrc/mc_runtime.hip (single simulations) and csrc/mc_server.hip (serving),
+which include the kernels, with hipcc into
 paper_2609_31258_amd/libmucite.so.  Flags: -O3, IEEE floating point without
 contraction (-ffp-contract=off: index arithmetic of classification and
 deposit is reproducible), packed FP32 instructions disabled.
@@ -14,7 +15,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmucite.so")
-SOURCES = [os.path.join(HERE, "csrc", "mc_runtime.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "mc_runtime.hip"), os.path.join(HERE, "csrc", "mc_server.hip")]
 ARCH = os.environ.get("MUCITE_ARCH", "gfx950")
 
 

@@ -91,10 +91,8 @@ struct EmitArgs {
 };
 
 template <class P, class Tab>
-__global__ __launch_bounds__(256) void k_emit(EmitArgs<P, Tab> a) {
+__device__ __forceinline__ void emit_one(const EmitArgs<P, Tab> &a, int64_t k) {
     using T = typename P::T;
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.count) return;
     const int64_t id = a.id0 + k, s = a.slot0 + k;
     const W4 wa = draw(id, a.step, kPurposeEmit, 0u, a.k0, a.k1);
     const W4 wb = draw(id, a.step, kPurposeEmit, 1u, a.k0, a.k1);
@@ -133,6 +131,34 @@ __global__ __launch_bounds__(256) void k_emit(EmitArgs<P, Tab> a) {
     a.p.q[s] = a.q;
     a.p.tag[s] = a.ion;
     a.p.status[s] = ST_ACTIVE;
+}
+
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_emit(EmitArgs<P, Tab> a) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < a.count) emit_one(a, k);
+}
+
+// Query owning a block in a multi-query launch: prefix[q] is the first block of
+// query q, prefix[nq] the total (uniform per block, so this is scalar code).
+__device__ __forceinline__ int block_query(const int32_t *prefix, int32_t nq) {
+    int lo = 0, hi = nq - 1;
+    const int b = (int)blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_emit_multi(const EmitArgs<P, Tab> *descs, const int32_t *prefix,
+                                                    int32_t nq) {
+    const int q = block_query(prefix, nq);
+    const EmitArgs<P, Tab> &a = descs[q];
+    const int64_t k = (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x;
+    if (k < a.count) emit_one(a, k);
 }
 
 // ---------------------------------------------------------------------------
@@ -213,13 +239,17 @@ __device__ __forceinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s
     }
 }
 
+struct StepCount {
+    uint64_t cand, acc, cap, clamp, act;
+};
+
+// One pack, one step.
 template <class P, class Tab>
-__global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
+__device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n) {
     using T = typename P::T;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nact = 0;
+    uint64_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0;
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
-        nact = 1;
+        n.act = 1;
         const Species sp = a.sp[a.p.tag[s]];
         const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
         const T x0 = a.p.x[s], y0 = a.p.y[s], z0 = a.p.z[s];
@@ -402,16 +432,42 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
         a.p.vy[s] = vy;
         a.p.vz[s] = vz;
     }
-    // wavefront-aggregated counters
-    const uint64_t sc = wave_sum_u64(ncand), sa = wave_sum_u64(nacc);
-    const uint64_t sp_ = wave_sum_u64(ncap), sl = wave_sum_u64(nclamp), sn = wave_sum_u64(nact);
+    n.cand = ncand;
+    n.acc = nacc;
+    n.cap = ncap;
+    n.clamp = nclamp;
+}
+
+// Wavefront-aggregated counters (every lane of the block's query calls this).
+__device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount &n) {
+    const uint64_t sc = wave_sum_u64(n.cand), sa = wave_sum_u64(n.acc);
+    const uint64_t sp_ = wave_sum_u64(n.cap), sl = wave_sum_u64(n.clamp), sn = wave_sum_u64(n.act);
     if ((threadIdx.x & 63) == 0) {
-        if (sn) atomicAdd(&a.t.cnt[TC_PACKSTEPS], (unsigned long long)sn);
-        if (sc) atomicAdd(&a.t.cnt[TC_CAND], (unsigned long long)sc);
-        if (sa) atomicAdd(&a.t.cnt[TC_COLL], (unsigned long long)sa);
-        if (sp_) atomicAdd(&a.t.cnt[TC_CAP], (unsigned long long)sp_);
-        if (sl) atomicAdd(&a.t.cnt[TC_CLAMP], (unsigned long long)sl);
+        if (sn) atomicAdd(&t.cnt[TC_PACKSTEPS], (unsigned long long)sn);
+        if (sc) atomicAdd(&t.cnt[TC_CAND], (unsigned long long)sc);
+        if (sa) atomicAdd(&t.cnt[TC_COLL], (unsigned long long)sa);
+        if (sp_) atomicAdd(&t.cnt[TC_CAP], (unsigned long long)sp_);
+        if (sl) atomicAdd(&t.cnt[TC_CLAMP], (unsigned long long)sl);
     }
+}
+
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
+    StepCount n{0, 0, 0, 0, 0};
+    step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n);
+    flush_counts(a.t, n);
+}
+
+// All resident queries of a server advance one step in one launch; each
+// block belongs to one query (descriptors in device memory).
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_step_multi(const StepArgs<P, Tab> *descs, const int32_t *prefix,
+                                                    int32_t nq) {
+    const int q = block_query(prefix, nq);
+    const StepArgs<P, Tab> &a = descs[q];
+    StepCount n{0, 0, 0, 0, 0};
+    step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n);
+    flush_counts(a.t, n);
 }
 
 // ---------------------------------------------------------------------------
@@ -528,7 +584,7 @@ __global__ __launch_bounds__(256) void k_dst_rows(const unsigned long long *q, c
 // Tridiagonal coefficients per (row i, mode k): cp = up / den, inv = 1 / den,
 // den_i = diag_i(k) - lo_i cp_{i-1}; diag = -(lo + up) + lambda_k,
 // lambda_k = -(4/dz^2) sin^2(pi k / (2 (nz-1))).
-__global__ __launch_bounds__(256) void k_thomas_coef(double *cp, double *inv, int32_t nr, int32_t nz, double dr,
+static __global__ __launch_bounds__(256) void k_thomas_coef(double *cp, double *inv, int32_t nr, int32_t nz, double dr,
                                                      double dz) {
     const int32_t m = nz - 2, nu = nr - 1;
     const int32_t k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
@@ -603,7 +659,7 @@ __global__ __launch_bounds__(256) void k_idst_rows(const D *ph, const double *si
 
 // E = -grad(phi) on nodes: central differences, one-sided at the outer
 // edges, E_r = 0 on the axis.
-__global__ __launch_bounds__(256) void k_bake(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
+static __global__ __launch_bounds__(256) void k_bake(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
                                               double dz) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)nr * nz) return;
@@ -658,7 +714,7 @@ __global__ __launch_bounds__(256) void k_gas(Tab *gtab, const double *ur, const 
 }
 
 // Electrode hit table: metal node, or a metal node within d_hit + h/2.
-__global__ __launch_bounds__(256) void k_hit(const uint8_t *mask, uint8_t *hit, int32_t nr, int32_t nz, double dr,
+static __global__ __launch_bounds__(256) void k_hit(const uint8_t *mask, uint8_t *hit, int32_t nr, int32_t nz, double dr,
                                              double dz, double reach, int32_t wi, int32_t wj) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)nr * nz) return;
@@ -745,7 +801,7 @@ __global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *
     if (threadIdx.x < 2 && lact[threadIdx.x]) atomicAdd(&act[threadIdx.x], lact[threadIdx.x]);
 }
 
-__global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, int64_t nb, double *out) {
+static __global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, int64_t nb, double *out) {
     __shared__ double red[3][256];
     double a[3] = {0.0, 0.0, 0.0};
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
@@ -762,12 +818,12 @@ __global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, 
 }
 
 // Small utilities.
-__global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
+static __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k < n) p[k] = 0ull;
 }
 
-__global__ __launch_bounds__(256) void k_sine_table(double *s, int32_t nz) {
+static __global__ __launch_bounds__(256) void k_sine_table(double *s, int32_t nz) {
     const int32_t n2 = 2 * (nz - 1);
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q < n2) s[q] = sin(kPi * (double)q / (double)(nz - 1));

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "mc_host.hpp"
 #include "mc_kernels.hpp"
 
 using namespace mc;
@@ -26,18 +27,11 @@ constexpr int kBlock = 256;
 // per CU, so each block's LDS table absorbs many packs
 constexpr int64_t kAggBlocks = 1024;
 
-struct Src {
-    mc_source in;
-    double w;
-    int64_t w_fx, q_fx, n_real_fx, acc_fx, emitted;
-};
-
 struct EvPair {
     hipEvent_t a, b;
     int kind;
 };
 
-inline int64_t fx32_host(double v) { return (int64_t)std::llrint(std::ldexp(v, 32)); }
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -217,12 +211,7 @@ static int32_t upload_species(mc_ctx *ctx) {
     return MC_OK;
 }
 
-static void species_alpha(mc_ctx *ctx, size_t k) {
-    const mc_ion &in = ctx->ions[k];
-    Species &S = ctx->sp_host[k];
-    const double mg = ctx->op.gas_mass_da * kDa, ma = S.m / in.n_atoms;
-    S.alpha = in.alpha >= 0.0 ? in.alpha : 4.0 * mg * ma / ((mg + ma) * (mg + ma));
-}
+static void ctx_alpha(mc_ctx *ctx, size_t k) { species_alpha(ctx->sp_host[k], ctx->ions[k], ctx->op.gas_mass_da); }
 
 // ---------------------------------------------------------------------------
 // Kernels launches.
@@ -291,22 +280,6 @@ static int32_t emit(mc_ctx *ctx, int si, int64_t count) {
     return MC_OK;
 }
 
-// Eq. 5 source accumulator in integer units of 2^-32 real ions.
-static int64_t due(Src &S, int64_t step) {
-    if (step < S.in.step_start || S.in.kind == 0) return 0;
-    const int64_t left = S.in.n_total - S.emitted;
-    if (left <= 0) return 0;
-    int64_t k;
-    if (S.in.kind == 1) {
-        k = S.in.packs_per_step;
-    } else {
-        S.acc_fx += S.n_real_fx;
-        k = S.w_fx > 0 ? S.acc_fx / S.w_fx : 0;
-        S.acc_fx -= k * S.w_fx;
-    }
-    return std::min(k, left);
-}
-
 template <class P, class Tab>
 static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     if (ctx->n_slots == 0) return MC_OK;
@@ -323,11 +296,11 @@ static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     a.step = ctx->step;
     const mc_operating &op = ctx->op;
     a.dt = op.dt;
-    a.t0 = (double)ctx->step * op.dt;
-    const double w2 = 2.0 * kPi * op.f_rf, t0 = a.t0;
-    a.c0 = op.v_rf * std::cos(w2 * t0 + op.phase_rf);
-    a.ch = op.v_rf * std::cos(w2 * (t0 + 0.5 * op.dt) + op.phase_rf);
-    a.c1 = op.v_rf * std::cos(w2 * (t0 + op.dt) + op.phase_rf);
+    double c[3];
+    rf_stages(op, ctx->step, &a.t0, c);
+    a.c0 = c[0];
+    a.ch = c[1];
+    a.c1 = c[2];
     a.z_det = op.z_det;
     a.r_det = op.r_det;
     a.R = ctx->R;
@@ -616,38 +589,14 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     return MC_OK;
 }
 
-static Species make_species(const mc_ion *in) {
-    Species S{};
-    S.m = in->mass_da * kDa;
-    S.qm = in->charge_z * kQe / S.m;
-    S.ccs = in->ccs_m2;
-    S.theta = in->theta_e;
-    S.skt = (3.0 * in->n_atoms - 6.0) * kB * in->theta_e;
-    S.e0 = in->t_eff0 > 0.0 ? S.skt / std::expm1(in->theta_e / in->t_eff0) : 0.0;
-    S.n_atoms = in->n_atoms;
-    S.act_kind = in->act_kind;
-    const double R = kNA * kB;
-    if (in->act_kind == 1) {
-        S.act_a = kB / kH * std::exp(in->act_p2 / R);
-        S.act_b = in->act_p1 / R;
-    } else if (in->act_kind == 2) {
-        S.act_a = in->act_p1;
-        S.act_b = in->act_p2 * kQe / kB;
-    }
-    S.alpha = in->alpha;
-    return S;
-}
-
 int32_t mc_define_ion(mc_ctx *ctx, const mc_ion *ion, int32_t *ion_id) {
     if (!ctx) return MC_EINVAL;
-    if (!ion || ion->n_atoms < 3 || !(ion->mass_da > 0) || ion->charge_z == 0 || !(ion->ccs_m2 >= 0) ||
-        !(ion->theta_e > 0) || ion->act_kind < 0 || ion->act_kind > 2)
-        return fail(ctx, MC_EINVAL, "invalid ion template");
+    if (!valid_ion(ion)) return fail(ctx, MC_EINVAL, "invalid ion template");
     if (ctx->ions.size() >= 64) return fail(ctx, MC_ENOMEM, "at most 64 ion templates");
     ctx->ions.push_back(*ion);
     ctx->sp_host.push_back(make_species(ion));
     ctx->charge_host.push_back(ion->charge_z);
-    if (ctx->has_op) species_alpha(ctx, ctx->ions.size() - 1);
+    if (ctx->has_op) ctx_alpha(ctx, ctx->ions.size() - 1);
     if (ion_id) *ion_id = (int32_t)ctx->ions.size() - 1;
     return upload_species(ctx);
 }
@@ -664,7 +613,7 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
         return fail(ctx, MC_ESTATE, "the number of exit bins is fixed by the first operating point");
     ctx->op = *op;
     ctx->has_op = true;
-    for (size_t k = 0; k < ctx->ions.size(); ++k) species_alpha(ctx, k);
+    for (size_t k = 0; k < ctx->ions.size(); ++k) ctx_alpha(ctx, k);
     int32_t rc = upload_species(ctx);
     if (rc) return rc;
     const int64_t nn = (int64_t)ctx->nr * ctx->nz;
@@ -705,15 +654,7 @@ int32_t mc_define_source(mc_ctx *ctx, const mc_source *src, int32_t *src_id) {
         (src->kind == 1 && src->packs_per_step <= 0) || (src->kind != 1 && !(src->weight > 0)))
         return fail(ctx, MC_EINVAL, "invalid source");
     if (ctx->srcs.size() >= 1024) return fail(ctx, MC_ENOMEM, "too many sources");
-    Src S{};
-    S.in = *src;
-    const double z = (double)ctx->ions[src->ion].charge_z;
-    const double n_real = src->current_a * ctx->op.dt / (z * kQe);
-    S.w = src->kind == 1 ? n_real / (double)src->packs_per_step : src->weight;
-    S.w_fx = fx32_host(S.w);
-    S.q_fx = fx32_host(z * S.w);
-    S.n_real_fx = fx32_host(n_real);
-    ctx->srcs.push_back(S);
+    ctx->srcs.push_back(make_source(*src, ctx->ions[src->ion].charge_z, ctx->op.dt));
     if (src_id) *src_id = (int32_t)ctx->srcs.size() - 1;
     return MC_OK;
 }

@@ -93,6 +93,31 @@ class Timing(C.Structure):
     _fields_ = [("ms", F64 * 6), ("launches", I64 * 6), ("pack_steps", I64)]
 
 
+class ServerOptions(C.Structure):
+    _fields_ = [("precision", I32), ("device", I32), ("hbm_budget", I64), ("max_resident", I32),
+                ("steps_per_sync", I32), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
+                ("alloc_user", C.c_void_p), ("fp32_tables", I32), ("reserved", I32), ("d_hit", F64),
+                ("gas_mass_da", F64)]
+
+
+class Query(C.Structure):
+    _fields_ = [("ion", Ion), ("source", Source), ("op", Operating), ("n_steps", I64), ("seed", U64),
+                ("exit_capacity", I64)]
+
+
+class QueryResult(C.Structure):
+    _fields_ = [("state", I32), ("error", I32), ("t_submit", F64), ("t_admit", F64), ("t_done", F64),
+                ("device_bytes", I64), ("tallies", Tallies)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(f, I64) for f in ("submitted", "admitted", "completed", "failed", "resident", "pending",
+                                   "pool_bytes", "pool_in_use", "pool_peak", "shared_bytes", "co_steps",
+                                   "pack_steps", "max_resident_seen")] + [("busy_s", F64), ("wall_s", F64)]
+
+
+Q_PENDING, Q_RUNNING, Q_DONE, Q_FAILED = 0, 1, 2, 3
+
 EXIT_DTYPE = np.dtype([(f, np.int64 if t is I64 else (np.int32 if t is I32 else np.float64))
                        for f, t in ExitRec._fields_])
 assert EXIT_DTYPE.itemsize == C.sizeof(ExitRec)
@@ -120,6 +145,15 @@ _SIGS = {
     "mc_read_hit": (I32, [C.c_void_p, PU8]),
     "mc_read_timing": (I32, [C.c_void_p, C.POINTER(Timing)]),
     "mc_reset_timing": (I32, [C.c_void_p]),
+    "mc_server_create": (I32, [C.POINTER(ServerOptions), C.POINTER(Grid), C.POINTER(FieldTables),
+                               C.POINTER(C.c_void_p)]),
+    "mc_server_destroy": (None, [C.c_void_p]),
+    "mc_server_last_error": (C.c_char_p, [C.c_void_p]),
+    "mc_server_submit": (I32, [C.c_void_p, C.POINTER(Query), C.POINTER(U64)]),
+    "mc_server_poll": (I32, [C.c_void_p, U64, C.POINTER(QueryResult)]),
+    "mc_server_wait": (I32, [C.c_void_p, U64, F64, C.POINTER(QueryResult)]),
+    "mc_server_release": (I32, [C.c_void_p, U64]),
+    "mc_server_get_stats": (I32, [C.c_void_p, C.POINTER(ServerStats)]),
 }
 
 _LIB = None
@@ -367,6 +401,116 @@ class Sim:
 
     def reset_timing(self) -> None:
         self._chk(self.L.mc_reset_timing(self._h), "mc_reset_timing")
+
+
+def _tally_buffers(nz: int, nr: int, n_exit_bins: int):
+    return dict(exit_bins=np.zeros(n_exit_bins, np.int64), loss_map=np.zeros((nz, nr), np.int64),
+                hist_ke=np.zeros(HIST_KE, np.int64), hist_teff=np.zeros(HIST_TEFF, np.int64),
+                hist_r=np.zeros(HIST_R, np.int64), act_hist_ke=np.zeros(HIST_KE, np.int64),
+                act_hist_teff=np.zeros(HIST_TEFF, np.int64))
+
+
+class Server:
+    """Continuous-batching server of design queries over one field set."""
+
+    def __init__(self, fields, *, hbm_budget: int, precision: int = PREC_FP32, max_resident: int = 64,
+                 steps_per_sync: int = 20, d_hit: float = 1e-5, gas_mass_da: float = 28.0134, device: int = 0,
+                 fp32_tables: bool = False, use_torch: bool = True):
+        self.L = load_library()
+        self._mem = _TorchMemory(device) if use_torch else None
+        o = ServerOptions()
+        o.precision = precision
+        o.device = device
+        o.hbm_budget = hbm_budget
+        o.max_resident = max_resident
+        o.steps_per_sync = steps_per_sync
+        o.fp32_tables = int(fp32_tables)
+        o.d_hit = d_hit
+        o.gas_mass_da = gas_mass_da
+        if self._mem is not None:
+            o.stream = self._mem.stream.cuda_stream
+            o.alloc = self._mem.alloc_cb
+            o.free = self._mem.free_cb
+        g = fields.grid
+        self.nr, self.nz = g.nr, g.nz
+        arrs = [_f64(a) for a in (fields.phi_dc, fields.phi_off, fields.phi_rf, fields.gas_ur, fields.gas_uz,
+                                  fields.gas_p, fields.gas_t)]
+        mask = np.ascontiguousarray(fields.mask, dtype=np.uint8)
+        t = FieldTables(*[_p(a, F64) for a in arrs], _p(mask, C.c_uint8))
+        self._h = C.c_void_p()
+        rc = self.L.mc_server_create(C.byref(o), C.byref(Grid(g.nr, g.nz, g.dr, g.dz)), C.byref(t),
+                                     C.byref(self._h))
+        if rc != MC_OK:
+            raise MucateError(rc, "mc_server_create", "server creation failed")
+        self._bins: Dict[int, int] = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self.L.mc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, rc, where):
+        if rc != MC_OK:
+            raise MucateError(rc, where, (self.L.mc_server_last_error(self._h) or b"").decode())
+
+    def submit(self, ion, source, op, n_steps: int, seed: int, exit_capacity: int = 0) -> int:
+        q = Query()
+        q.ion = _struct(Ion, ion)
+        q.source = _struct(Source, source)
+        q.op = _struct(Operating, op)
+        q.n_steps = n_steps
+        q.seed = seed
+        q.exit_capacity = exit_capacity
+        out = U64()
+        self._chk(self.L.mc_server_submit(self._h, C.byref(q), C.byref(out)), "mc_server_submit")
+        self._bins[out.value] = op.n_exit_bins
+        return out.value
+
+    def _result(self, qid: int, fn, *args):
+        r = QueryResult()
+        bufs = _tally_buffers(self.nz, self.nr, self._bins.get(qid, 1))
+        for k, a in bufs.items():
+            setattr(r.tallies, k, _p(a, I64))
+        self._chk(fn(self._h, qid, *args, C.byref(r)), fn.__name__)
+        out = dict(state=r.state, error=r.error, t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done,
+                   device_bytes=r.device_bytes)
+        if r.state == Q_DONE:
+            T = r.tallies
+            tal = dict(bufs)
+            for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "pack_steps",
+                      "exit_overflow", "exit_dropped", "sum_w_ke_active", "sum_w_eint_active",
+                      "sum_w_dissoc_terminal"):
+                tal[k] = getattr(T, k)
+            tal["class_n"] = np.array(list(T.class_n), np.int64)
+            tal["class_w"] = np.array(list(T.class_w), np.int64)
+            out["tallies"] = tal
+        return out
+
+    def poll(self, qid: int) -> Dict[str, object]:
+        return self._result(qid, self.L.mc_server_poll)
+
+    def wait(self, qid: int, timeout_s: float = 600.0) -> Dict[str, object]:
+        return self._result(qid, self.L.mc_server_wait, F64(timeout_s))
+
+    def release(self, qid: int) -> None:
+        self._chk(self.L.mc_server_release(self._h, qid), "mc_server_release")
+
+    def stats(self) -> Dict[str, float]:
+        st = ServerStats()
+        self._chk(self.L.mc_server_get_stats(self._h, C.byref(st)), "mc_server_get_stats")
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
 
 
 def declared_symbols(header: str = HEADER):

@@ -35,9 +35,25 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
     assert got == want
 
 
+def test_serving_struct_layouts_match_the_header(tmp_path):
+    src = tmp_path / "sz2.c"
+    src.write_text('#include "mucite.h"\n#include <stdio.h>\n'
+                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(mc_server_options), sizeof(mc_query), '
+                   'sizeof(mc_query_result), sizeof(mc_server_stats));return 0;}\n')
+    inc = os.path.join(os.path.dirname(mucite.HERE), "include")
+    exe = tmp_path / "sz2"
+    subprocess.run(["gcc", "-I" + inc, str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [C.sizeof(s) for s in (mucite.ServerOptions, mucite.Query, mucite.QueryResult, mucite.ServerStats)]
+    assert got == want
+
+
 def test_null_arguments_are_rejected_without_a_device():
     L = mucite.load_library()
     assert L.mc_create(None, None) == mucite.MC_EINVAL
     assert L.mc_step(None, 1) == mucite.MC_EINVAL
     assert L.mc_read_tallies(None, None) == mucite.MC_EINVAL
     L.mc_destroy(None)
+    assert L.mc_server_submit(None, None, None) == mucite.MC_EINVAL
+    assert L.mc_server_poll(None, 1, None) == mucite.MC_EINVAL
+    L.mc_server_destroy(None)
