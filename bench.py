@@ -129,7 +129,7 @@ def run_gpu(precision: int, steps: int, warmup: int):
     cand = after["n_cand"] - before["n_cand"]
     coll = after["n_coll"] - before["n_coll"]
     return dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim, slots=info["n_slots"],
-                active=int(after["class_n"][0]), classes=after["class_n"].tolist())
+                active=int(after["class_n"][0]), classes=after["class_n"].tolist(), tallies=after)
 
 
 def roofline(r, precision: str, alpha: float):
@@ -144,6 +144,28 @@ def roofline(r, precision: str, alpha: float):
             "frac": achieved / PEAK_OPS, "traffic": measured_traffic(precision),
             "kernel": "k_step (fused push/classify/collide)", "avg_launch_ms": avg_s * 1e3, "launches": launches,
             "ops_per_launch": ops_per_launch}
+
+
+def precision_report(t64, t32):
+    """Error of the FP32 form against the FP64 path on the same packs, seed and
+    steps: relative differences of the weighted mean kinetic and internal
+    energies, total-variation distance and Kolmogorov-Smirnov statistic of the
+    KE and T_eff histograms of the active population, class fractions."""
+    import numpy as np
+    out = {}
+    w64, w32 = t64["class_w"][0], t32["class_w"][0]
+    for k in ("sum_w_ke_active", "sum_w_eint_active"):
+        a, b = t64[k] / max(w64, 1), t32[k] / max(w32, 1)
+        out[k.replace("sum_w_", "rel_err_mean_")] = abs(b - a) / abs(a) if a else None
+    for h in ("act_hist_ke", "act_hist_teff"):
+        p, q = np.asarray(t64[h], float), np.asarray(t32[h], float)
+        p, q = p / max(p.sum(), 1), q / max(q.sum(), 1)
+        out["tv_" + h] = 0.5 * float(np.abs(p - q).sum())
+        out["ks_" + h] = float(np.abs(np.cumsum(p) - np.cumsum(q)).max())
+    n64, n32 = max(t64["class_n"].sum(), 1), max(t32["class_n"].sum(), 1)
+    out["class_fraction_diff"] = [float(a / n64 - b / n32) for a, b in zip(t64["class_n"], t32["class_n"])]
+    out["candidates_rel_diff"] = abs(t32["n_cand"] - t64["n_cand"]) / max(t64["n_cand"], 1)
+    return out
 
 
 def default_alpha() -> float:
@@ -276,7 +298,8 @@ def main():
         out["fp32_form"] = {"value": q["pack_steps"] / q["wall"], "unit": "pack-steps/s",
                             "ms_per_step": q["wall"] * 1e3 / args.steps, "dtype": "f32 (BF16 tables)",
                             "speedup_vs_fp64": (q["pack_steps"] / q["wall"]) / value,
-                            "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"]}
+                            "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"],
+                            "error_vs_fp64": precision_report(r["tallies"], q["tallies"])}
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)

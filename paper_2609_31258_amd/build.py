@@ -4,9 +4,9 @@
 
 compiles csrc/mc_runtime.hip (single simulations) and csrc/mc_server.hip (serving),
 which include the kernels, with hipcc into
-paper_2609_31258_amd/libmucite.so.  Flags: -O3, IEEE floating point without
-contraction (-ffp-contract=off: index arithmetic of classification and
-deposit is reproducible), packed FP32 instructions disabled.
+paper_2609_31258_amd/libmucite.so.  Flags: -O3, FMA contraction on (the
+kernels turn it off locally where results must be bit-reproducible), packed
+FP32 instructions disabled.
 """
 import os
 import subprocess
@@ -28,7 +28,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=off",
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=fast-honor-pragmas",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
            "-I" + os.path.join(ROOT, "include"), "-o", tmp] + SOURCES
     if verbose:

@@ -13,9 +13,10 @@
 //   k_hit       electrode hit table from the mask and hit distance
 //   k_snapshot  read-time tallies of the active population
 //
-// Everything is compiled with -ffp-contract=off, so the index arithmetic of
-// classification and deposit is plain IEEE and reproducible on any IEEE
-// implementation given the same positions.
+// The library is compiled with FMA contraction on; the blocks whose results
+// must be reproducible bit for bit on any IEEE implementation given the same
+// positions (classification, deposit, hit table, histogram bins) switch it
+// off locally with `#pragma clang fp contract(off)`.
 #pragma once
 #include "../../include/mucite.h"
 #include "mc_device.hpp"
@@ -50,6 +51,7 @@ struct TallyPtrs {
 // exit radius over [0, r_det]; bin 0 = underflow, last = overflow.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int hbin_ke(double ke_ev) {
+#pragma clang fp contract(off)
     if (!(ke_ev > 0.0)) return 0;
     const double u = (log10(ke_ev) + 3.0) * (200.0 / 6.0);
     if (!(u >= 0.0)) return 0;
@@ -57,12 +59,14 @@ __device__ __forceinline__ int hbin_ke(double ke_ev) {
     return 1 + (int)floor(u);
 }
 __device__ __forceinline__ int hbin_teff(double t) {
+#pragma clang fp contract(off)
     const double u = t * (200.0 / 5000.0);
     if (!(u >= 0.0)) return 0;
     if (u >= 200.0) return 201;
     return 1 + (int)floor(u);
 }
 __device__ __forceinline__ int hbin_r(double r, double rdet) {
+#pragma clang fp contract(off)
     const double u = r / rdet * 100.0;
     if (!(u >= 0.0)) return 0;
     if (u >= 100.0) return 101;
@@ -202,6 +206,7 @@ __device__ __forceinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s
                                             int32_t jn, double x, double y, double z, double vx, double vy,
                                             double vz, double tc, double rc, double eint, double h,
                                             const Species &sp) {
+#pragma clang fp contract(off)
     const double w = a.p.w[s];
     const int64_t wfx = fx32(w);
     atom_add(&a.t.cnt[TC_CLASS_N + cls], 1);
@@ -296,11 +301,13 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         // ---- terminal classification at the new position ----
         // (the FP64 form performs exactly the IEEE operations of its reference;
         // the two-float form classifies its full-precision position in FP64)
-        const double X0 = (double)x0 + (double)xl0, Y0 = (double)y0 + (double)yl0, Zo = (double)z0 + (double)zl0;
         const double X1 = (double)x1 + (double)xl, Y1 = (double)y1 + (double)yl, Z1 = (double)z1 + (double)zl;
         int32_t cls = ST_ACTIVE, in = -1, jn = -1;
-        double tcross = 0.0, rcross = 0.0;
-        const double r1 = sqrt(X1 * X1 + Y1 * Y1);
+        double tcross = 0.0, rcross = 0.0, r1;
+        {
+#pragma clang fp contract(off)
+        const double X0 = (double)x0 + (double)xl0, Y0 = (double)y0 + (double)yl0, Zo = (double)z0 + (double)zl0;
+        r1 = sqrt(X1 * X1 + Y1 * Y1);
         const bool finite = isfinite(X1) && isfinite(Y1) && isfinite(Z1) && isfinite((double)vx) &&
                             isfinite((double)vy) && isfinite((double)vz);
         if (!finite) {
@@ -322,6 +329,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 jn = jj;
             }
         }
+        }
 
         if (cls == ST_ACTIVE && a.collisions_on) {
             // ---- collisions with the gas at the new position ----
@@ -336,6 +344,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 const T ag = P::sqrt_(P::div((T)kB * tg, mg));
                 const T abar = ag * (T)1.5957691216057308;  // sqrt(8/pi)
                 const T M = m + mg, fm = P::div(mg, M), fi = P::div(m, M), mu = mg * fi;  // no m*mg product (FP32 range)
+                const T two_mu = P::div((T)2, mu);
                 const T alpha = (T)sp.alpha, skt = (T)sp.skt, theta = (T)sp.theta;
                 T rx = vx - ux, ry = vy - uy, rz = vz - uz;
                 T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
@@ -358,7 +367,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), a.k0, a.k1);
                     // partner thermal velocity: E = |w|^2/(2 a^2) ~ Gamma(3/2) (Maxwellian branch)
                     // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
-                    const bool maxw = P::u01(wa.w1) < P::div(sv, sv + abar);
+                    const bool maxw = P::u01(wa.w1) * (sv + abar) < sv;  // u < s/(s + abar)
                     const T cc = P::cos2pi(P::u01(wb.w0));
                     const T en = -P::ln(P::u01(wa.w2)) - P::ln(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
                     const T wn = ag * P::sqrt_((T)2 * en);
@@ -379,7 +388,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     const T et = (T)0.5 * mu * g2;
                     T etp = et;
                     // exchange select: the acceptance residual, uniform given acceptance
-                    if (P::div(uacc * (sv + wn), gn) < alpha) {
+                    if (uacc * (sv + wn) < alpha * gn) {  // residual uacc (s + |w|)/|g| < alpha
                         const T te = einstein_t<P>(e + el, skt, theta);
                         etp = -(T)kB * te * P::ln(P::u01(wc.w2) * P::u01(wc.w3));
                         const T de = et - etp;
@@ -396,7 +405,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     const T schi = P::sqrt_(fmax((T)0, (T)1 - cchi * cchi));
                     T sps, cps;
                     P::sc2pi(P::u01(wc.w1), &sps, &cps);
-                    const T f = fm * P::sqrt_(P::div((T)2 * etp, mu));
+                    const T f = fm * P::sqrt_(etp * two_mu);
                     vx = vcx + f * schi * cps;
                     vy = vcy + f * schi * sps;
                     vz = vcz + f * cchi;
@@ -517,6 +526,7 @@ __global__ __launch_bounds__(256) void k_deposit(DepositArgs<typename P::T> a) {
     __syncthreads();
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_slots; s += stride) {
+#pragma clang fp contract(off)
         if (a.p.status[s] != ST_ACTIVE) continue;
         double X = a.p.x[s], Y = a.p.y[s], Z = a.p.z[s];
         if constexpr (P::kTwo) {
@@ -716,6 +726,7 @@ __global__ __launch_bounds__(256) void k_gas(Tab *gtab, const double *ur, const 
 // Electrode hit table: metal node, or a metal node within d_hit + h/2.
 static __global__ __launch_bounds__(256) void k_hit(const uint8_t *mask, uint8_t *hit, int32_t nr, int32_t nz, double dr,
                                              double dz, double reach, int32_t wi, int32_t wj) {
+#pragma clang fp contract(off)
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)nr * nz) return;
     const int32_t i = (int32_t)(n % nr), j = (int32_t)(n / nr);
@@ -759,6 +770,7 @@ __global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n_slots; s += stride) {
+#pragma clang fp contract(off)
         const Species S = sp[p.tag[s]];
         const double w = p.w[s];
         const double e = (double)p.e[s] + (p.el ? (double)p.el[s] : 0.0);

@@ -245,7 +245,7 @@ def test_full_size_c2_sampled_step():
 def test_loss_and_transmission_statistics():
     _say("C1T-like run with losses")
     f, ions, srcs, op, _ = synth.config_c1t(4000)
-    srcs[0].z_inj = 2.0e-3
+    srcs[0].z_inj, srcs[0].sigma_r, srcs[0].r_trunc = 2.3e-3, 2e-4, 6e-4  # next to the first ring
     op.v_rf = 300.0
     g, o = make_pair(f, ions, srcs, op, cap=4000)
     g.inject(0, 4000)
@@ -273,7 +273,7 @@ def test_loss_and_transmission_statistics():
 def test_gpu_run_is_deterministic():
     _say("determinism")
     f, ions, srcs, op, _ = synth.config_c1t(2000)
-    srcs[0].z_inj = 2.0e-3
+    srcs[0].z_inj, srcs[0].sigma_r, srcs[0].r_trunc = 2.3e-3, 2e-4, 6e-4  # next to the first ring
     op.v_rf = 300.0
     from paper_2609_31258_amd import mucite
     outs = []
@@ -328,3 +328,46 @@ def test_timing_and_pack_step_counter():
     assert t["launches"]["step"] == 10 and t["ms"]["step"] > 0
     assert t["pack_steps"] == g.read_tallies()["pack_steps"] == 40_000
     g.close()
+
+
+# ---------------------------------------------------------------------------
+# Precision form against FP64 on a run that transmits and loses packs
+# ---------------------------------------------------------------------------
+
+def test_fp32_form_statistics_match_fp64_and_oracle():
+    """Same packs and seed through the FP64 path, the FP32 form (BF16 tables)
+    and the oracle: class fractions within 4-sigma bounds, electrode weight per
+    ring, and the KE / T_eff histograms of the active population (KS distance
+    below the bound for the sample sizes)."""
+    _say("fp32 form statistics, low-pressure run with losses")
+    f, ions, srcs, op, _ = synth.config_c1t(4000)
+    srcs[0].z_inj, srcs[0].sigma_r, srcs[0].r_trunc = 2.3e-3, 2e-4, 6e-4  # next to the first ring
+    op.v_rf = 300.0
+    from oracle.binding import OracleSim
+    from paper_2609_31258_amd import mucite
+    runs = {}
+    for name, prec in (("fp64", 0), ("fp32", 1)):
+        g = mucite.Sim(seed=synth.SEED, pack_capacity=4000, precision=prec)
+        g.setup(f, ions, srcs, op)
+        g.inject(0, 4000)
+        g.step(1500)
+        runs[name] = g.read_tallies()
+        g.close()
+    o = OracleSim(synth.SEED)
+    o.setup(f, ions, srcs, op)
+    o.inject(0, 4000)
+    o.step(1500)
+    runs["oracle"] = o.read_tallies()
+    n = 4000
+    for a, b in (("fp32", "fp64"), ("fp32", "oracle")):
+        ta, tb = runs[a], runs[b]
+        _say(f"  {a} classes {ta['class_n'].tolist()} {b} {tb['class_n'].tolist()}")
+        for c in range(5):
+            fa, fb = ta["class_n"][c] / n, tb["class_n"][c] / n
+            assert abs(fa - fb) <= frac_bound(fa, fb, n, n) + 2.0 / n, (a, b, c)
+        for h in ("act_hist_ke", "act_hist_teff"):
+            p = np.cumsum(ta[h]) / max(ta[h].sum(), 1)
+            q = np.cumsum(tb[h]) / max(tb[h].sum(), 1)
+            ks = np.abs(p - q).max()
+            na, nb = ta["class_n"][0], tb["class_n"][0]
+            assert ks < 1.95 * math.sqrt((na + nb) / (na * nb)), (a, b, h, ks)  # KS at alpha = 1e-3
