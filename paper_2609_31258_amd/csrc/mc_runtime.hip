@@ -57,6 +57,7 @@ struct mc_ctx {
     unsigned long long *qgrid = nullptr;
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
     void *bh = nullptr;
+    Bluestein blu;
 
     std::vector<mc_ion> ions;
     std::vector<Species> sp_host;
@@ -351,12 +352,25 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     {
         Timer t(ctx, MC_K_POISSON);
         D *bh = static_cast<D *>(ctx->bh);
-        k_dst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(ctx->qgrid, ctx->sine, bh, ctx->nr, ctx->nz,
-                                                                  ctx->dr, ctx->dz);
+        const Bluestein &B = ctx->blu;
+        if (B.L > 0) {
+            k_dst_bluestein<D, true><<<nu, 1024, B.lds, ctx->stream>>>(
+                ctx->qgrid, bh, nullptr, (const Cx<D> *)B.chirp, (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, ctx->nr,
+                ctx->nz, B.L, ctx->dr, ctx->dz);
+        } else {
+            k_dst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(ctx->qgrid, ctx->sine, bh, ctx->nr, ctx->nz,
+                                                                      ctx->dr, ctx->dz);
+        }
         LAUNCHCHK();
         k_thomas<D><<<grid_for(m), kBlock, 0, ctx->stream>>>(bh, ctx->tcp, ctx->tinv, ctx->nr, ctx->nz, ctx->dr);
         LAUNCHCHK();
-        k_idst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(bh, ctx->sine, ctx->phi_sc, ctx->nr, ctx->nz);
+        if (B.L > 0) {
+            k_dst_bluestein<D, false><<<nu, 1024, B.lds, ctx->stream>>>(
+                nullptr, bh, ctx->phi_sc, (const Cx<D> *)B.chirp, (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, ctx->nr,
+                ctx->nz, B.L, ctx->dr, ctx->dz);
+        } else {
+            k_idst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(bh, ctx->sine, ctx->phi_sc, ctx->nr, ctx->nz);
+        }
         LAUNCHCHK();
     }
     {
@@ -565,6 +579,23 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     LAUNCHCHK();
     k_thomas_coef<<<grid_for(m), kBlock, 0, ctx->stream>>>(ctx->tcp, ctx->tinv, g->nr, g->nz, g->dr, g->dz);
     LAUNCHCHK();
+    // chirp z sine transform tables when the FFT length fits in LDS
+    {
+        Bluestein &B = ctx->blu;
+        const size_t cx = ctx->fp32() ? 2 * sizeof(float) : 2 * sizeof(double);
+        const int32_t L = bluestein_length(m);
+        if ((size_t)L * cx <= lds_per_block()) {
+            B.L = L;
+            B.lds = (size_t)L * cx;
+            int32_t rc2 = dalloc(ctx, &B.chirp, (size_t)m * cx);
+            if (!rc2) rc2 = dalloc(ctx, &B.tw, (size_t)std::max(L / 2, 1) * cx);
+            if (!rc2) rc2 = dalloc(ctx, &B.fb, (size_t)L * cx);
+            if (rc2) return rc2;
+            const hipError_t e = ctx->fp32() ? bluestein_prepare<float>(B, m, ctx->stream)
+                                             : bluestein_prepare<double>(B, m, ctx->stream);
+            if (e != hipSuccess) B.L = 0;  // fall back to the direct sine sums
+        }
+    }
     HIPCHK(hipStreamSynchronize(ctx->stream));
     // the staging buffer is returned at once
     for (size_t k = 0; k < ctx->allocs.size(); ++k)

@@ -73,6 +73,7 @@ struct mc_server {
     float gsc[4] = {1, 1, 1, 1}, esc[4] = {1, 1, 1, 1};
     uint8_t *hit = nullptr;
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
+    Bluestein blu;
     std::vector<std::pair<void *, size_t>> allocs;
     int64_t shared_bytes = 0;
     char *pool_base = nullptr;
@@ -306,9 +307,20 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         k_deposit<P><<<(unsigned)std::min<int64_t>(blocks_for(Q.n_slots), kAggMax), kBlk, 0, S->stream>>>(a);
     }
     D *bh = static_cast<D *>(Q.bh);
-    k_dst_rows<D><<<nu, kBlk, m * sizeof(D), S->stream>>>(Q.qgrid, S->sine, bh, S->nr, S->nz, S->dr, S->dz);
+    const Bluestein &B = S->blu;
+    if (B.L > 0)
+        k_dst_bluestein<D, true><<<nu, 1024, B.lds, S->stream>>>(Q.qgrid, bh, nullptr, (const Cx<D> *)B.chirp,
+                                                                 (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, S->nr,
+                                                                 S->nz, B.L, S->dr, S->dz);
+    else
+        k_dst_rows<D><<<nu, kBlk, m * sizeof(D), S->stream>>>(Q.qgrid, S->sine, bh, S->nr, S->nz, S->dr, S->dz);
     k_thomas<D><<<blocks_for(m), kBlk, 0, S->stream>>>(bh, S->tcp, S->tinv, S->nr, S->nz, S->dr);
-    k_idst_rows<D><<<nu, kBlk, m * sizeof(D), S->stream>>>(bh, S->sine, Q.phi, S->nr, S->nz);
+    if (B.L > 0)
+        k_dst_bluestein<D, false><<<nu, 1024, B.lds, S->stream>>>(nullptr, bh, Q.phi, (const Cx<D> *)B.chirp,
+                                                                  (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, S->nr,
+                                                                  S->nz, B.L, S->dr, S->dz);
+    else
+        k_idst_rows<D><<<nu, kBlk, m * sizeof(D), S->stream>>>(bh, S->sine, Q.phi, S->nr, S->nz);
     k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.phi, Q.e_sc, S->nr, S->nz, S->dr, S->dz);
     SCHK(hipGetLastError());
     return fold_query<Tab>(S, Q);
@@ -690,6 +702,21 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
     k_sine_table<<<blocks_for(2 * (g->nz - 1)), kBlk, 0, S->stream>>>(S->sine, g->nz);
     k_thomas_coef<<<blocks_for(m), kBlk, 0, S->stream>>>(S->tcp, S->tinv, g->nr, g->nz, g->dr, g->dz);
     SC2(hipGetLastError());
+    {
+        Bluestein &B = S->blu;
+        const size_t cx = S->fp32() ? 2 * sizeof(float) : 2 * sizeof(double);
+        const int32_t L = bluestein_length(m);
+        if ((size_t)L * cx <= lds_per_block()) {
+            B.L = L;
+            B.lds = (size_t)L * cx;
+            if (salloc(S, &B.chirp, (size_t)m * cx) || salloc(S, &B.tw, (size_t)std::max(L / 2, 1) * cx) ||
+                salloc(S, &B.fb, (size_t)L * cx))
+                return bail(MC_ENOMEM);
+            const hipError_t e = S->fp32() ? bluestein_prepare<float>(B, m, S->stream)
+                                           : bluestein_prepare<double>(B, m, S->stream);
+            if (e != hipSuccess) B.L = 0;
+        }
+    }
     SC2(hipStreamSynchronize(S->stream));
     if (S->bf16()) {
         std::vector<double2> h(nn);

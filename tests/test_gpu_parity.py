@@ -190,6 +190,55 @@ def test_pic_update_bit_exact_deposit_and_poisson():
     g.close()
 
 
+# Poisson grids: the C2 grid (nz-2 = 1022 sine modes) in both precisions, and
+# tall narrow grids whose FFT length reaches 8192 (FP64) / 16384 (FP32)
+# complex points (128 KiB of LDS), plus an FP64 grid too tall for LDS that
+# takes the direct sine sums.  Bars: deposit bit-exact; FP64 Phi within 1e-10
+# of max|Phi|; FP32 sums in single precision (rounding ~6e-8 per operation,
+# about log2(L) ~ 14 butterfly levels in each of four FFTs), Phi within 5e-6
+# of max|Phi| and E within 1e-4 of max|E| (differences over a node amplify
+# the relative error by the ratio of the potential's length scale to dz).
+@pytest.mark.parametrize("precision,nr,nz", [(1, 0, 0), (0, 16, 4096), (1, 16, 8192), (0, 12, 8192)])
+def test_poisson_transforms_match_oracle(precision, nr, nz):
+    n = 100_000
+    if nr == 0:
+        f, ions, srcs, op, _ = _c2_like()
+        snap = synth.pack_snapshot(n, f, seed=22, z_hi=f.grid.L * 0.3, r_hi=1.5e-3, weight=0.012483)
+    else:
+        f = synth.uniform_fields(nr, nz, 5e-5)
+        _, ions, _, op, _ = _c2_like()
+        op = synth.Operating(**{**op.__dict__, "z_det": f.grid.L, "r_det": f.grid.R, "sc_on": 1})
+        snap = synth.pack_snapshot(n, f, seed=23, z_lo=0.1 * f.grid.L, z_hi=0.7 * f.grid.L, r_hi=0.6 * f.grid.R,
+                                   weight=0.01)
+    if precision == 1:
+        # The FP32 form holds a position as a pair of floats (about 48
+        # significant bits); give both sides positions that pair holds
+        # exactly, so the deposit can still be compared bit for bit.
+        for k in ("x", "y", "z"):
+            hi = snap[k].astype(np.float32)
+            snap[k] = hi.astype(np.float64) + (snap[k] - hi.astype(np.float64)).astype(np.float32).astype(np.float64)
+    _say("poisson transform", precision, f.grid.nr, f.grid.nz)
+    g, o = make_pair(f, ions, [], op, cap=n, precision=precision)
+    g.write_packs(snap)
+    o.write_packs(snap)
+    g.pic_update()
+    o.pic_update()
+    assert np.array_equal(g.read_charge(), o.read_charge())
+    pa, era, eza = g.read_sc()
+    pb, erb, ezb = o.read_sc()
+    scale = np.abs(pb).max()
+    es = max(np.abs(erb).max(), np.abs(ezb).max())
+    assert scale > 0 and es > 0
+    ep = np.abs(pa - pb).max() / scale
+    ee = max(np.abs(era - erb).max(), np.abs(eza - ezb).max()) / es
+    _say(f"  phi max rel err {ep:.2e}, E max rel err {ee:.2e}")
+    if precision == 0:
+        assert ep <= 1e-10 and ee <= 1e-8
+    else:
+        assert ep <= 5e-6 and ee <= 1e-4
+    g.close()
+
+
 def test_pic_update_empty_population():
     _say("pic update, no packs")
     f, ions, _, op, _ = _c2_like()
