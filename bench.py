@@ -92,6 +92,12 @@ def parse():
     ap.add_argument("--serving-steps", type=int, default=2000)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--large", action="store_true",
+                    help="also time a window of the large configuration (1024x8192 grid, 1.6e7 packs of ten "
+                         "species, FP32 form) at full occupancy")
+    ap.add_argument("--large-fill-steps", type=int, default=10_000,
+                    help="steps over which the large configuration emits its packs before the timed window")
+    ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -130,6 +136,49 @@ def run_gpu(precision: int, steps: int, warmup: int):
     coll = after["n_coll"] - before["n_coll"]
     return dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim, slots=info["n_slots"],
                 active=int(after["class_n"][0]), classes=after["class_n"].tolist(), tallies=after)
+
+
+def run_large(fill_steps: int, steps: int, n_packs: int = 16_000_000):
+    """The large configuration in the FP32 form: emission of all packs over
+    fill_steps steps (untimed), then a timed window of `steps` steps at full
+    occupancy with space charge every 5 steps."""
+    import torch
+    from paper_2609_31258_amd import mucite, synth
+    f, ions, srcs, op, meta = synth.config_c5(n_packs=n_packs, emit_steps=fill_steps)
+    sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=1, timing=True)
+    sim.setup(f, ions, srcs, op)
+    t0 = time.time()
+    done = 0
+    while done < fill_steps:
+        k = min(500, fill_steps - done)
+        sim.step(k)
+        sim.synchronize()
+        done += k
+        print(f"[bench] large fill {done}/{fill_steps} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+    sim.reset_timing()
+    before = sim.read_tallies()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    t2 = time.perf_counter()
+    after = sim.read_tallies()
+    tim = sim.read_timing()
+    sim.close()
+    wall = t2 - t1
+    ps = after["pack_steps"] - before["pack_steps"]
+    coll = after["n_coll"] - before["n_coll"]
+    cand = after["n_cand"] - before["n_cand"]
+    alpha = sum(4 * synth.M_N2_DA * (i.mass_da / i.n_atoms) / (synth.M_N2_DA + i.mass_da / i.n_atoms) ** 2
+                for i in ions) / len(ions)
+    r = dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim)
+    return {"workload": "1024x8192 grid, 1.6e7 packs of ten species (200-5e4 Da, Arrhenius), 50 nA, "
+                        "SC every 5 steps, dt=0.25 ns, FP32 form (BF16 tables)",
+            "fill_steps": fill_steps, "steps": steps, "value": ps / wall, "unit": "pack-steps/s",
+            "ms_per_step": wall * 1e3 / steps, "active": int(after["class_n"][0]),
+            "classes": after["class_n"].tolist(), "collisions_per_s": coll / wall,
+            "candidates_per_pack_step": cand / max(ps, 1), "kernel_ms": tim["ms"],
+            "roofline": roofline(r, "none", alpha)}
 
 
 def roofline(r, precision: str, alpha: float):
@@ -303,6 +352,8 @@ def main():
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)
+    if args.large:
+        out["large"] = run_large(args.large_fill_steps, args.large_steps)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_packs, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -98,6 +98,7 @@ def lib():
         "orc_read_sc": (I32, [C.c_void_p, PD, PD, PD]),
         "orc_read_hit": (I32, [C.c_void_p, PU8]),
         "orc_pic_update": (I32, [C.c_void_p]),
+        "orc_deposit": (I32, [C.c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -269,6 +270,9 @@ class OracleSim:
 
     def pic_update(self):
         self._chk(lib().orc_pic_update(self._h), "pic_update")
+
+    def deposit(self):
+        self._chk(lib().orc_deposit(self._h), "deposit")
 
     @property
     def n_packs(self) -> int:

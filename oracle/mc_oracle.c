@@ -794,6 +794,12 @@ static void deposit(orc_sim *s) {
     }
 }
 
+/* The deposit alone (charge grid only; the potential is left as it was).   */
+int32_t orc_deposit(orc_sim *s) {
+    deposit(s);
+    return 0;
+}
+
 int32_t orc_pic_update(orc_sim *s) {
     size_t nn = (size_t)s->nr * s->nz;
     deposit(s);

@@ -128,6 +128,8 @@ int32_t orc_read_charge(const orc_sim *s, int64_t *q);
 int32_t orc_read_sc(const orc_sim *s, double *phi, double *er, double *ez);
 int32_t orc_read_hit(const orc_sim *s, uint8_t *hit);
 int32_t orc_pic_update(orc_sim *s);
+/* CIC deposit only: refreshes the charge grid, leaves the potential alone. */
+int32_t orc_deposit(orc_sim *s);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,316 @@
+// mc_poisson.hpp -- HIP kernels of the cylindrical Poisson solve (gfx950).
+//
+// The space-charge potential solves the finite-volume cylindrical Poisson
+// equation with Dirichlet ends in z and at r = R (the space-charge section):
+// a sine transform (DST-I) along z per radial row diagonalises the axial
+// operator, leaving one tridiagonal system in r per sine mode.
+//
+//   k_dst_bluestein  forward / inverse DST-I of one radial row by Bluestein's
+//                    chirp z-transform: power-of-two FFTs held in LDS
+//   k_dst_rows, k_idst_rows  the same transforms as direct sums (used when
+//                    the FFT length does not fit in a workgroup's LDS)
+//   k_thomas_coef, k_thomas  per-mode tridiagonal solve in r, FP64 always
+#pragma once
+#include "mc_device.hpp"
+
+#include <algorithm>
+
+namespace mc {
+
+static __global__ __launch_bounds__(256) void k_sine_table(double *s, int32_t nz) {
+    const int32_t n2 = 2 * (nz - 1);
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n2) s[q] = sin(kPi * (double)q / (double)(nz - 1));
+}
+
+// ---------------------------------------------------------------------------
+// Poisson: unknowns Phi[i][j], 0 <= i <= nr-2, 1 <= j <= nz-2 (m = nz-2).
+// Right-hand side b = -rho/eps0 with rho = Q e 2^-32 / V_i, V_0 = pi dr^2 dz/3,
+// V_i = 2 pi r_i dr dz.  Forward DST-I per radial row (scaled 2/(m+1)), one
+// tridiagonal system per mode (coefficients precomputed), inverse DST-I.
+// Row-major work arrays bh[i][k], k contiguous.
+// ---------------------------------------------------------------------------
+template <class D>
+__global__ __launch_bounds__(256) void k_dst_rows(const unsigned long long *q, const double *sine, D *bh,
+                                                  int32_t nr, int32_t nz, double dr, double dz) {
+    extern __shared__ unsigned char smem_raw[];
+    D *row = reinterpret_cast<D *>(smem_raw);
+    const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
+    const double vol = (i == 0) ? kPi * dr * dr * dz / 3.0 : 2.0 * kPi * ((double)i * dr) * dr * dz;
+    const double scale = -kQe * 0x1p-32 / (vol * kEps0);
+    for (int32_t j = threadIdx.x; j < m; j += blockDim.x)
+        row[j] = (D)((double)(int64_t)q[(int64_t)(j + 1) * nr + i] * scale);
+    __syncthreads();
+    const D norm = (D)(2.0 / (double)(nz - 1));
+    for (int32_t k = 1 + threadIdx.x; k <= m; k += blockDim.x) {
+        D acc = 0;
+        int32_t idx = 0;
+        for (int32_t j = 1; j <= m; ++j) {
+            idx += k;
+            if (idx >= n2) idx -= n2;
+            acc += row[j - 1] * (D)sine[idx];
+        }
+        bh[(int64_t)i * m + (k - 1)] = acc * norm;
+    }
+}
+
+// Tridiagonal coefficients per (row i, mode k): cp = up / den, inv = 1 / den,
+// den_i = diag_i(k) - lo_i cp_{i-1}; diag = -(lo + up) + lambda_k,
+// lambda_k = -(4/dz^2) sin^2(pi k / (2 (nz-1))).
+static __global__ __launch_bounds__(256) void k_thomas_coef(double *cp, double *inv, int32_t nr, int32_t nz, double dr,
+                                                     double dz) {
+    const int32_t m = nz - 2, nu = nr - 1;
+    const int32_t k = 1 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (k > m) return;
+    const double sk = sin(kPi * (double)k / (2.0 * (double)(nz - 1)));
+    const double lam = -(4.0 / (dz * dz)) * sk * sk;
+    double cprev = 0.0;
+    for (int32_t i = 0; i < nu; ++i) {
+        double lo, up, di;
+        if (i == 0) {
+            lo = 0.0;
+            di = -4.0 / (dr * dr) + lam;
+            up = 4.0 / (dr * dr);
+        } else {
+            const double ri = (double)i * dr;
+            lo = (ri - 0.5 * dr) / (ri * dr * dr);
+            up = (ri + 0.5 * dr) / (ri * dr * dr);
+            di = -(lo + up) + lam;
+        }
+        const double den = (i == 0) ? di : di - lo * cprev;
+        cprev = up / den;
+        cp[(int64_t)i * m + (k - 1)] = cprev;
+        inv[(int64_t)i * m + (k - 1)] = 1.0 / den;
+    }
+}
+
+template <class D>
+__global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const double *inv, int32_t nr, int32_t nz,
+                                                double dr) {
+    const int32_t m = nz - 2, nu = nr - 1;
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    // forward sweep in FP64
+    double dprev = 0.0;
+    for (int32_t i = 0; i < nu; ++i) {
+        const int64_t o = (int64_t)i * m + k;
+        double lo = 0.0;
+        if (i > 0) {
+            const double ri = (double)i * dr;
+            lo = (ri - 0.5 * dr) / (ri * dr * dr);
+        }
+        dprev = ((double)bh[o] - lo * dprev) * inv[o];
+        bh[o] = (D)dprev;
+    }
+    double x = 0.0;
+    for (int32_t i = nu - 1; i >= 0; --i) {
+        const int64_t o = (int64_t)i * m + k;
+        x = (i == nu - 1) ? (double)bh[o] : (double)bh[o] - cp[o] * x;
+        bh[o] = (D)x;
+    }
+}
+
+template <class D>
+__global__ __launch_bounds__(256) void k_idst_rows(const D *ph, const double *sine, double *phi, int32_t nr,
+                                                   int32_t nz) {
+    extern __shared__ unsigned char smem_raw[];
+    D *row = reinterpret_cast<D *>(smem_raw);
+    const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
+    for (int32_t k = threadIdx.x; k < m; k += blockDim.x) row[k] = ph[(int64_t)i * m + k];
+    __syncthreads();
+    for (int32_t j = 1 + threadIdx.x; j <= m; j += blockDim.x) {
+        D acc = 0;
+        int32_t idx = 0;
+        for (int32_t k = 1; k <= m; ++k) {
+            idx += j;
+            if (idx >= n2) idx -= n2;
+            acc += row[k - 1] * (D)sine[idx];
+        }
+        phi[(int64_t)j * nr + i] = (double)acc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sine transform by Bluestein's chirp z-transform (O(L log L) per row).
+// With kj = (k^2 + j^2 - (k-j)^2)/2,
+//   X_k = sum_j x_j sin(pi k j / N) = Im[ c_k sum_j (x_j c_j) b_{k-j} ],
+//   c_j = exp(i pi j^2 / 2N),  b_d = exp(-i pi d^2 / 2N),
+// a linear convolution of length m evaluated with power-of-two FFTs of
+// length L >= 2m - 1 held in LDS.  The forward FFT is decimation in
+// frequency (natural order in, bit-reversed out), the filter spectrum FFT(b)
+// is stored bit-reversed, and the inverse is decimation in time
+// (bit-reversed in, natural out), so no permutation pass is needed.
+// Phases use j^2 mod 4N in integers, so large j lose no accuracy.
+// ---------------------------------------------------------------------------
+template <class D>
+struct Cx {
+    D re, im;
+};
+
+template <class D>
+__device__ __forceinline__ Cx<D> cmul(Cx<D> a, Cx<D> b) {
+    return Cx<D>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+// In-place radix-2 FFT on LDS.  Forward (DIF, twiddles exp(-2 pi i k / L)):
+// natural order in, bit-reversed out.  Inverse (DIT, conjugate twiddles,
+// scaled by 1/L): bit-reversed in, natural out.
+template <class D, bool kInverse>
+__device__ void fft_lds(Cx<D> *a, int32_t L, const Cx<D> *tw) {
+    const int32_t half_total = L >> 1;
+    if (!kInverse) {
+        for (int32_t len = L; len >= 2; len >>= 1) {
+            const int32_t half = len >> 1, stride = L / len;
+            for (int32_t b = threadIdx.x; b < half_total; b += blockDim.x) {
+                const int32_t k = b % half, i0 = (b / half) * len + k, i1 = i0 + half;
+                const Cx<D> u = a[i0], v = a[i1];
+                a[i0] = Cx<D>{u.re + v.re, u.im + v.im};
+                a[i1] = cmul(Cx<D>{u.re - v.re, u.im - v.im}, tw[k * stride]);
+            }
+            __syncthreads();
+        }
+    } else {
+        for (int32_t len = 2; len <= L; len <<= 1) {
+            const int32_t half = len >> 1, stride = L / len;
+            for (int32_t b = threadIdx.x; b < half_total; b += blockDim.x) {
+                const int32_t k = b % half, i0 = (b / half) * len + k, i1 = i0 + half;
+                const Cx<D> w = tw[k * stride];
+                const Cx<D> t = cmul(a[i1], Cx<D>{w.re, -w.im});
+                const Cx<D> u = a[i0];
+                a[i0] = Cx<D>{u.re + t.re, u.im + t.im};
+                a[i1] = Cx<D>{u.re - t.re, u.im - t.im};
+            }
+            __syncthreads();
+        }
+        const D s = (D)1 / (D)L;
+        for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
+            a[n].re *= s;
+            a[n].im *= s;
+        }
+        __syncthreads();
+    }
+}
+
+// Tables for one grid: chirp[n] = c_{n+1} (n < m), tw[k] = exp(-2 pi i k/L)
+// (k < L/2), and fb = FFT(b) in bit-reversed order (built by k_bluestein_filter).
+template <class D>
+__global__ __launch_bounds__(256) void k_bluestein_tables(Cx<D> *chirp, Cx<D> *tw, int32_t m, int32_t L) {
+    const int32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t fourN = 4 * (int64_t)(m + 1);
+    if (n < m) {
+        const int64_t j = n + 1, q = (j * j) % fourN;
+        double sv, cv;
+        sincospi((double)q / (double)(2 * (m + 1)), &sv, &cv);
+        chirp[n] = Cx<D>{(D)cv, (D)sv};
+    }
+    if (n < (L >> 1)) {
+        double sv, cv;
+        sincospi(-2.0 * (double)n / (double)L, &sv, &cv);
+        tw[n] = Cx<D>{(D)cv, (D)sv};
+    }
+}
+
+template <class D>
+__global__ __launch_bounds__(1024) void k_bluestein_filter(Cx<D> *fb, const Cx<D> *tw, int32_t m, int32_t L) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<D> *a = reinterpret_cast<Cx<D> *>(smem_raw);
+    const int64_t fourN = 4 * (int64_t)(m + 1);
+    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
+        int64_t d = -1;
+        if (n < m) d = n;
+        else if (n > L - m) d = L - n;  // b_{-d} = b_d
+        Cx<D> v{(D)0, (D)0};
+        if (d >= 0) {
+            const int64_t q = (d * d) % fourN;
+            double sv, cv;
+            sincospi((double)q / (double)(2 * (m + 1)), &sv, &cv);
+            v = Cx<D>{(D)cv, (D)(-sv)};
+        }
+        a[n] = v;
+    }
+    __syncthreads();
+    fft_lds<D, false>(a, L, tw);
+    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) fb[n] = a[n];
+}
+
+// One radial row per block.  kForward: input -rho/eps0 of column i from the
+// int64 charge grid, output bh[i][:] scaled by 2/N.  Inverse: input bh[i][:],
+// output Phi[1..m][i].
+template <class D, bool kForward>
+__global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long *q, D *bh, double *phi,
+                                                        const Cx<D> *chirp, const Cx<D> *fb, const Cx<D> *tw,
+                                                        int32_t nr, int32_t nz, int32_t L, double dr, double dz) {
+    extern __shared__ unsigned char smem_raw[];
+    Cx<D> *a = reinterpret_cast<Cx<D> *>(smem_raw);
+    const int32_t i = blockIdx.x, m = nz - 2;
+    const double vol = (i == 0) ? kPi * dr * dr * dz / 3.0 : 2.0 * kPi * ((double)i * dr) * dr * dz;
+    const double scale = -kQe * 0x1p-32 / (vol * kEps0);
+    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
+        Cx<D> v{(D)0, (D)0};
+        if (n < m) {
+            const D x = kForward ? (D)((double)(int64_t)q[(int64_t)(n + 1) * nr + i] * scale) : bh[(int64_t)i * m + n];
+            const Cx<D> c = chirp[n];
+            v = Cx<D>{x * c.re, x * c.im};
+        }
+        a[n] = v;
+    }
+    __syncthreads();
+    fft_lds<D, false>(a, L, tw);
+    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) a[n] = cmul(a[n], fb[n]);
+    __syncthreads();
+    fft_lds<D, true>(a, L, tw);
+    const D norm = kForward ? (D)(2.0 / (double)(nz - 1)) : (D)1;
+    for (int32_t k = threadIdx.x; k < m; k += blockDim.x) {
+        const Cx<D> c = chirp[k], y = a[k];
+        const D X = (c.re * y.im + c.im * y.re) * norm;  // Im(c y)
+        if (kForward) bh[(int64_t)i * m + k] = X;
+        else phi[(int64_t)(k + 1) * nr + i] = (double)X;
+    }
+}
+
+// Host side of the chirp z sine transform: one set of tables per grid.
+struct Bluestein {
+    int32_t L = 0;      // 0: not used (FFT length would not fit in LDS)
+    size_t lds = 0;     // bytes of LDS per row block
+    void *chirp = nullptr, *tw = nullptr, *fb = nullptr;
+};
+
+constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+
+// LDS a workgroup may take on the current device (the smaller of the
+// architectural limit and what the runtime reports).
+inline size_t lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return std::min(kLdsLimit, (size_t)v);
+}
+
+inline int32_t bluestein_length(int32_t m) {
+    int32_t L = 1;
+    while (L < 2 * m - 1) L <<= 1;
+    return L;
+}
+
+template <class D>
+inline hipError_t bluestein_prepare(Bluestein &B, int32_t m, hipStream_t st) {
+    const int32_t n = std::max(m, B.L >> 1);
+    k_bluestein_tables<D><<<(n + 255) / 256, 256, 0, st>>>((Cx<D> *)B.chirp, (Cx<D> *)B.tw, m, B.L);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (B.lds > 65536) {
+        e = hipFuncSetAttribute((const void *)&k_bluestein_filter<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)B.lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)&k_dst_bluestein<D, true>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void *)&k_dst_bluestein<D, false>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)B.lds);
+        if (e != hipSuccess) return e;
+    }
+    k_bluestein_filter<D><<<1, 1024, B.lds, st>>>((Cx<D> *)B.fb, (const Cx<D> *)B.tw, m, B.L);
+    return hipGetLastError();
+}
+}  // namespace mc

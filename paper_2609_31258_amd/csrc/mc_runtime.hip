@@ -17,6 +17,7 @@
 
 #include "mc_host.hpp"
 #include "mc_kernels.hpp"
+#include "mc_poisson.hpp"
 
 using namespace mc;
 

@@ -22,6 +22,7 @@
 
 #include "mc_host.hpp"
 #include "mc_kernels.hpp"
+#include "mc_poisson.hpp"
 #include "mc_pool.hpp"
 
 using namespace mc;

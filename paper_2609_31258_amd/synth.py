@@ -234,6 +234,23 @@ def config_c5_species(n_species: int = 10):
     return ions
 
 
+def config_c5(n_packs: int = 16_000_000, emit_steps: int = 10_000, current_a: float = 50e-9,
+              nr: int = 1024, nz: int = 8192):
+    """Large: 1024x8192 grid (0.05 mm), ten species sharing the packs and the
+    current equally (5 nA each), each emitted at n_packs / (10 emit_steps)
+    packs per step over the first emit_steps steps; Einstein heat capacity
+    and Arrhenius dissociation per species; space charge every 5 steps;
+    dt = 0.25 ns, 1e5 steps; run in the FP32 precision form."""
+    f = ring_fields(nr, nz)
+    ions = config_c5_species(10)
+    per = n_packs // len(ions)
+    srcs = [Source(kind=1, ion=k, current_a=current_a / len(ions), packs_per_step=max(1, per // emit_steps),
+                   n_total=per, sigma_r=1e-4, r_trunc=3e-4, z_inj=0.0) for k in range(len(ions))]
+    op = Operating(dt=0.25e-9, v_rf=100.0, f_rf=1e6, z_det=f.grid.L, r_det=f.grid.R, sc_on=1, sc_every=5,
+                   exit_bin_dt=1e-7, n_exit_bins=1000)
+    return f, ions, srcs, op, {"steps": 100_000, "emit_steps": emit_steps}
+
+
 def serving_queries(n_queries: int = 256, rate_hz: float = 20.0, seed: int = SEED,
                     pack_lo: float = 1e3, pack_hi: float = 1e6) -> List[Dict]:
     """Design queries with Poisson arrivals: RF amplitude U(50, 300) V, DC

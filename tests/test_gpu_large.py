@@ -1,0 +1,168 @@
+"""The large configuration on the GPU: 1024x8192 grid (8.4 M nodes), ten
+species with Einstein heat capacities and Arrhenius dissociation, space
+charge every 5 steps, FP32 precision form (and the FP64 path beside it).
+
+Bars: single-step state against the oracle as for the smaller grids (FP64:
+within 1e-6 relative, identical classification; FP32 form: the precision-form
+bounds); deposit bit-exact against the oracle on the full grid; the potential
+checked through properties that hold at any size (the discrete Poisson
+residual of the FP64 path; the FP32 path against the FP64 path), because the
+oracle's direct O(nz^2) sine sums take minutes on a grid this size.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2609_31258_amd import synth
+from tests.parity_util import make_pair, step_errors, thermal_speed
+
+pytestmark = pytest.mark.gpu
+
+KB = 1.380649e-23
+EPS0 = 8.8541878188e-12
+QE = 1.602176634e-19
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _c5_snapshot(f, ions, n, seed, z_hi, r_hi, weight=1.0):
+    snap = synth.pack_snapshot(n, f, seed=seed, z_hi=z_hi, r_hi=r_hi, v_sigma=200.0, weight=weight)
+    tag = (np.arange(n) % len(ions)).astype(np.int32)
+    snap["tag"] = tag
+    # internal energy of an Einstein solid near 300-1500 K for each species
+    dof = np.array([3 * ions[k].n_atoms - 6 for k in tag], dtype=np.float64)
+    u = np.random.default_rng(seed + 1).uniform(0.3, 1.5, n)
+    snap["e_int"] = dof * KB * 300.0 * u
+    snap["h"] = np.random.default_rng(seed + 2).uniform(0, 1e-3, n)
+    return snap
+
+
+def _two_float(snap):
+    for k in ("x", "y", "z"):
+        hi = snap[k].astype(np.float32)
+        snap[k] = hi.astype(np.float64) + (snap[k] - hi.astype(np.float64)).astype(np.float32).astype(np.float64)
+    return snap
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_large_grid_ten_species_single_step(precision):
+    n = 20_011
+    f, ions, _, op, _ = synth.config_c5(n_packs=n)
+    op.sc_on = 0
+    snap = _c5_snapshot(f, ions, n, seed=14, z_hi=0.05, r_hi=1.5e-2)
+    _say("large grid single step, precision", precision, f.grid.nr, f.grid.nz, n)
+    g, o = make_pair(f, ions, [], op, cap=n, precision=precision)
+    g.write_packs(snap)
+    o.write_packs(snap)
+    g.step(1)
+    o.step(1)
+    r = step_errors(g.read_packs(), o.read_packs(), f.grid.dr, thermal_speed(), snap["h"])
+    flips = int((~r["same_status"]).sum())
+    ta, tb = g.read_tallies(), o.read_tallies()
+    _say(f"  max dx {r['max_dx']:.2e} dv {r['max_dv']:.2e} de {r['max_de']:.2e} median dv "
+         f"{np.median(r['dv']):.2e} flips {flips} classes {tb['class_n'].tolist()} candidates {tb['n_cand']}")
+    assert tb["n_cand"] > 10 * n  # the dense inlet: many collisions per pack-step
+    if precision == 0:
+        assert flips == 0
+        assert r["ok"].sum() >= n - max(1, n // 10_000)
+        assert np.array_equal(ta["class_n"], tb["class_n"]) and np.array_equal(ta["class_w"], tb["class_w"])
+        assert np.array_equal(ta["loss_map"], tb["loss_map"])
+        assert abs(ta["n_cand"] - tb["n_cand"]) <= max(2, tb["n_cand"] // 100_000)
+    else:
+        assert flips <= max(2, n // 1000)
+        assert np.median(r["dv"]) < 1e-3 and np.median(r["dx"]) < 1e-5
+        assert abs(ta["n_cand"] - tb["n_cand"]) <= 1e-3 * tb["n_cand"]
+    g.close()
+
+
+def _poisson_residual(q, phi, dr, dz):
+    """max |L phi + rho/eps0| / max |rho/eps0| over the unknowns, with L the
+    finite-volume cylindrical operator (axis row: 4 (phi_1 - phi_0)/dr^2)."""
+    nz, nr = q.shape
+    i = np.arange(nr, dtype=np.float64)
+    vol = np.where(i == 0, np.pi * dr * dr * dz / 3.0, 2.0 * np.pi * i * dr * dr * dz)
+    b = -(q.astype(np.float64) * QE * 2.0 ** -32 / vol[None, :]) / EPS0
+    p = phi
+    ar = np.empty((nz - 2, nr - 1))
+    pj = p[1:-1]
+    ar[:, 0] = 4.0 * (pj[:, 1] - pj[:, 0]) / dr ** 2
+    ri = i[1:nr - 1] * dr
+    ar[:, 1:] = ((ri + 0.5 * dr) * (pj[:, 2:] - pj[:, 1:-1]) - (ri - 0.5 * dr) * (pj[:, 1:-1] - pj[:, :-2])) / (
+        ri * dr * dr)
+    az = (p[2:, :nr - 1] - 2.0 * p[1:-1, :nr - 1] + p[:-2, :nr - 1]) / dz ** 2
+    bb = b[1:-1, :nr - 1]
+    return np.abs(ar + az - bb).max() / np.abs(bb).max()
+
+
+def test_large_grid_deposit_and_poisson():
+    n = 200_000
+    f, ions, _, op, _ = synth.config_c5(n_packs=n)
+    snap = _two_float(_c5_snapshot(f, ions, n, seed=15, z_hi=0.1, r_hi=1.5e-2, weight=0.01))
+    _say("large grid deposit and poisson", f.grid.nr, f.grid.nz, n)
+    g64, o = make_pair(f, ions, [], op, cap=n, precision=0)
+    o.write_packs(snap)
+    o.deposit()
+    q_ref = o.read_charge()
+    g64.write_packs(snap)
+    g64.pic_update()
+    assert np.array_equal(g64.read_charge(), q_ref)
+    p64, er64, ez64 = g64.read_sc()
+    g64.close()
+    res = _poisson_residual(q_ref, p64, f.grid.dr, f.grid.dz)
+    _say(f"  fp64 poisson residual {res:.2e}")
+    assert res <= 1e-8
+    # E = -grad phi: central differences inside, E_r = 0 on the axis
+    ez_c = -(p64[2:, :] - p64[:-2, :]) / (2 * f.grid.dz)
+    er_c = -(p64[:, 2:] - p64[:, :-2]) / (2 * f.grid.dr)
+    es = max(np.abs(er64).max(), np.abs(ez64).max())
+    assert np.abs(ez64[1:-1, :] - ez_c).max() <= 1e-12 * es
+    assert np.abs(er64[:, 1:-1] - er_c).max() <= 1e-12 * es and not er64[:, 0].any()
+    from paper_2609_31258_amd import mucite
+    g32 = mucite.Sim(seed=7, pack_capacity=n, precision=1)
+    g32.setup(f, ions, [], op)
+    g32.write_packs(snap)
+    g32.pic_update()
+    assert np.array_equal(g32.read_charge(), q_ref)
+    p32, er32, ez32 = g32.read_sc()
+    g32.close()
+    ep = np.abs(p32 - p64).max() / np.abs(p64).max()
+    ee = max(np.abs(er32 - er64).max(), np.abs(ez32 - ez64).max()) / es
+    _say(f"  fp32 vs fp64: phi {ep:.2e}, E {ee:.2e}")
+    assert ep <= 5e-6 and ee <= 1e-4
+
+
+def test_large_configuration_runs_with_space_charge():
+    """A short stretch of the large configuration in the FP32 form, ten
+    sources emitting, space charge every 5 steps: conservation of emitted
+    weight and charge, and bit-for-bit repeatability."""
+    from paper_2609_31258_amd import mucite
+    n = 400_000
+    f, ions, srcs, op, meta = synth.config_c5(n_packs=n, emit_steps=100)
+    _say("large configuration, 60 steps, fp32", n)
+    out = []
+    for _ in range(2):
+        g = mucite.Sim(seed=7, pack_capacity=n, precision=1)
+        g.setup(f, ions, srcs, op)
+        g.step(60)
+        t = g.read_tallies()
+        q = g.read_charge()
+        p = g.read_packs()
+        g.close()
+        out.append((t, q, p))
+    t, q, p = out[0]
+    assert t["emitted_n"] == 10 * 60 * (n // 10 // 100)
+    assert t["class_w"].sum() == t["emitted_w"]
+    assert t["n_coll"] > 0 and t["pack_steps"] > 0
+    # the charge grid holds the last deposit (step 55); conservation against
+    # the packs active then is checked on the smaller grids, here it is > 0
+    assert q.sum() > 0
+    t2, q2, p2 = out[1]
+    assert np.array_equal(q, q2)
+    for k in ("class_n", "class_w", "loss_map", "hist_ke", "hist_teff"):
+        assert np.array_equal(np.asarray(t[k]), np.asarray(t2[k])), k
+    assert np.array_equal(p["x"], p2["x"]) and np.array_equal(p["e_int"], p2["e_int"])
+    _say(f"  classes {t['class_n'].tolist()} collisions {t['n_coll']} pack-steps {t['pack_steps']}")
