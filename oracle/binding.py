@@ -32,7 +32,8 @@ class Source(C.Structure):
 class Operating(C.Structure):
     _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
-                ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32)]
+                ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
+                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64)]
 
 
 class Packs(C.Structure):
@@ -42,7 +43,7 @@ class Packs(C.Structure):
 
 class Tallies(C.Structure):
     _fields_ = [("emitted_n", I64), ("emitted_w", I64), ("class_n", I64 * NCLASS), ("class_w", I64 * NCLASS),
-                ("n_cand", I64), ("n_coll", I64), ("n_cap", I64), ("n_clamp", I64), ("exit_overflow", I64),
+                ("n_cand", I64), ("n_coll", I64), ("n_cap", I64), ("n_clamp", I64), ("exit_overflow", I64), ("n_langevin", I64),
                 ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
                 ("exit_bins", PI64), ("loss_map", PI64), ("hist_ke", PI64), ("hist_teff", PI64), ("hist_r", PI64),
                 ("act_hist_ke", PI64), ("act_hist_teff", PI64)]
@@ -99,6 +100,8 @@ def lib():
         "orc_read_hit": (I32, [C.c_void_p, PU8]),
         "orc_pic_update": (I32, [C.c_void_p]),
         "orc_deposit": (I32, [C.c_void_p]),
+        "orc_langevin_gamma": (F64, [F64, F64, F64, F64]),
+        "orc_langevin_relax": (None, [F64, F64, F64, PD, F64, PD, PD]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -192,6 +195,16 @@ def iict_update(m, mg, v, vgas, e_int, t_eff, alpha, uniforms):
     lib().orc_iict_update(m, mg, _p(v, F64), _p(vg, F64), e_int, t_eff, alpha, _p(w, F64), _p(vo, F64),
                           _p(vgo, F64), _p(eo, F64), _p(cl, I32))
     return vo, vgo, float(eo[0]), int(cl[0])
+
+
+def langevin_gamma(m: float, mg: float, n_sigma: float, t_gas: float) -> float:
+    return lib().orc_langevin_gamma(m, mg, n_sigma, t_gas)
+
+
+def langevin_relax(m, gamma, t_gas, u, dt, xi, v) -> np.ndarray:
+    u, xi, v = _f64(u), _f64(xi), _f64(v).copy()
+    lib().orc_langevin_relax(m, gamma, t_gas, _p(u, F64), dt, _p(xi, F64), _p(v, F64))
+    return v
 
 
 def collision_probe(m_da, ccs, mg_da, p, t_gas, u, v, dt, n_steps, seed):
@@ -315,7 +328,7 @@ class OracleSim:
             setattr(T, k, _p(a, I64))
         self._chk(lib().orc_read_tallies(self._h, C.byref(T)), "read_tallies")
         out = dict(bufs)
-        for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "exit_overflow",
+        for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "exit_overflow", "n_langevin",
                   "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
             out[k] = getattr(T, k)
         out["class_n"] = np.array(list(T.class_n), np.int64)

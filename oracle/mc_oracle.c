@@ -67,7 +67,7 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 static double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
 
 /* Stream layout: counter = (pack id low, step, purpose<<24 | block, pack id high). */
-enum { PURPOSE_INJECT = 0, PURPOSE_COLLIDE = 1 };
+enum { PURPOSE_INJECT = 0, PURPOSE_COLLIDE = 1, PURPOSE_LANGEVIN = 2 };
 static void draw(const uint32_t key[2], int64_t id, int64_t step, uint32_t purpose, uint32_t block, uint32_t w[4]) {
     uint32_t ctr[4] = {(uint32_t)((uint64_t)id & 0xffffffffu), (uint32_t)step, (purpose << 24) | block,
                        (uint32_t)((uint64_t)id >> 32)};
@@ -393,7 +393,7 @@ typedef struct {
 } coll_env_t;
 
 typedef struct {
-    int64_t n_cand, n_acc, n_cap, n_clamp;
+    int64_t n_cand, n_acc, n_cap, n_clamp, n_lang;
     double sum_g, sum_g2;
 } coll_count_t;
 
@@ -526,7 +526,7 @@ struct orc_sim {
     int32_t *ex_i, *ex_j;
     double *ex_t, *ex_r;
     /* per-step counters */
-    int64_t n_cand, n_coll, n_cap, n_clamp;
+    int64_t n_cand, n_coll, n_cap, n_clamp, n_lang;
     int64_t emitted_n, emitted_w;
 };
 
@@ -662,6 +662,7 @@ int32_t orc_define_source(orc_sim *s, const orc_source *in) {
 
 int32_t orc_set_operating(orc_sim *s, const orc_operating *op) {
     if (!(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1) return -1;
+    if (op->langevin_on && !(op->lv_switch >= 0.0)) return -1;
     s->op = *op;
     s->has_op = 1;
     for (int k = 0; k < s->n_ion; ++k) set_alpha(s, &s->ion[k]);
@@ -830,6 +831,55 @@ static void efield(const orc_sim *s, double x, double y, double z, double c, dou
     e[2] = ez;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Hybrid Langevin branch (collision section; Ermak and Buckholz, ref. 31). */
+/* In the dense region the explicit events of a step are replaced by the    */
+/* relaxation of the velocity toward the local gas velocity with a          */
+/* temperature-dependent random part; T_eff and the hazard are not updated  */
+/* in such a step.  Readings:                                               */
+/*  - the step is the collision sub-step of the splitting (the RK4 push has */
+/*    already applied the field), so the velocity solves                    */
+/*    dv = -gamma (v - u) dt + sqrt(2 gamma kB T / m) dW over dt exactly:    */
+/*    v' = u + (v - u) e^{-gamma dt} + sqrt(kB T/m (1 - e^{-2 gamma dt})) xi; */
+/*  - gamma is the momentum-transfer rate of the same hard-sphere gas at low */
+/*    field (first Chapman-Enskog approximation, for which the hard-sphere   */
+/*    momentum-transfer cross section equals the CCS):                       */
+/*    gamma = (16/3) (n sigma / m) sqrt(mu kB T / (2 pi)),                  */
+/*    written with mu/m and kB T/m so single precision cannot underflow;     */
+/*  - a pack takes the branch for a step when the branch is on, its z after  */
+/*    the push lies in [z_lo, z_hi) (any z when z_hi <= z_lo) and           */
+/*    lambda dt >= lv_switch, lambda = n sigma (s + abar) the candidate rate */
+/*    of the explicit branch at the post-push velocity;                      */
+/*  - xi: Box-Muller normals from one Philox block (purpose 2, block 0):     */
+/*    (w0, w1) -> xi_x, xi_y; (w2, w3) -> xi_z.                             */
+/* Pinned: gamma against the heavy-ion (Epstein specular) limit            */
+/* (4/3) n sigma mg abar / m; the relaxation's mean and variance against   */
+/* the Ornstein-Uhlenbeck closed form; equipartition; drift in a uniform   */
+/* field equal to (a/gamma)(x/2)coth(x/2), x = gamma dt, the same splitting */
+/* factor as the explicit branch; explicit and Langevin low-field drift     */
+/* agree.                                                                   */
+/* ------------------------------------------------------------------------ */
+double orc_langevin_gamma(double m, double mg, double n_sigma, double t_gas) {
+    double mu_over_m = mg / (m + mg);
+    return (16.0 / 3.0) * n_sigma * sqrt(mu_over_m * (KB * t_gas / m) / (2.0 * PI));
+}
+
+void orc_langevin_relax(double m, double gamma, double t_gas, const double u[3], double dt, const double xi[3],
+                        double v[3]) {
+    double f = exp(-gamma * dt);
+    double sd = sqrt((KB * t_gas / m) * (1.0 - f * f));
+    for (int a = 0; a < 3; ++a) v[a] = u[a] + (v[a] - u[a]) * f + sd * xi[a];
+}
+
+static void langevin_normals(const uint32_t key[2], int64_t id, int64_t step, double xi[3]) {
+    uint32_t w[4];
+    draw(key, id, step, PURPOSE_LANGEVIN, 0, w);
+    double r0 = sqrt(-2.0 * log(u01(w[0]))), r1 = sqrt(-2.0 * log(u01(w[2])));
+    xi[0] = r0 * cos(2.0 * PI * u01(w[1]));
+    xi[1] = r0 * sin(2.0 * PI * u01(w[1]));
+    xi[2] = r1 * cos(2.0 * PI * u01(w[3]));
+}
+
 /* One pack, one step: RK4 push, classification, collisions, dissociation.  */
 static void advance(orc_sim *s, int64_t k, int64_t step, const double cst[3], coll_count_t *cnt) {
     const ion_t *I = &s->ion[s->tag[k]];
@@ -905,9 +955,25 @@ static void advance(orc_sim *s, int64_t k, int64_t step, const double cst[3], co
         E.a_g = sqrt(KB * tg / E.mg);
         E.abar = E.a_g * sqrt(8.0 / PI);
         double v[3] = {v1[0], v1[1], v1[2]}, ei = s->eint[k];
-        collide(&E, s->key, s->id[k], step, dt, v, &ei, 0, cnt);
+        int lv = 0;
+        if (s->op.langevin_on && E.n_gas > 0.0 && isfinite(E.n_gas) &&
+            (!(s->op.lv_z_hi > s->op.lv_z_lo) || (x1[2] >= s->op.lv_z_lo && x1[2] < s->op.lv_z_hi))) {
+            double rel[3] = {v[0] - E.u[0], v[1] - E.u[1], v[2] - E.u[2]};
+            double sv = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
+            double lam = E.n_gas * E.sigma * (sv + E.abar);
+            lv = lam * dt >= s->op.lv_switch;
+        }
+        if (lv) {
+            double xi[3];
+            langevin_normals(s->key, s->id[k], step, xi);
+            orc_langevin_relax(E.m, orc_langevin_gamma(E.m, E.mg, E.n_gas * E.sigma, tg), tg, E.u, dt, xi, v);
+            cnt->n_lang++;
+        } else {
+            collide(&E, s->key, s->id[k], step, dt, v, &ei, 0, cnt);
+        }
         s->vx[k] = v[0]; s->vy[k] = v[1]; s->vz[k] = v[2];
         s->eint[k] = ei;
+        if (lv) return; /* no T_eff or hazard update in an aggregated step */
     }
     /* Eq. 7: hazard H accumulates k(T_eff) dt with the post-collision T_eff */
     double te = orc_einstein_t(s->eint[k], I->in.n_atoms, I->in.theta_e);
@@ -924,8 +990,8 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
         double cst[3] = {s->op.v_rf * cos(w2 * t0 + s->op.phase_rf),
                          s->op.v_rf * cos(w2 * (t0 + 0.5 * dt) + s->op.phase_rf),
                          s->op.v_rf * cos(w2 * (t0 + dt) + s->op.phase_rf)};
-        int64_t nc = 0, na = 0, ncap = 0, ncl = 0;
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nc, na, ncap, ncl)
+        int64_t nc = 0, na = 0, ncap = 0, ncl = 0, nlv = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nc, na, ncap, ncl, nlv)
         for (int64_t k = 0; k < s->n; ++k) {
             if (s->status[k] != ORC_ACTIVE) continue;
             coll_count_t cnt;
@@ -935,11 +1001,13 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
             na += cnt.n_acc;
             ncap += cnt.n_cap;
             ncl += cnt.n_clamp;
+            nlv += cnt.n_lang;
         }
         s->n_cand += nc;
         s->n_coll += na;
         s->n_cap += ncap;
         s->n_clamp += ncl;
+        s->n_lang += nlv;
         s->step++;
     }
     return 0;
@@ -1058,6 +1126,7 @@ int32_t orc_read_tallies(const orc_sim *s, orc_tallies *t) {
     t->n_coll = s->n_coll;
     t->n_cap = s->n_cap;
     t->n_clamp = s->n_clamp;
+    t->n_langevin = s->n_lang;
     return 0;
 }
 

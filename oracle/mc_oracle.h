@@ -56,6 +56,10 @@ typedef struct orc_operating {
     int32_t collisions_on, sc_on, sc_every;
     double z_det, r_det, d_hit, exit_bin_dt;
     int32_t n_exit_bins;
+    /* hybrid Langevin branch: on, axial window [lv_z_lo, lv_z_hi) (no window
+     * when lv_z_hi <= lv_z_lo), switch when lambda dt >= lv_switch */
+    int32_t langevin_on;
+    double lv_z_lo, lv_z_hi, lv_switch;
 } orc_operating;
 
 typedef struct orc_packs {
@@ -68,7 +72,7 @@ typedef struct orc_packs {
 typedef struct orc_tallies {
     int64_t emitted_n, emitted_w;
     int64_t class_n[ORC_NCLASS], class_w[ORC_NCLASS];
-    int64_t n_cand, n_coll, n_cap, n_clamp, exit_overflow;
+    int64_t n_cand, n_coll, n_cap, n_clamp, exit_overflow, n_langevin;
     double sum_w_ke_active, sum_w_eint_active, sum_w_dissoc_terminal;
     int64_t *exit_bins; /* [n_exit_bins] */
     int64_t *loss_map;  /* [nz*nr] */
@@ -128,6 +132,11 @@ int32_t orc_read_charge(const orc_sim *s, int64_t *q);
 int32_t orc_read_sc(const orc_sim *s, double *phi, double *er, double *ez);
 int32_t orc_read_hit(const orc_sim *s, uint8_t *hit);
 int32_t orc_pic_update(orc_sim *s);
+/* Hybrid Langevin branch: friction rate of the hard-sphere gas and the
+ * exact relaxation of the velocity over dt (see mc_oracle.c). */
+double orc_langevin_gamma(double m, double mg, double n_sigma, double t_gas);
+void orc_langevin_relax(double m, double gamma, double t_gas, const double u[3], double dt, const double xi[3],
+                        double v[3]);
 /* CIC deposit only: refreshes the charge grid, leaves the potential alone. */
 int32_t orc_deposit(orc_sim *s);
 

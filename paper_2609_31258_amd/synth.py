@@ -97,6 +97,10 @@ class Operating:
     d_hit: float = 1e-5
     exit_bin_dt: float = 1e-7
     n_exit_bins: int = 1000
+    langevin_on: int = 0          # hybrid Langevin branch
+    lv_z_lo: float = 0.0          # axial window [lv_z_lo, lv_z_hi); none when lv_z_hi <= lv_z_lo
+    lv_z_hi: float = 0.0
+    lv_switch: float = 0.05       # switch when lambda dt >= lv_switch
 
 
 @dataclasses.dataclass
