@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 1
+#define MC_ABI_VERSION 2
 
 enum {
     MC_OK = 0,
@@ -145,12 +145,24 @@ typedef struct mc_source {
  * v_off scales the DC-offset basis; collisions_on enables the collision
  * step; sc_on/sc_every: deposit + Poisson + field every sc_every steps;
  * z_det/r_det: detector plane and radius; d_hit: electrode hit distance;
- * exit current (Eq. 8) is binned in n_exit_bins bins of exit_bin_dt. */
+ * exit current (Eq. 8) is binned in n_exit_bins bins of exit_bin_dt.
+ *
+ * Hybrid Langevin branch (collision section; Ermak-Buckholz): with
+ * langevin_on, a pack whose post-push z lies in [lv_z_lo, lv_z_hi) (any z
+ * when lv_z_hi <= lv_z_lo) and whose candidate rate lambda = n sigma (s +
+ * abar) satisfies lambda dt >= lv_switch (the paper's switch is 0.05) skips
+ * the explicit events of the step: its velocity relaxes toward the local
+ * gas velocity by the exact Ornstein-Uhlenbeck update over dt with the
+ * hard-sphere friction rate gamma = (16/3)(n sigma/m) sqrt(mu kB T/(2 pi)),
+ * and its internal energy and hazard are left unchanged for that step.
+ * lv_switch must be >= 0 when the branch is on (MC_EINVAL otherwise). */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
     int32_t collisions_on, sc_on, sc_every;
     double z_det, r_det, d_hit, exit_bin_dt;
     int32_t n_exit_bins;
+    int32_t langevin_on;
+    double lv_z_lo, lv_z_hi, lv_switch;
 } mc_operating;
 
 /* Pack population (host arrays of length n) for snapshot read/write.
@@ -175,12 +187,13 @@ typedef struct mc_packs {
  * act_hist_* histogram the active population at read time.
  * n_cand/n_coll: collision candidates and accepted collisions; n_cap: pack
  * steps that hit the candidate cap; n_clamp: internal-energy clamps;
- * pack_steps: sum over steps of the active packs advanced.
+ * pack_steps: sum over steps of the active packs advanced; n_langevin:
+ * pack steps taken by the hybrid Langevin branch.
  * sum_w_*: FP64 sums, reduced in a fixed order (run-to-run identical). */
 typedef struct mc_tallies {
     int64_t emitted_n, emitted_w;
     int64_t class_n[MC_NCLASS], class_w[MC_NCLASS];
-    int64_t n_cand, n_coll, n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped;
+    int64_t n_cand, n_coll, n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, n_langevin;
     double sum_w_ke_active, sum_w_eint_active, sum_w_dissoc_terminal;
     int64_t *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r, *act_hist_ke, *act_hist_teff;
 } mc_tallies;

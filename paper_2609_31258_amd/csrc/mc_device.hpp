@@ -27,7 +27,7 @@ enum : int32_t { ST_ACTIVE = 0, ST_TRANSMITTED = 1, ST_ELECTRODE = 2, ST_RADIAL 
 // constants 0x9E3779B9 / 0xBB67AE85 after each round.  The key is uniform
 // across a wavefront, so the key schedule lives in scalar registers.
 // Stream layout: counter = (pack id low 32, step, purpose << 24 | block,
-// pack id high 32); purpose 0 = emission, 1 = collisions.
+// pack id high 32); purpose 0 = emission, 1 = collisions, 2 = Langevin.
 // ---------------------------------------------------------------------------
 struct W4 {
     uint32_t w0, w1, w2, w3;
@@ -50,7 +50,7 @@ __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     return W4{c0, c1, c2, c3};
 }
 
-constexpr uint32_t kPurposeEmit = 0u, kPurposeCollide = 1u;
+constexpr uint32_t kPurposeEmit = 0u, kPurposeCollide = 1u, kPurposeLangevin = 2u;
 
 __device__ __forceinline__ W4 draw(int64_t id, int64_t step, uint32_t purpose, uint32_t block, uint32_t k0,
                                    uint32_t k1) {

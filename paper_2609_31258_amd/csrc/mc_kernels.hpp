@@ -36,7 +36,7 @@ struct PackPtrs {
 // int64 tally block.  Layout of cnt: class_n[6], class_w[6], n_cand, n_coll,
 // n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, exit_count.
 enum { TC_CLASS_N = 0, TC_CLASS_W = 6, TC_CAND = 12, TC_COLL = 13, TC_CAP = 14, TC_CLAMP = 15, TC_PACKSTEPS = 16,
-       TC_EXOVER = 17, TC_EXDROP = 18, TC_EXCOUNT = 19, TC_N = 20 };
+       TC_EXOVER = 17, TC_EXDROP = 18, TC_EXCOUNT = 19, TC_LANG = 20, TC_N = 21 };
 
 struct TallyPtrs {
     unsigned long long *cnt, *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r;
@@ -178,6 +178,8 @@ struct StepArgs {
     double dt, t0, c0, ch, c1;      // c = V_RF cos(2 pi f t + phase) at t0, t0 + dt/2, t0 + dt
     double z_det, r_det, R, inv_dr, inv_dz, mg, exit_bin_dt;
     int32_t nr, nz, n_exit_bins, collisions_on;
+    int32_t langevin_on;
+    double lv_z_lo, lv_z_hi, lv_switch;
     uint32_t k0, k1;
 };
 
@@ -243,14 +245,14 @@ __device__ __forceinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s
 }
 
 struct StepCount {
-    uint64_t cand, acc, cap, clamp, act;
+    uint64_t cand, acc, cap, clamp, act, lang;
 };
 
 // One pack, one step.
 template <class P, class Tab>
 __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n) {
     using T = typename P::T;
-    uint64_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0;
+    uint64_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0;
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
         n.act = 1;
         const Species sp = a.sp[a.p.tag[s]];
@@ -329,6 +331,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         }
         }
 
+        bool lang = false;
         if (cls == ST_ACTIVE && a.collisions_on) {
             // ---- collisions with the gas at the new position ----
             const T rr = (T)r1;
@@ -347,12 +350,32 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 T rx = vx - ux, ry = vy - uy, rz = vz - uz;
                 T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
                 T lam = ngs * (sv + abar);
+                lang = a.langevin_on && (!(a.lv_z_hi > a.lv_z_lo) || (Z1 >= a.lv_z_lo && Z1 < a.lv_z_hi)) &&
+                       lam * dt >= (T)a.lv_switch;
+                if (lang) {
+                    // hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward the gas
+                    // velocity over dt, hard-sphere friction rate, Box-Muller normals from one block
+                    const W4 w = draw(a.p.id[s], a.step, kPurposeLangevin, 0u, a.k0, a.k1);
+                    const T r0 = P::sqrt_((T)-2 * P::ln(P::u01(w.w0)));
+                    const T r1 = P::sqrt_((T)-2 * P::ln(P::u01(w.w2)));
+                    T s0, c0;
+                    P::sc2pi(P::u01(w.w1), &s0, &c0);
+                    const T c1 = P::cos2pi(P::u01(w.w3));
+                    const T ktm = P::div((T)kB * tg, m);  // kB T / m (no underflow in FP32)
+                    const T gam = (T)(16.0 / 3.0) * ngs * P::sqrt_(fm * ktm * (T)0.15915494309189535);
+                    const T f = P::exp_(-gam * dt);
+                    const T sd = P::sqrt_(ktm * ((T)1 - f * f));
+                    vx = ux + (vx - ux) * f + sd * (r0 * c0);
+                    vy = uy + (vy - uy) * f + sd * (r0 * s0);
+                    vz = uz + (vz - uz) * f + sd * (r1 * c1);
+                    ++nlang;
+                }
                 // candidate cap; a non-finite rate ends the loop at once
-                const T nexp = lam * dt;
+                const T nexp = lang ? (T)0 : lam * dt;
                 const int64_t cap = (nexp < (T)1e6) ? 64 + 8 * (int64_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
-                T tleft = dt;
+                T tleft = lang ? (T)0 : dt;
                 const int64_t id = a.p.id[s];
-                for (int64_t c = 0;; ++c) {
+                for (int64_t c = 0; !lang; ++c) {
                     if (c == cap) {
                         ++ncap;
                         break;
@@ -418,8 +441,11 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
 
         if (cls == ST_ACTIVE) {
             // ---- Eq. 7: hazard with the post-collision effective temperature ----
-            const T te = einstein_t<P>(e + el, (T)sp.skt, (T)sp.theta);
-            a.p.h[s] = a.p.h[s] + rate<P>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * dt;
+            // (not accumulated in an aggregated Langevin step)
+            if (!lang) {
+                const T te = einstein_t<P>(e + el, (T)sp.skt, (T)sp.theta);
+                a.p.h[s] = a.p.h[s] + rate<P>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * dt;
+            }
             a.p.e[s] = e;
             if constexpr (P::kTwo) a.p.el[s] = el;
         } else {
@@ -443,24 +469,27 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
     n.acc = nacc;
     n.cap = ncap;
     n.clamp = nclamp;
+    n.lang = nlang;
 }
 
 // Wavefront-aggregated counters (every lane of the block's query calls this).
 __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount &n) {
     const uint64_t sc = wave_sum_u64(n.cand), sa = wave_sum_u64(n.acc);
     const uint64_t sp_ = wave_sum_u64(n.cap), sl = wave_sum_u64(n.clamp), sn = wave_sum_u64(n.act);
+    const uint64_t sg = wave_sum_u64(n.lang);
     if ((threadIdx.x & 63) == 0) {
         if (sn) atomicAdd(&t.cnt[TC_PACKSTEPS], (unsigned long long)sn);
         if (sc) atomicAdd(&t.cnt[TC_CAND], (unsigned long long)sc);
         if (sa) atomicAdd(&t.cnt[TC_COLL], (unsigned long long)sa);
         if (sp_) atomicAdd(&t.cnt[TC_CAP], (unsigned long long)sp_);
         if (sl) atomicAdd(&t.cnt[TC_CLAMP], (unsigned long long)sl);
+        if (sg) atomicAdd(&t.cnt[TC_LANG], (unsigned long long)sg);
     }
 }
 
 template <class P, class Tab>
 __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
-    StepCount n{0, 0, 0, 0, 0};
+    StepCount n{0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n);
     flush_counts(a.t, n);
 }
@@ -472,7 +501,7 @@ __global__ __launch_bounds__(256) void k_step_multi(const StepArgs<P, Tab> *desc
                                                     int32_t nq) {
     const int q = block_query(prefix, nq);
     const StepArgs<P, Tab> &a = descs[q];
-    StepCount n{0, 0, 0, 0, 0};
+    StepCount n{0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n);
     flush_counts(a.t, n);
 }

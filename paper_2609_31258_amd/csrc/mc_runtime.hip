@@ -314,6 +314,10 @@ static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     a.nz = ctx->nz;
     a.n_exit_bins = op.n_exit_bins;
     a.collisions_on = op.collisions_on;
+    a.langevin_on = op.langevin_on;
+    a.lv_z_lo = op.lv_z_lo;
+    a.lv_z_hi = op.lv_z_hi;
+    a.lv_switch = op.lv_switch;
     a.k0 = (uint32_t)ctx->opt.seed;
     a.k1 = (uint32_t)(ctx->opt.seed >> 32);
     Timer t(ctx, MC_K_STEP);
@@ -636,7 +640,8 @@ int32_t mc_define_ion(mc_ctx *ctx, const mc_ion *ion, int32_t *ion_id) {
 int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
     if (!ctx) return MC_EINVAL;
     if (!op || !(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1 || !(op->exit_bin_dt > 0) ||
-        !(op->gas_mass_da > 0) || !(op->r_det > 0) || !(op->d_hit >= 0))
+        !(op->gas_mass_da > 0) || !(op->r_det > 0) || !(op->d_hit >= 0) ||
+        (op->langevin_on && !(op->lv_switch >= 0)))
         return fail(ctx, MC_EINVAL, "invalid operating point");
     if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "load fields first");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -776,6 +781,7 @@ int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out) {
     out->pack_steps = (int64_t)cnt[TC_PACKSTEPS];
     out->exit_overflow = (int64_t)cnt[TC_EXOVER];
     out->exit_dropped = (int64_t)cnt[TC_EXDROP];
+    out->n_langevin = (int64_t)cnt[TC_LANG];
     out->sum_w_ke_active = sums[0];
     out->sum_w_eint_active = sums[1];
     out->sum_w_dissoc_terminal = sums[2];

@@ -416,6 +416,10 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
             a.nz = S->nz;
             a.n_exit_bins = op.n_exit_bins;
             a.collisions_on = op.collisions_on;
+            a.langevin_on = op.langevin_on;
+            a.lv_z_lo = op.lv_z_lo;
+            a.lv_z_hi = op.lv_z_hi;
+            a.lv_switch = op.lv_switch;
             a.k0 = (uint32_t)Q.q.seed;
             a.k1 = (uint32_t)(Q.q.seed >> 32);
             ps[ns] = bs;
@@ -479,6 +483,7 @@ static int32_t retire_query(mc_server *S, Query &Q, PackPtrs<T> p) {
     r.pack_steps = (int64_t)tal[TC_PACKSTEPS];
     r.exit_overflow = (int64_t)tal[TC_EXOVER];
     r.exit_dropped = (int64_t)tal[TC_EXDROP];
+    r.n_langevin = (int64_t)tal[TC_LANG];
     r.sum_w_ke_active = sums[0];
     r.sum_w_eint_active = sums[1];
     r.sum_w_dissoc_terminal = sums[2];
@@ -776,6 +781,7 @@ static bool valid_query(const mc_server *S, const mc_query *q) {
     if (!q || !valid_ion(&q->ion) || q->n_steps < 0) return false;
     const mc_operating &op = q->op;
     if (!(op.dt > 0) || op.sc_every < 1 || op.n_exit_bins < 1 || !(op.exit_bin_dt > 0) || !(op.r_det > 0)) return false;
+    if (op.langevin_on && !(op.lv_switch >= 0)) return false;
     const mc_source &s = q->source;
     if (s.kind < 0 || s.kind > 2 || !(s.sigma_r > 0) || !(s.r_trunc > 0) || s.n_total < 0) return false;
     if ((s.kind == 1 && s.packs_per_step <= 0) || (s.kind != 1 && !(s.weight > 0))) return false;

@@ -23,6 +23,7 @@ PD, PI64, PI32, PU8 = C.POINTER(F64), C.POINTER(I64), C.POINTER(I32), C.POINTER(
 
 MC_OK, MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE, MC_ENUMERIC, MC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PREC_FP64, PREC_FP32 = 0, 1
+ABI_VERSION = 2
 NCLASS = 6
 HIST_KE, HIST_TEFF, HIST_R = 202, 202, 102
 K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY = range(6)
@@ -60,7 +61,8 @@ class Source(C.Structure):
 class Operating(C.Structure):
     _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
-                ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32)]
+                ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
+                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64)]
 
 
 class Packs(C.Structure):
@@ -71,7 +73,7 @@ class Packs(C.Structure):
 class Tallies(C.Structure):
     _fields_ = [("emitted_n", I64), ("emitted_w", I64), ("class_n", I64 * NCLASS), ("class_w", I64 * NCLASS),
                 ("n_cand", I64), ("n_coll", I64), ("n_cap", I64), ("n_clamp", I64), ("pack_steps", I64),
-                ("exit_overflow", I64), ("exit_dropped", I64),
+                ("exit_overflow", I64), ("exit_dropped", I64), ("n_langevin", I64),
                 ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
                 ("exit_bins", PI64), ("loss_map", PI64), ("hist_ke", PI64), ("hist_teff", PI64), ("hist_r", PI64),
                 ("act_hist_ke", PI64), ("act_hist_teff", PI64)]
@@ -177,7 +179,7 @@ def load_library():
         fn = getattr(L, name)
         fn.restype = res
         fn.argtypes = args
-    if L.mc_abi_version() != 1:
+    if L.mc_abi_version() != ABI_VERSION:
         raise RuntimeError("ABI version mismatch")
     _LIB = L
     return L
@@ -364,7 +366,7 @@ class Sim:
         self._chk(self.L.mc_read_tallies(self._h, C.byref(T)), "mc_read_tallies")
         out = dict(bufs)
         for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "pack_steps", "exit_overflow",
-                  "exit_dropped", "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
+                  "exit_dropped", "n_langevin", "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
             out[k] = getattr(T, k)
         out["class_n"] = np.array(list(T.class_n), np.int64)
         out["class_w"] = np.array(list(T.class_w), np.int64)
@@ -490,7 +492,7 @@ class Server:
             T = r.tallies
             tal = dict(bufs)
             for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "pack_steps",
-                      "exit_overflow", "exit_dropped", "sum_w_ke_active", "sum_w_eint_active",
+                      "exit_overflow", "exit_dropped", "n_langevin", "sum_w_ke_active", "sum_w_eint_active",
                       "sum_w_dissoc_terminal"):
                 tal[k] = getattr(T, k)
             tal["class_n"] = np.array(list(T.class_n), np.int64)
