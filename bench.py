@@ -11,7 +11,8 @@ fills the population to 1e6 packs); then exactly `steps` steps are timed
 with the device synchronised on both sides.  value = active pack-steps
 advanced in the timed window / wall seconds, FP64 path; the FP32 form
 (FP32 math, BF16 tables, two-float positions) is timed the same way and
-reported beside it.
+reported beside it, and so is the hybrid form (the FP32 form with the
+Langevin branch taking the dense first millimetre).
 
 Also reported: the dominant kernel's roofline (HIP events around every
 launch of the fused step kernel), and the CPU oracle's rate on a bounded
@@ -50,6 +51,18 @@ OPS_CANDIDATE = 276       # every candidate inside the step: two Philox blocks, 
 OPS_ACCEPTED = 161        # accepted candidate: third block, impulsive update, scattering
 OPS_EXCHANGE = 18         # internal-energy exchange (taken with probability alpha)
 
+# Algorithmic HBM bytes per active pack-step of the fused step kernel: read
+# status, tag, id, position, velocity, internal energy and hazard; write back
+# position, velocity, internal energy and hazard.  FP64: 80 + 64 B.  FP32 form
+# (two-float position and internal energy, FP32 velocity and hazard):
+# 64 + 48 B.  An inactive slot costs its status word (4 B).
+BYTES_STEP = {"fp64": 144, "fp32": 112}
+# Deposit: status, position (FP64, or the FP32 form's hi+lo pairs) and the
+# int64 charge of every active pack (the LDS-aggregated grid atomics are
+# counted as L2 traffic, not HBM).
+BYTES_DEPOSIT = {"fp64": 36, "fp32": 36}
+HBM_PEAK = 8.0e12
+
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_traffic.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_31258_amd", "csrc", f) for f in ("mc_kernels.hpp", "mc_device.hpp")]
 
@@ -83,7 +96,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=2000)
-    ap.add_argument("--precision", choices=["fp64", "fp32", "both"], default="both")
+    ap.add_argument("--forms", default="fp64,fp32,hybrid",
+                    help="comma list of the forms to time: fp64 (plain FP64 path), fp32 (FP32 math, BF16 tables, "
+                         "two-float positions), hybrid (FP32 form with the Langevin branch in 0-1 mm)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packs", type=int, default=400_000)
     ap.add_argument("--cpu-steps", type=int, default=20)
@@ -103,10 +118,12 @@ def parse():
     return ap.parse_args()
 
 
-def run_gpu(precision: int, steps: int, warmup: int):
+def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False):
     import torch
     from paper_2609_31258_amd import mucite, synth
     f, ions, srcs, op, _ = synth.config_c2()
+    if langevin:  # hybrid form: aggregated relaxation in the dense first millimetre
+        op.langevin_on, op.lv_z_lo, op.lv_z_hi, op.lv_switch = 1, 0.0, 1e-3, 0.05
     sim = mucite.Sim(seed=synth.SEED, pack_capacity=srcs[0].n_total, precision=precision, timing=True)
     sim.setup(f, ions, srcs, op)
     t0 = time.time()
@@ -116,7 +133,7 @@ def run_gpu(precision: int, steps: int, warmup: int):
         sim.step(k)
         sim.synchronize()
         done += k
-        print(f"[bench] {'fp64' if precision == 0 else 'fp32'} warmup {done}/{warmup} "
+        print(f"[bench] {'fp64' if precision == 0 else 'fp32'}{' hybrid' if langevin else ''} warmup {done}/{warmup} "
               f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
     sim.reset_timing()
     before = sim.read_tallies()
@@ -135,7 +152,24 @@ def run_gpu(precision: int, steps: int, warmup: int):
     cand = after["n_cand"] - before["n_cand"]
     coll = after["n_coll"] - before["n_coll"]
     return dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim, slots=info["n_slots"],
-                active=int(after["class_n"][0]), classes=after["class_n"].tolist(), tallies=after)
+                active=int(after["class_n"][0]), classes=after["class_n"].tolist(), tallies=after,
+                langevin=after["n_langevin"] - before["n_langevin"], steps=steps)
+
+
+def hbm_roofline(r, precision: str, kernel: str):
+    """HBM roofline of a bandwidth-bound kernel from its algorithmic bytes."""
+    key = {"step": "step", "deposit": "deposit"}[kernel]
+    ms, launches = r["timing"]["ms"][key], max(r["timing"]["launches"][key], 1)
+    avg_s = ms / 1e3 / launches
+    if kernel == "step":
+        idle = max(r["slots"] * r["steps"] - r["pack_steps"], 0)
+        nbytes = (r["pack_steps"] * BYTES_STEP[precision] + 4 * idle) / launches
+    else:
+        nbytes = r["active"] * BYTES_DEPOSIT[precision]  # population is nearly constant in the window
+    achieved = nbytes / avg_s if avg_s > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK, "traffic": None, "kernel": kernel, "avg_launch_ms": avg_s * 1e3,
+            "launches": launches, "bytes_per_launch": nbytes}
 
 
 def run_large(fill_steps: int, steps: int, n_packs: int = 16_000_000):
@@ -323,11 +357,17 @@ def main():
     if args.copy_calibration:
         copy_calibration()
     res = {}
-    if args.precision in ("fp64", "both"):
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    if not forms or any(f not in ("fp64", "fp32", "hybrid") for f in forms):
+        print(json.dumps({"error": f"unknown form list {args.forms!r}"}))
+        sys.exit(2)
+    if "fp64" in forms:
         res["fp64"] = run_gpu(0, args.steps, args.warmup)
-    if args.precision in ("fp32", "both"):
+    if "fp32" in forms:
         res["fp32"] = run_gpu(1, args.steps, args.warmup)
-    main_key = "fp64" if "fp64" in res else "fp32"
+    if "hybrid" in forms:
+        res["hybrid"] = run_gpu(1, args.steps, args.warmup, langevin=True)
+    main_key = "fp64" if "fp64" in res else ("fp32" if "fp32" in res else "hybrid")
     r = res[main_key]
     value = r["pack_steps"] / r["wall"]
     out = {
@@ -337,7 +377,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "grid": [256, 1024], "packs": r["slots"], "active": r["active"],
                    "sc_every": 10, "dt_s": 0.5e-9, "precision": main_key},
-        "roofline": roofline(r, main_key, default_alpha()),
+        "roofline": hbm_roofline(r, "fp32", "step") if main_key == "hybrid" else roofline(r, main_key, default_alpha()),
         "collisions_per_s": r["coll"] / r["wall"],
         "candidates_per_pack_step": r["cand"] / max(r["pack_steps"], 1),
         "kernel_ms": r["timing"]["ms"],
@@ -349,6 +389,17 @@ def main():
                             "speedup_vs_fp64": (q["pack_steps"] / q["wall"]) / value,
                             "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"],
                             "error_vs_fp64": precision_report(r["tallies"], q["tallies"])}
+    if "fp32" in res:
+        out["deposit_roofline_fp32"] = hbm_roofline(res["fp32"], "fp32", "deposit")
+    if "hybrid" in res and main_key != "hybrid":
+        h = res["hybrid"]
+        ref = res.get("fp32")
+        out["hybrid_form"] = {"value": h["pack_steps"] / h["wall"], "unit": "pack-steps/s",
+                              "ms_per_step": h["wall"] * 1e3 / args.steps, "dtype": "f32 (BF16 tables)",
+                              "langevin_fraction": h["langevin"] / max(h["pack_steps"], 1),
+                              "speedup_vs_explicit_fp32": (h["pack_steps"] / h["wall"]) / (ref["pack_steps"] / ref["wall"])
+                              if ref else None,
+                              "roofline": hbm_roofline(h, "fp32", "step"), "kernel_ms": h["timing"]["ms"]}
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)

@@ -38,8 +38,26 @@ struct PackPtrs {
 enum { TC_CLASS_N = 0, TC_CLASS_W = 6, TC_CAND = 12, TC_COLL = 13, TC_CAP = 14, TC_CLAMP = 15, TC_PACKSTEPS = 16,
        TC_EXOVER = 17, TC_EXDROP = 18, TC_EXCOUNT = 19, TC_LANG = 20, TC_N = 21 };
 
+// Per-step event counters (pack steps, candidates, collisions, caps, clamps,
+// Langevin steps): each block adds its totals to one of kHotRep replicas,
+// one 128-byte line each, so concurrent blocks rarely update the same
+// address; readers add the replicas into the counters (fold_hot).
+enum { HOT_PACKSTEPS = 0, HOT_CAND = 1, HOT_COLL = 2, HOT_CAP = 3, HOT_CLAMP = 4, HOT_LANG = 5, HOT_N = 6 };
+constexpr int kHotRep = 128, kHotStride = 16;
+constexpr int64_t kHotLen = (int64_t)kHotRep * kHotStride;
+
+// Offset of the replicated counters in a tally array whose other regions
+// take `base` words (rounded up to whole 128-byte lines).
+inline int64_t hot_offset(int64_t base) { return (base + kHotStride - 1) / kHotStride * kHotStride; }
+
+inline void fold_hot(const unsigned long long *hot, unsigned long long *cnt) {
+    static const int to[HOT_N] = {TC_PACKSTEPS, TC_CAND, TC_COLL, TC_CAP, TC_CLAMP, TC_LANG};
+    for (int r = 0; r < kHotRep; ++r)
+        for (int k = 0; k < HOT_N; ++k) cnt[to[k]] += hot[(int64_t)r * kHotStride + k];
+}
+
 struct TallyPtrs {
-    unsigned long long *cnt, *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r;
+    unsigned long long *cnt, *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r, *hot;
     mc_exit_rec *exits;
     int64_t exit_cap;
 };
@@ -252,7 +270,7 @@ struct StepCount {
 template <class P, class Tab>
 __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n) {
     using T = typename P::T;
-    uint64_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0;
+    uint32_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0;  // per pack and step: < 2^32
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
         n.act = 1;
         const Species sp = a.sp[a.p.tag[s]];
@@ -331,6 +349,15 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         }
         }
 
+        // the position is final: store it now so it is not held through the collision loop
+        a.p.x[s] = x1;
+        a.p.y[s] = y1;
+        a.p.z[s] = z1;
+        if constexpr (P::kTwo) {
+            a.p.xl[s] = xl;
+            a.p.yl[s] = yl;
+            a.p.zl[s] = zl;
+        }
         bool lang = false;
         if (cls == ST_ACTIVE && a.collisions_on) {
             // ---- collisions with the gas at the new position ----
@@ -372,10 +399,10 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 }
                 // candidate cap; a non-finite rate ends the loop at once
                 const T nexp = lang ? (T)0 : lam * dt;
-                const int64_t cap = (nexp < (T)1e6) ? 64 + 8 * (int64_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
+                const int32_t cap = (nexp < (T)1e6) ? 64 + 8 * (int32_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
                 T tleft = lang ? (T)0 : dt;
                 const int64_t id = a.p.id[s];
-                for (int64_t c = 0; !lang; ++c) {
+                for (int32_t c = 0; !lang; ++c) {
                     if (c == cap) {
                         ++ncap;
                         break;
@@ -453,14 +480,6 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                         (double)e + (double)el, (double)a.p.h[s], sp);
             a.p.status[s] = cls;
         }
-        a.p.x[s] = x1;
-        a.p.y[s] = y1;
-        a.p.z[s] = z1;
-        if constexpr (P::kTwo) {
-            a.p.xl[s] = xl;
-            a.p.yl[s] = yl;
-            a.p.zl[s] = zl;
-        }
         a.p.vx[s] = vx;
         a.p.vy[s] = vy;
         a.p.vz[s] = vz;
@@ -472,23 +491,35 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
     n.lang = nlang;
 }
 
-// Wavefront-aggregated counters (every lane of the block's query calls this).
+// Block-aggregated counters: wavefront sums, then LDS, then one atomic per
+// counter and block into the block's replica (every thread of the block
+// calls this; all of a block's threads belong to one query).
 __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount &n) {
-    const uint64_t sc = wave_sum_u64(n.cand), sa = wave_sum_u64(n.acc);
-    const uint64_t sp_ = wave_sum_u64(n.cap), sl = wave_sum_u64(n.clamp), sn = wave_sum_u64(n.act);
-    const uint64_t sg = wave_sum_u64(n.lang);
+    __shared__ unsigned long long red[HOT_N];
+    if (threadIdx.x < HOT_N) red[threadIdx.x] = 0ull;
+    __syncthreads();
+    const uint64_t v[HOT_N] = {wave_sum_u64(n.act), wave_sum_u64(n.cand), wave_sum_u64(n.acc),
+                               wave_sum_u64(n.cap), wave_sum_u64(n.clamp), wave_sum_u64(n.lang)};
     if ((threadIdx.x & 63) == 0) {
-        if (sn) atomicAdd(&t.cnt[TC_PACKSTEPS], (unsigned long long)sn);
-        if (sc) atomicAdd(&t.cnt[TC_CAND], (unsigned long long)sc);
-        if (sa) atomicAdd(&t.cnt[TC_COLL], (unsigned long long)sa);
-        if (sp_) atomicAdd(&t.cnt[TC_CAP], (unsigned long long)sp_);
-        if (sl) atomicAdd(&t.cnt[TC_CLAMP], (unsigned long long)sl);
-        if (sg) atomicAdd(&t.cnt[TC_LANG], (unsigned long long)sg);
+#pragma unroll
+        for (int k = 0; k < HOT_N; ++k)
+            if (v[k]) atomicAdd(&red[k], (unsigned long long)v[k]);
     }
+    __syncthreads();
+    if (threadIdx.x < HOT_N && red[threadIdx.x])
+        atomicAdd(&t.hot[(int64_t)(blockIdx.x & (kHotRep - 1)) * kHotStride + threadIdx.x], red[threadIdx.x]);
+}
+
+// Waves per SIMD the step kernel is compiled for (its register budget):
+// the FP64 form holds its loop state in register pairs and fits three
+// waves; the FP32 form with BF16 tables fits five without spilling.
+template <class P, class Tab>
+constexpr int step_waves() {
+    return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 3;
 }
 
 template <class P, class Tab>
-__global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
+__global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
     StepCount n{0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n);
     flush_counts(a.t, n);
@@ -497,7 +528,7 @@ __global__ __launch_bounds__(256) void k_step(StepArgs<P, Tab> a) {
 // All resident queries of a server advance one step in one launch; each
 // block belongs to one query (descriptors in device memory).
 template <class P, class Tab>
-__global__ __launch_bounds__(256) void k_step_multi(const StepArgs<P, Tab> *descs, const int32_t *prefix,
+__global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(const StepArgs<P, Tab> *descs, const int32_t *prefix,
                                                     int32_t nq) {
     const int q = block_query(prefix, nq);
     const StepArgs<P, Tab> &a = descs[q];
@@ -526,6 +557,11 @@ struct DepositArgs {
 // removes almost all contention on the global grid; integer sums make the
 // result independent of the order.
 constexpr int kDepHash = 2048;
+// Grid of the deposit: one block per CU.  Every block flushes one device
+// atomic per distinct node it saw, and the packs of a step crowd into a few
+// hundred nodes, so the flush is bound by same-address atomics; more blocks
+// than CUs only add flushes.
+constexpr int64_t kDepositBlocks = 256;
 
 __device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
                                            int32_t node, int64_t v) {

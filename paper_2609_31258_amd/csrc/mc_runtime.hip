@@ -349,7 +349,7 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
             a.inv_dz = ctx->inv_dz;
             a.nr = ctx->nr;
             a.nz = ctx->nz;
-            const unsigned nb = (unsigned)std::min<int64_t>(grid_for(ctx->n_slots), kAggBlocks);
+            const unsigned nb = (unsigned)std::min<int64_t>(grid_for(ctx->n_slots), kDepositBlocks);
             k_deposit<P><<<nb, kBlock, 0, ctx->stream>>>(a);
             LAUNCHCHK();
         }
@@ -655,7 +655,8 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
     if (rc) return rc;
     const int64_t nn = (int64_t)ctx->nr * ctx->nz;
     if (first) {
-        ctx->tal_len = TC_N + op->n_exit_bins + nn + MC_HIST_KE + MC_HIST_TEFF + MC_HIST_R;
+        const int64_t base = TC_N + op->n_exit_bins + nn + MC_HIST_KE + MC_HIST_TEFF + MC_HIST_R;
+        ctx->tal_len = hot_offset(base) + kHotLen;
         rc = dalloc_t(ctx, &ctx->tal, ctx->tal_len);
         if (rc) return rc;
         HIPCHK(hipMemsetAsync(ctx->tal, 0, ctx->tal_len * sizeof(unsigned long long), ctx->stream));
@@ -671,6 +672,7 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
         ctx->tp.hist_teff = p;
         p += MC_HIST_TEFF;
         ctx->tp.hist_r = p;
+        ctx->tp.hot = ctx->tal + hot_offset(base);
     }
     const double reach = op->d_hit + 0.5 * std::min(ctx->dr, ctx->dz);
     const int32_t wi = (int32_t)std::ceil(reach / ctx->dr), wj = (int32_t)std::ceil(reach / ctx->dz);
@@ -761,9 +763,11 @@ int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out) {
     int32_t rc = ctx->fp32() ? snapshot_t<float>(ctx, ctx->p32) : snapshot_t<double>(ctx, ctx->p64);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(ctx->stream));
-    std::vector<unsigned long long> cnt(TC_N), snap(2 + MC_HIST_KE + MC_HIST_TEFF);
+    std::vector<unsigned long long> cnt(TC_N), hot(kHotLen), snap(2 + MC_HIST_KE + MC_HIST_TEFF);
     double sums[3];
     HIPCHK(hipMemcpy(cnt.data(), ctx->tp.cnt, TC_N * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(hot.data(), ctx->tp.hot, kHotLen * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    fold_hot(hot.data(), cnt.data());
     HIPCHK(hipMemcpy(snap.data(), ctx->snap, snap.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
     HIPCHK(hipMemcpy(sums, ctx->sums, 3 * sizeof(double), hipMemcpyDeviceToHost));
     out->emitted_n = ctx->emitted_n;
@@ -962,9 +966,12 @@ int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out) {
         out->ms[k] = ctx->t_ms[k];
         out->launches[k] = ctx->t_launch[k];
     }
-    unsigned long long ps = 0;
-    if (ctx->tp.cnt) HIPCHK(hipMemcpy(&ps, ctx->tp.cnt + TC_PACKSTEPS, 8, hipMemcpyDeviceToHost));
-    out->pack_steps = (int64_t)ps;
+    std::vector<unsigned long long> cnt(TC_N, 0ull), hot(kHotLen);
+    if (ctx->tp.hot) {
+        HIPCHK(hipMemcpy(hot.data(), ctx->tp.hot, kHotLen * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+        fold_hot(hot.data(), cnt.data());
+    }
+    out->pack_steps = (int64_t)cnt[TC_PACKSTEPS];
     return MC_OK;
 }
 

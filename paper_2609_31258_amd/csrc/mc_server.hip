@@ -174,7 +174,7 @@ static int64_t query_layout(const mc_server *S, const Query &Q, F &&place) {
         place("qgrid", 0, L.take(nn * 8));
         place("bh", 0, L.take((int64_t)nu * m * fsz));
     }
-    const int64_t tal_len = TC_N + Q.q.op.n_exit_bins + nn + MC_HIST_KE + MC_HIST_TEFF + MC_HIST_R;
+    const int64_t tal_len = hot_offset(TC_N + Q.q.op.n_exit_bins + nn + MC_HIST_KE + MC_HIST_TEFF + MC_HIST_R) + kHotLen;
     place("tal", tal_len, L.take(tal_len * 8));
     place("snap", 0, L.take((2 + MC_HIST_KE + MC_HIST_TEFF) * 8));
     const int64_t pl = std::max<int64_t>(1, std::min<int64_t>(blocks_for(cap), kAggMax));
@@ -257,6 +257,7 @@ static void bind_query(mc_server *S, Query &Q) {
     Q.tp.hist_teff = p;
     p += MC_HIST_TEFF;
     Q.tp.hist_r = p;
+    Q.tp.hot = Q.tal + (Q.tal_len - kHotLen);
     Q.tp.exit_cap = std::max<int64_t>(Q.q.exit_capacity, 0);
 }
 
@@ -305,7 +306,7 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         a.inv_dz = S->inv_dz;
         a.nr = S->nr;
         a.nz = S->nz;
-        k_deposit<P><<<(unsigned)std::min<int64_t>(blocks_for(Q.n_slots), kAggMax), kBlk, 0, S->stream>>>(a);
+        k_deposit<P><<<(unsigned)std::min<int64_t>(blocks_for(Q.n_slots), kDepositBlocks), kBlk, 0, S->stream>>>(a);
     }
     D *bh = static_cast<D *>(Q.bh);
     const Bluestein &B = S->blu;
@@ -467,6 +468,7 @@ static int32_t retire_query(mc_server *S, Query &Q, PackPtrs<T> p) {
     SCHK(hipMemcpyAsync(snap.data(), Q.snap, ns * 8, hipMemcpyDeviceToHost, S->stream));
     SCHK(hipMemcpyAsync(sums, Q.sums, 4 * 8, hipMemcpyDeviceToHost, S->stream));
     SCHK(hipStreamSynchronize(S->stream));
+    fold_hot(tal.data() + (Q.tal_len - kHotLen), tal.data());
     mc_tallies &r = Q.r;
     r.emitted_n = Q.emitted_n;
     r.emitted_w = Q.emitted_w;
