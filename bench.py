@@ -156,7 +156,7 @@ def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False):
                 langevin=after["n_langevin"] - before["n_langevin"], steps=steps)
 
 
-def hbm_roofline(r, precision: str, kernel: str):
+def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
     """HBM roofline of a bandwidth-bound kernel from its algorithmic bytes."""
     key = {"step": "step", "deposit": "deposit"}[kernel]
     ms, launches = r["timing"]["ms"][key], max(r["timing"]["launches"][key], 1)
@@ -168,7 +168,8 @@ def hbm_roofline(r, precision: str, kernel: str):
         nbytes = r["active"] * BYTES_DEPOSIT[precision]  # population is nearly constant in the window
     achieved = nbytes / avg_s if avg_s > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK, "traffic": None, "kernel": kernel, "avg_launch_ms": avg_s * 1e3,
+            "frac": achieved / HBM_PEAK, "traffic": measured_traffic(traffic_key) if traffic_key else None,
+            "kernel": kernel, "avg_launch_ms": avg_s * 1e3,
             "launches": launches, "bytes_per_launch": nbytes}
 
 
@@ -377,7 +378,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "grid": [256, 1024], "packs": r["slots"], "active": r["active"],
                    "sc_every": 10, "dt_s": 0.5e-9, "precision": main_key},
-        "roofline": hbm_roofline(r, "fp32", "step") if main_key == "hybrid" else roofline(r, main_key, default_alpha()),
+        "roofline": hbm_roofline(r, "fp32", "step", "hybrid") if main_key == "hybrid" else roofline(r, main_key, default_alpha()),
         "collisions_per_s": r["coll"] / r["wall"],
         "candidates_per_pack_step": r["cand"] / max(r["pack_steps"], 1),
         "kernel_ms": r["timing"]["ms"],
@@ -390,7 +391,7 @@ def main():
                             "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"],
                             "error_vs_fp64": precision_report(r["tallies"], q["tallies"])}
     if "fp32" in res:
-        out["deposit_roofline_fp32"] = hbm_roofline(res["fp32"], "fp32", "deposit")
+        out["deposit_roofline_fp32"] = hbm_roofline(res["fp32"], "fp32", "deposit", "deposit_fp32")
     if "hybrid" in res and main_key != "hybrid":
         h = res["hybrid"]
         ref = res.get("fp32")
@@ -399,7 +400,7 @@ def main():
                               "langevin_fraction": h["langevin"] / max(h["pack_steps"], 1),
                               "speedup_vs_explicit_fp32": (h["pack_steps"] / h["wall"]) / (ref["pack_steps"] / ref["wall"])
                               if ref else None,
-                              "roofline": hbm_roofline(h, "fp32", "step"), "kernel_ms": h["timing"]["ms"]}
+                              "roofline": hbm_roofline(h, "fp32", "step", "hybrid"), "kernel_ms": h["timing"]["ms"]}
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)
