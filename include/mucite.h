@@ -155,7 +155,14 @@ typedef struct mc_source {
  * gas velocity by the exact Ornstein-Uhlenbeck update over dt with the
  * hard-sphere friction rate gamma = (16/3)(n sigma/m) sqrt(mu kB T/(2 pi)),
  * and its internal energy and hazard are left unchanged for that step.
- * lv_switch must be >= 0 when the branch is on (MC_EINVAL otherwise). */
+ * lv_switch must be >= 0 when the branch is on (MC_EINVAL otherwise).
+ *
+ * sc_mask: the space-charge potential also vanishes on the metal-mask nodes
+ * (the space-charge section: zero perturbation potential on the mask,
+ * whose potentials the static field already holds).  Imposed by a
+ * capacitance-matrix correction built at the first such update (one solve
+ * per interior mask node, at most 2048 of them, else MC_EINVAL) and then
+ * applied with one extra solve per update. */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
     int32_t collisions_on, sc_on, sc_every;
@@ -163,6 +170,7 @@ typedef struct mc_operating {
     int32_t n_exit_bins;
     int32_t langevin_on;
     double lv_z_lo, lv_z_hi, lv_switch;
+    int32_t sc_mask;
 } mc_operating;
 
 /* Pack population (host arrays of length n) for snapshot read/write.

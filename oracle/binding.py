@@ -33,7 +33,7 @@ class Operating(C.Structure):
     _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
-                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64)]
+                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32)]
 
 
 class Packs(C.Structure):
@@ -77,6 +77,7 @@ def lib():
         "orc_dst1": (None, [PD, I32, PD]),
         "orc_poisson": (None, [I32, I32, F64, F64, PD, PD]),
         "orc_poisson_residual": (F64, [I32, I32, F64, F64, PD, PD]),
+        "orc_poisson_masked": (I32, [I32, I32, F64, F64, PD, PU8, F64, I32, PD]),
         "orc_rho_from_charge": (None, [I32, I32, F64, F64, PI64, PD]),
         "orc_iict_update": (None, [F64, F64, PD, PD, F64, F64, F64, PD, PD, PD, PD, PI32]),
         "orc_collision_probe": (I32, [F64, F64, F64, F64, F64, PD, PD, F64, I64, U64, C.POINTER(Probe)]),
@@ -172,6 +173,17 @@ def poisson(rho: np.ndarray, dr: float, dz: float) -> np.ndarray:
     phi = np.zeros_like(rho)
     lib().orc_poisson(nr, nz, dr, dz, _p(rho, F64), _p(phi, F64))
     return phi
+
+
+def poisson_masked(rho: np.ndarray, mask: np.ndarray, dr: float, dz: float, tol: float = 1e-13,
+                   max_iter: int = 2000):
+    """Phi with Phi = 0 on the mask nodes; returns (phi, iterations)."""
+    nz, nr = rho.shape
+    rho = _f64(rho)
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    phi = np.zeros((nz, nr))
+    it = lib().orc_poisson_masked(nr, nz, dr, dz, _p(rho, F64), _p(m, C.c_uint8), tol, max_iter, _p(phi, F64))
+    return phi, it
 
 
 def poisson_residual(rho, phi, dr, dz) -> float:

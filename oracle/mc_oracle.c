@@ -223,8 +223,8 @@ void orc_rho_from_charge(int32_t nr, int32_t nz, double dr, double dz, const int
 /*   (A_r Phi)_i + (Phi_{i,j+1} - 2 Phi_{i,j} + Phi_{i,j-1}) / dz^2 = -rho/eps0 */
 /*   (A_r Phi)_0 = 4 (Phi_1 - Phi_0) / dr^2              (disk of radius dr/2) */
 /*   (A_r Phi)_i = [r_{i+1/2}(Phi_{i+1}-Phi_i) - r_{i-1/2}(Phi_i-Phi_{i-1})] / (r_i dr^2) */
-/* Reading: the Dirichlet condition on metal-mask nodes is not imposed       */
-/* (the separable direct solver cannot); see the design notes.              */
+/* This separable direct solver leaves the metal-mask nodes free; the      */
+/* masked problem is orc_poisson_masked below.                              */
 /* Solve: DST-I along z by definition, one tridiagonal system per sine mode  */
 /* with z-eigenvalue -(4/dz^2) sin^2(pi k / (2(nz-1))) (Thomas algorithm),   */
 /* inverse DST-I.  Pinned: the 2-D residual, the discrete Gauss law of a     */
@@ -287,6 +287,112 @@ void orc_poisson(int32_t nr, int32_t nz, double dr, double dz, const double *rho
     free(tab);
     free(bh);
     free(ph);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The same equation with the metal-mask Dirichlet condition ("Zero         */
+/* perturbation potential is imposed at ... metal mask nodes"): Phi = 0 on   */
+/* every mask node among the unknowns, the equation above at all others.   */
+/* Multiplying row (i, j) by w_i (w_0 = dr/8, w_i = r_i) makes the operator */
+/* symmetric; -W L restricted to the non-mask unknowns is symmetric positive */
+/* definite and is solved by conjugate gradients.  The preconditioner is the */
+/* mask-free direct solver (orc_poisson) applied to the residual with the   */
+/* mask entries zeroed -- a compression of an SPD inverse, so SPD on the    */
+/* same subspace; it changes only the iteration count, never the solution, */
+/* which the matrix-free operator below defines.  Stops when the residual  */
+/* of -W L Phi = W rho/eps0 falls below tol times its right-hand side's    */
+/* norm.  Returns the iterations used, or -1 without convergence.          */
+/* Pinned: an empty mask reproduces orc_poisson; Phi = 0 on the mask and   */
+/* the residual vanishes elsewhere; a mask filling a whole z-plane splits   */
+/* the problem into two independent boxes solved by orc_poisson; for a    */
+/* non-negative charge, 0 <= Phi(masked) <= Phi(no mask) (discrete maximum   */
+/* principle).                                                             */
+/* ------------------------------------------------------------------------ */
+static double fv_weight(int32_t i, double dr) { return i == 0 ? dr / 8.0 : i * dr; }
+
+/* y = -W L x on the unknowns, x = 0 on mask nodes and on the boundary.     */
+static void fv_apply(int32_t nr, int32_t nz, double dr, double dz, const uint8_t *mask, const double *x,
+                     double *y) {
+#pragma omp parallel for schedule(static)
+    for (int32_t j = 1; j <= nz - 2; ++j)
+        for (int32_t i = 0; i <= nr - 2; ++i) {
+            int64_t o = (int64_t)j * nr + i;
+            if (mask[o]) {
+                y[o] = 0.0;
+                continue;
+            }
+            const double *p = x + (int64_t)j * nr;
+            double ar;
+            if (i == 0) ar = 4.0 * (p[1] - p[0]) / (dr * dr);
+            else {
+                double ri = i * dr;
+                ar = ((ri + 0.5 * dr) * (p[i + 1] - p[i]) - (ri - 0.5 * dr) * (p[i] - p[i - 1])) / (ri * dr * dr);
+            }
+            double az = (x[o + nr] - 2.0 * p[i] + x[o - nr]) / (dz * dz);
+            y[o] = -fv_weight(i, dr) * (ar + az);
+        }
+}
+
+static double fv_dot(int64_t n, const double *a, const double *b) {
+    double s = 0.0;
+#pragma omp parallel for reduction(+ : s) schedule(static)
+    for (int64_t k = 0; k < n; ++k) s += a[k] * b[k];
+    return s;
+}
+
+/* z = P r: the mask-free solve of -W L z = r, restricted to non-mask unknowns */
+static void fv_precondition(int32_t nr, int32_t nz, double dr, double dz, const uint8_t *mask, const double *r,
+                            double *rho, double *z) {
+    int64_t nn = (int64_t)nr * nz;
+    for (int64_t o = 0; o < nn; ++o) {
+        int32_t i = (int32_t)(o % nr), j = (int32_t)(o / nr);
+        int unknown = i <= nr - 2 && j >= 1 && j <= nz - 2 && !mask[o];
+        /* -W L z = r  <=>  L z = -r / w  <=>  rho / eps0 = r / w */
+        rho[o] = unknown ? EPS0 * r[o] / fv_weight(i, dr) : 0.0;
+    }
+    orc_poisson(nr, nz, dr, dz, rho, z);
+    for (int64_t o = 0; o < nn; ++o)
+        if (mask[o]) z[o] = 0.0;
+}
+
+int32_t orc_poisson_masked(int32_t nr, int32_t nz, double dr, double dz, const double *rho, const uint8_t *mask,
+                           double tol, int32_t max_iter, double *phi) {
+    int64_t nn = (int64_t)nr * nz;
+    double *b = (double *)calloc(nn, sizeof(double)), *r = (double *)calloc(nn, sizeof(double));
+    double *z = (double *)calloc(nn, sizeof(double)), *d = (double *)calloc(nn, sizeof(double));
+    double *q = (double *)calloc(nn, sizeof(double)), *tmp = (double *)calloc(nn, sizeof(double));
+    for (int32_t j = 1; j <= nz - 2; ++j)
+        for (int32_t i = 0; i <= nr - 2; ++i) {
+            int64_t o = (int64_t)j * nr + i;
+            b[o] = mask[o] ? 0.0 : fv_weight(i, dr) * rho[o] / EPS0;
+        }
+    memset(phi, 0, sizeof(double) * nn);
+    memcpy(r, b, sizeof(double) * nn);
+    double bn = sqrt(fv_dot(nn, b, b));
+    int32_t it = 0, ok = bn == 0.0;
+    if (!ok) {
+        fv_precondition(nr, nz, dr, dz, mask, r, tmp, z);
+        memcpy(d, z, sizeof(double) * nn);
+        double rz = fv_dot(nn, r, z);
+        for (it = 1; it <= max_iter; ++it) {
+            fv_apply(nr, nz, dr, dz, mask, d, q);
+            double alpha = rz / fv_dot(nn, d, q);
+            for (int64_t o = 0; o < nn; ++o) {
+                phi[o] += alpha * d[o];
+                r[o] -= alpha * q[o];
+            }
+            if (sqrt(fv_dot(nn, r, r)) <= tol * bn) {
+                ok = 1;
+                break;
+            }
+            fv_precondition(nr, nz, dr, dz, mask, r, tmp, z);
+            double rz1 = fv_dot(nn, r, z);
+            for (int64_t o = 0; o < nn; ++o) d[o] = z[o] + (rz1 / rz) * d[o];
+            rz = rz1;
+        }
+    }
+    free(b); free(r); free(z); free(d); free(q); free(tmp);
+    return ok ? it : -1;
 }
 
 /* max |L Phi + rho/eps0| / max |rho/eps0| over the unknowns (L as above). */
@@ -806,7 +912,14 @@ int32_t orc_pic_update(orc_sim *s) {
     deposit(s);
     double *rho = (double *)malloc(sizeof(double) * nn);
     orc_rho_from_charge(s->nr, s->nz, s->dr, s->dz, s->qgrid, rho);
-    orc_poisson(s->nr, s->nz, s->dr, s->dz, rho, s->phi_sc);
+    if (s->op.sc_mask) {
+        if (orc_poisson_masked(s->nr, s->nz, s->dr, s->dz, rho, s->mask, 1e-13, 2000, s->phi_sc) < 0) {
+            free(rho);
+            return -3;
+        }
+    } else {
+        orc_poisson(s->nr, s->nz, s->dr, s->dz, rho, s->phi_sc);
+    }
     orc_bake(s->phi_sc, s->nr, s->nz, s->dr, s->dz, s->er_sc, s->ez_sc);
     free(rho);
     return 0;
@@ -984,7 +1097,7 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
     if (!s->has_fields || !s->has_op) return -2;
     for (int64_t it = 0; it < n_steps; ++it) {
         int64_t step = s->step;
-        if (s->op.sc_on && step % s->op.sc_every == 0) orc_pic_update(s);
+        if (s->op.sc_on && step % s->op.sc_every == 0 && orc_pic_update(s) < 0) return -3;
         for (int si = 0; si < s->n_src; ++si) emit(s, si, due(&s->src[si], step), step);
         const double dt = s->op.dt, w2 = 2.0 * PI * s->op.f_rf, t0 = (double)step * dt;
         double cst[3] = {s->op.v_rf * cos(w2 * t0 + s->op.phase_rf),

@@ -60,6 +60,7 @@ typedef struct orc_operating {
      * when lv_z_hi <= lv_z_lo), switch when lambda dt >= lv_switch */
     int32_t langevin_on;
     double lv_z_lo, lv_z_hi, lv_switch;
+    int32_t sc_mask; /* space charge: Phi = 0 on the metal-mask nodes */
 } orc_operating;
 
 typedef struct orc_packs {
@@ -102,6 +103,10 @@ double orc_einstein_t(double e, int32_t n_atoms, double theta);
 double orc_rate(int32_t kind, double p1, double p2, double t);
 void orc_dst1(const double *in, int32_t m, double *out);
 void orc_poisson(int32_t nr, int32_t nz, double dr, double dz, const double *rho, double *phi);
+/* The same equation with Phi = 0 on the metal-mask nodes (mask != 0), by
+ * preconditioned conjugate gradients; returns iterations or -1. */
+int32_t orc_poisson_masked(int32_t nr, int32_t nz, double dr, double dz, const double *rho, const uint8_t *mask,
+                           double tol, int32_t max_iter, double *phi);
 double orc_poisson_residual(int32_t nr, int32_t nz, double dr, double dz, const double *rho, const double *phi);
 void orc_rho_from_charge(int32_t nr, int32_t nz, double dr, double dz, const int64_t *q, double *rho);
 void orc_iict_update(double m, double mg, const double v[3], const double vgas[3], double e_int, double t_eff,

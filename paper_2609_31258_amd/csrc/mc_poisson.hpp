@@ -10,10 +10,19 @@
 //   k_dst_rows, k_idst_rows  the same transforms as direct sums (used when
 //                    the FFT length does not fit in a workgroup's LDS)
 //   k_thomas_coef, k_thomas  per-mode tridiagonal solve in r, FP64 always
+//   k_mask_*         the metal-mask Dirichlet condition by a capacitance-
+//                    matrix correction (induced charges on the mask nodes)
+//
+// A solve takes its right-hand side either from the int64 charge grid
+// (b = -rho/eps0 with rho from the control volumes) or from an FP64 array of
+// b values, and either writes Phi or adds to it.
 #pragma once
+#include "mc_capmat.hpp"
 #include "mc_device.hpp"
 
 #include <algorithm>
+#include <string>
+#include <vector>
 
 namespace mc {
 
@@ -31,15 +40,17 @@ static __global__ __launch_bounds__(256) void k_sine_table(double *s, int32_t nz
 // Row-major work arrays bh[i][k], k contiguous.
 // ---------------------------------------------------------------------------
 template <class D>
-__global__ __launch_bounds__(256) void k_dst_rows(const unsigned long long *q, const double *sine, D *bh,
-                                                  int32_t nr, int32_t nz, double dr, double dz) {
+__global__ __launch_bounds__(256) void k_dst_rows(const unsigned long long *q, const double *rhs, const double *sine,
+                                                  D *bh, int32_t nr, int32_t nz, double dr, double dz) {
     extern __shared__ unsigned char smem_raw[];
     D *row = reinterpret_cast<D *>(smem_raw);
     const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
     const double vol = (i == 0) ? kPi * dr * dr * dz / 3.0 : 2.0 * kPi * ((double)i * dr) * dr * dz;
     const double scale = -kQe * 0x1p-32 / (vol * kEps0);
-    for (int32_t j = threadIdx.x; j < m; j += blockDim.x)
-        row[j] = (D)((double)(int64_t)q[(int64_t)(j + 1) * nr + i] * scale);
+    for (int32_t j = threadIdx.x; j < m; j += blockDim.x) {
+        const int64_t o = (int64_t)(j + 1) * nr + i;
+        row[j] = (D)(q ? (double)(int64_t)q[o] * scale : rhs[o]);
+    }
     __syncthreads();
     const D norm = (D)(2.0 / (double)(nz - 1));
     for (int32_t k = 1 + threadIdx.x; k <= m; k += blockDim.x) {
@@ -112,7 +123,7 @@ __global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const d
 
 template <class D>
 __global__ __launch_bounds__(256) void k_idst_rows(const D *ph, const double *sine, double *phi, int32_t nr,
-                                                   int32_t nz) {
+                                                   int32_t nz, int32_t accumulate) {
     extern __shared__ unsigned char smem_raw[];
     D *row = reinterpret_cast<D *>(smem_raw);
     const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
@@ -126,7 +137,8 @@ __global__ __launch_bounds__(256) void k_idst_rows(const D *ph, const double *si
             if (idx >= n2) idx -= n2;
             acc += row[k - 1] * (D)sine[idx];
         }
-        phi[(int64_t)j * nr + i] = (double)acc;
+        const int64_t o = (int64_t)j * nr + i;
+        phi[o] = accumulate ? phi[o] + (double)acc : (double)acc;
     }
 }
 
@@ -237,7 +249,8 @@ __global__ __launch_bounds__(1024) void k_bluestein_filter(Cx<D> *fb, const Cx<D
 // int64 charge grid, output bh[i][:] scaled by 2/N.  Inverse: input bh[i][:],
 // output Phi[1..m][i].
 template <class D, bool kForward>
-__global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long *q, D *bh, double *phi,
+__global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long *q, const double *rhs, D *bh,
+                                                        double *phi, int32_t accumulate,
                                                         const Cx<D> *chirp, const Cx<D> *fb, const Cx<D> *tw,
                                                         int32_t nr, int32_t nz, int32_t L, double dr, double dz) {
     extern __shared__ unsigned char smem_raw[];
@@ -248,7 +261,8 @@ __global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long
     for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
         Cx<D> v{(D)0, (D)0};
         if (n < m) {
-            const D x = kForward ? (D)((double)(int64_t)q[(int64_t)(n + 1) * nr + i] * scale) : bh[(int64_t)i * m + n];
+            const int64_t o = (int64_t)(n + 1) * nr + i;
+            const D x = kForward ? (D)(q ? (double)(int64_t)q[o] * scale : rhs[o]) : bh[(int64_t)i * m + n];
             const Cx<D> c = chirp[n];
             v = Cx<D>{x * c.re, x * c.im};
         }
@@ -264,7 +278,10 @@ __global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long
         const Cx<D> c = chirp[k], y = a[k];
         const D X = (c.re * y.im + c.im * y.re) * norm;  // Im(c y)
         if (kForward) bh[(int64_t)i * m + k] = X;
-        else phi[(int64_t)(k + 1) * nr + i] = (double)X;
+        else {
+            const int64_t o = (int64_t)(k + 1) * nr + i;
+            phi[o] = accumulate ? phi[o] + (double)X : (double)X;
+        }
     }
 }
 
@@ -313,4 +330,147 @@ inline hipError_t bluestein_prepare(Bluestein &B, int32_t m, hipStream_t st) {
     k_bluestein_filter<D><<<1, 1024, B.lds, st>>>((Cx<D> *)B.fb, (const Cx<D> *)B.tw, m, B.L);
     return hipGetLastError();
 }
+
+// ---------------------------------------------------------------------------
+// One Poisson solve (host side): forward transform of the right-hand side
+// (int64 charge grid q, or FP64 b values rhs when q is null), one
+// tridiagonal system per mode, inverse transform into phi (or added to phi).
+// ---------------------------------------------------------------------------
+struct PoissonGrid {
+    int32_t nr = 0, nz = 0;
+    double dr = 0, dz = 0;
+    const double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
+    const Bluestein *blu = nullptr;
+};
+
+template <class D>
+inline hipError_t poisson_solve(const PoissonGrid &g, const unsigned long long *q, const double *rhs, D *bh,
+                                double *phi, bool accumulate, hipStream_t st) {
+    const int32_t m = g.nz - 2, nu = g.nr - 1;
+    const Bluestein &B = *g.blu;
+    const Cx<D> *chirp = (const Cx<D> *)B.chirp, *fb = (const Cx<D> *)B.fb, *tw = (const Cx<D> *)B.tw;
+    if (B.L > 0)
+        k_dst_bluestein<D, true><<<nu, 1024, B.lds, st>>>(q, rhs, bh, nullptr, 0, chirp, fb, tw, g.nr, g.nz, B.L,
+                                                           g.dr, g.dz);
+    else
+        k_dst_rows<D><<<nu, 256, m * sizeof(D), st>>>(q, rhs, g.sine, bh, g.nr, g.nz, g.dr, g.dz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_thomas<D><<<(m + 255) / 256, 256, 0, st>>>(bh, g.tcp, g.tinv, g.nr, g.nz, g.dr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (B.L > 0)
+        k_dst_bluestein<D, false><<<nu, 1024, B.lds, st>>>(nullptr, nullptr, bh, phi, accumulate ? 1 : 0, chirp, fb,
+                                                            tw, g.nr, g.nz, B.L, g.dr, g.dz);
+    else
+        k_idst_rows<D><<<nu, 256, m * sizeof(D), st>>>(bh, g.sine, phi, g.nr, g.nz, accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Metal-mask Dirichlet condition (Phi = 0 on the mask nodes among the
+// unknowns) by a capacitance-matrix correction.  With G_m = A^-1 e_m the
+// response to a unit right-hand side at mask node m, the potential
+// Phi = Phi_0 + sum_m s_m G_m vanishes on every mask node a when
+// C s = -Phi_0|mask with C[a][m] = G_m(node a).  C is built once per grid
+// (one solve per mask node) and inverted on the host in FP64 (Gauss-Jordan,
+// partial pivoting); each space-charge update then costs one matrix-vector
+// product and a second solve whose right-hand side is s on the mask nodes.
+// The correction solve is exact for the masked system: the equation holds at
+// every other unknown, and the mask rows are replaced by Phi = 0.
+// ---------------------------------------------------------------------------
+constexpr int32_t kMaxMaskNodes = 2048;
+
+static __global__ __launch_bounds__(64) void k_mask_unit(double *rhs, const int32_t *nodes, int32_t prev,
+                                                         int32_t cur) {
+    if (threadIdx.x == 0) {
+        if (prev >= 0) rhs[nodes[prev]] = 0.0;
+        rhs[nodes[cur]] = 1.0;
+    }
+}
+
+static __global__ __launch_bounds__(256) void k_mask_column(const double *phi, const int32_t *nodes, int32_t M,
+                                                            double *c, int32_t col) {
+    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < M) c[(int64_t)a * M + col] = phi[nodes[a]];
+}
+
+// rhs[node_a] = -sum_m cinv[a][m] phi[node_m]: one block per row a.
+static __global__ __launch_bounds__(256) void k_mask_correct(const double *cinv, const int32_t *nodes,
+                                                             const double *phi, double *rhs, int32_t M) {
+    __shared__ double red[256];
+    const int32_t a = blockIdx.x;
+    double acc = 0.0;
+    for (int32_t m = threadIdx.x; m < M; m += blockDim.x) acc += cinv[(int64_t)a * M + m] * phi[nodes[m]];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int32_t w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int32_t)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) rhs[nodes[a]] = -red[0];
+}
+
+static __global__ __launch_bounds__(256) void k_mask_zero(double *phi, const int32_t *nodes, int32_t M) {
+    const int32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a < M) phi[nodes[a]] = 0.0;
+}
+
+// Device tables of the correction; the caller owns the buffers.
+struct MaskCap {
+    int32_t M = 0;
+    bool ready = false;
+    int32_t *nodes = nullptr;  // [M] node index j * nr + i
+    double *cinv = nullptr;    // [M * M] row-major inverse capacitance
+};
+
+// Build C column by column (unit right-hand sides in rhs_tmp, potentials in
+// phi_tmp, both nz*nr, rhs_tmp all zero on entry and on return) and store
+// its inverse in cap.cinv.  Returns an empty string on success.
+template <class D>
+inline std::string mask_prepare(const PoissonGrid &g, MaskCap &cap, const std::vector<int32_t> &nodes, D *bh,
+                                double *rhs_tmp, double *phi_tmp, hipStream_t st) {
+    const int32_t M = (int32_t)nodes.size();
+    cap.M = M;
+    if (M == 0) {
+        cap.ready = true;
+        return "";
+    }
+    hipError_t e = hipMemcpyAsync(cap.nodes, nodes.data(), M * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    for (int32_t m = 0; m < M && e == hipSuccess; ++m) {
+        k_mask_unit<<<1, 64, 0, st>>>(rhs_tmp, cap.nodes, m - 1, m);
+        if ((e = hipGetLastError()) != hipSuccess) break;
+        if ((e = poisson_solve<D>(g, nullptr, rhs_tmp, bh, phi_tmp, false, st)) != hipSuccess) break;
+        k_mask_column<<<(M + 255) / 256, 256, 0, st>>>(phi_tmp, cap.nodes, M, cap.cinv, m);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_mask_zero<<<(M + 255) / 256, 256, 0, st>>>(rhs_tmp, cap.nodes, M);
+        e = hipGetLastError();
+    }
+    std::vector<double> c((size_t)M * M);
+    if (e == hipSuccess) e = hipMemcpyAsync(c.data(), cap.cinv, c.size() * sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return std::string("capacitance matrix: ") + hipGetErrorString(e);
+    if (!invert_in_place(c, M)) return "capacitance matrix is singular";
+    e = hipMemcpyAsync(cap.cinv, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return std::string("capacitance matrix upload: ") + hipGetErrorString(e);
+    cap.ready = true;
+    return "";
+}
+
+// After Phi_0 is in phi: induced right-hand side on the mask nodes, the
+// correction solve added to phi, and Phi = 0 set on the mask nodes.
+template <class D>
+inline hipError_t mask_correct(const PoissonGrid &g, const MaskCap &cap, D *bh, double *rhs, double *phi,
+                               hipStream_t st) {
+    if (cap.M == 0) return hipSuccess;
+    k_mask_correct<<<cap.M, 256, 0, st>>>(cap.cinv, cap.nodes, phi, rhs, cap.M);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = poisson_solve<D>(g, nullptr, rhs, bh, phi, true, st)) != hipSuccess) return e;
+    k_mask_zero<<<(cap.M + 255) / 256, 256, 0, st>>>(phi, cap.nodes, cap.M);
+    return hipGetLastError();
+}
+
 }  // namespace mc

@@ -59,6 +59,11 @@ struct mc_ctx {
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
     void *bh = nullptr;
     Bluestein blu;
+    PoissonGrid pg;
+    // metal-mask correction (built at the first masked space-charge update)
+    std::vector<int32_t> mask_nodes;
+    MaskCap mcap;
+    double *rhs = nullptr, *phi_tmp = nullptr;
 
     std::vector<mc_ion> ions;
     std::vector<Species> sp_host;
@@ -332,10 +337,53 @@ static int32_t step_once(mc_ctx *ctx) {
     return launch_step<P32, float4>(ctx, ctx->p32);
 }
 
+// Capacitance matrix of the metal-mask nodes: one FP64 solve per node, once
+// per grid (at the first space-charge update that asks for the mask
+// condition).  The matrix is always built and inverted in FP64, also for the
+// FP32 form: its inverse maps the potential on the mask to induced charges,
+// and single-precision columns would lose digits to its conditioning.
+static int32_t mask_setup(mc_ctx *ctx) {
+    const int32_t M = (int32_t)ctx->mask_nodes.size();
+    if (M > kMaxMaskNodes)
+        return fail(ctx, MC_EINVAL, "the metal mask has " + std::to_string(M) +
+                                        " interior nodes; the correction holds at most " + std::to_string(kMaxMaskNodes));
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    const int32_t m = ctx->nz - 2, nu = ctx->nr - 1;
+    int32_t rc = MC_OK;
+    if (!ctx->rhs) rc = dalloc_t(ctx, &ctx->rhs, nn);
+    if (!rc && !ctx->phi_tmp) rc = dalloc_t(ctx, &ctx->phi_tmp, nn);
+    if (!rc && M > 0) rc = dalloc_t(ctx, &ctx->mcap.nodes, M);
+    if (!rc && M > 0) rc = dalloc_t(ctx, &ctx->mcap.cinv, (size_t)M * M);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(ctx->rhs, 0, nn * sizeof(double), ctx->stream));
+    PoissonGrid g64 = ctx->pg;
+    double *bh64 = static_cast<double *>(ctx->bh);
+    Bluestein b64;
+    if (ctx->fp32()) {
+        // FP64 transform tables and work array for the setup solves
+        rc = dalloc_t(ctx, &bh64, (size_t)nu * m);
+        const int32_t L = bluestein_length(m);
+        const size_t cx = 2 * sizeof(double);
+        if (!rc && (size_t)L * cx <= lds_per_block()) {
+            b64.L = L;
+            b64.lds = (size_t)L * cx;
+            rc = dalloc(ctx, &b64.chirp, (size_t)m * cx);
+            if (!rc) rc = dalloc(ctx, &b64.tw, (size_t)std::max(L / 2, 1) * cx);
+            if (!rc) rc = dalloc(ctx, &b64.fb, (size_t)L * cx);
+            if (!rc && bluestein_prepare<double>(b64, m, ctx->stream) != hipSuccess) b64.L = 0;
+        }
+        if (rc) return rc;
+        g64.blu = &b64;
+    }
+    const std::string err = mask_prepare<double>(g64, ctx->mcap, ctx->mask_nodes, bh64, ctx->rhs, ctx->phi_tmp,
+                                                 ctx->stream);
+    if (!err.empty()) return fail(ctx, MC_EDEVICE, err);
+    return MC_OK;
+}
+
 template <class P, class D>
 static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     const int64_t nn = (int64_t)ctx->nr * ctx->nz;
-    const int32_t m = ctx->nz - 2, nu = ctx->nr - 1;
     {
         Timer t(ctx, MC_K_DEPOSIT);
         k_zero_u64<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->qgrid, nn);
@@ -354,29 +402,15 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
             LAUNCHCHK();
         }
     }
+    if (ctx->op.sc_mask && !ctx->mcap.ready) {
+        const int32_t rc = mask_setup(ctx);
+        if (rc) return rc;
+    }
     {
         Timer t(ctx, MC_K_POISSON);
         D *bh = static_cast<D *>(ctx->bh);
-        const Bluestein &B = ctx->blu;
-        if (B.L > 0) {
-            k_dst_bluestein<D, true><<<nu, 1024, B.lds, ctx->stream>>>(
-                ctx->qgrid, bh, nullptr, (const Cx<D> *)B.chirp, (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, ctx->nr,
-                ctx->nz, B.L, ctx->dr, ctx->dz);
-        } else {
-            k_dst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(ctx->qgrid, ctx->sine, bh, ctx->nr, ctx->nz,
-                                                                      ctx->dr, ctx->dz);
-        }
-        LAUNCHCHK();
-        k_thomas<D><<<grid_for(m), kBlock, 0, ctx->stream>>>(bh, ctx->tcp, ctx->tinv, ctx->nr, ctx->nz, ctx->dr);
-        LAUNCHCHK();
-        if (B.L > 0) {
-            k_dst_bluestein<D, false><<<nu, 1024, B.lds, ctx->stream>>>(
-                nullptr, bh, ctx->phi_sc, (const Cx<D> *)B.chirp, (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, ctx->nr,
-                ctx->nz, B.L, ctx->dr, ctx->dz);
-        } else {
-            k_idst_rows<D><<<nu, kBlock, m * sizeof(D), ctx->stream>>>(bh, ctx->sine, ctx->phi_sc, ctx->nr, ctx->nz);
-        }
-        LAUNCHCHK();
+        HIPCHK(poisson_solve<D>(ctx->pg, ctx->qgrid, nullptr, bh, ctx->phi_sc, false, ctx->stream));
+        if (ctx->op.sc_mask) HIPCHK(mask_correct<D>(ctx->pg, ctx->mcap, bh, ctx->rhs, ctx->phi_sc, ctx->stream));
     }
     {
         Timer t(ctx, MC_K_FIELD);
@@ -601,6 +635,15 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
             if (e != hipSuccess) B.L = 0;  // fall back to the direct sine sums
         }
     }
+    ctx->pg.nr = g->nr;
+    ctx->pg.nz = g->nz;
+    ctx->pg.dr = g->dr;
+    ctx->pg.dz = g->dz;
+    ctx->pg.sine = ctx->sine;
+    ctx->pg.tcp = ctx->tcp;
+    ctx->pg.tinv = ctx->tinv;
+    ctx->pg.blu = &ctx->blu;
+    ctx->mask_nodes = mask_unknowns(t->mask, g->nr, g->nz);
     HIPCHK(hipStreamSynchronize(ctx->stream));
     // the staging buffer is returned at once
     for (size_t k = 0; k < ctx->allocs.size(); ++k)

@@ -49,7 +49,7 @@ struct Query {
     PackPtrs<float> p32{};
     void *etab = nullptr, *bh = nullptr;
     double2 *e_sc = nullptr;
-    double *phi = nullptr, *partial = nullptr, *sums = nullptr;
+    double *phi = nullptr, *partial = nullptr, *sums = nullptr, *rhs = nullptr;
     unsigned long long *qgrid = nullptr, *tal = nullptr, *snap = nullptr;
     int64_t tal_len = 0;
     TallyPtrs tp{};
@@ -75,6 +75,9 @@ struct mc_server {
     uint8_t *hit = nullptr;
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
     Bluestein blu;
+    PoissonGrid pg;
+    std::vector<int32_t> mask_nodes;  // metal-mask nodes among the Poisson unknowns
+    MaskCap cap;                      // their capacitance correction, built at first use
     std::vector<std::pair<void *, size_t>> allocs;
     int64_t shared_bytes = 0;
     char *pool_base = nullptr;
@@ -173,6 +176,7 @@ static int64_t query_layout(const mc_server *S, const Query &Q, F &&place) {
         place("phi", 0, L.take(nn * 8));
         place("qgrid", 0, L.take(nn * 8));
         place("bh", 0, L.take((int64_t)nu * m * fsz));
+        if (Q.q.op.sc_mask) place("rhs", 0, L.take(nn * 8));
     }
     const int64_t tal_len = hot_offset(TC_N + Q.q.op.n_exit_bins + nn + MC_HIST_KE + MC_HIST_TEFF + MC_HIST_R) + kHotLen;
     place("tal", tal_len, L.take(tal_len * 8));
@@ -216,6 +220,8 @@ static void bind_query(mc_server *S, Query &Q) {
             Q.qgrid = (unsigned long long *)p;
         } else if (w == "bh") {
             Q.bh = p;
+        } else if (w == "rhs") {
+            Q.rhs = (double *)p;
         } else if (w == "tal") {
             Q.tal = (unsigned long long *)p;
             Q.tal_len = k;
@@ -282,6 +288,7 @@ static int32_t admit_query(mc_server *S, Query &Q) {
     if (Q.q.op.sc_on) {
         k_zero_u64<<<blocks_for(2 * nn), kBlk, 0, S->stream>>>((unsigned long long *)Q.e_sc, 2 * nn);
         k_zero_u64<<<blocks_for(nn), kBlk, 0, S->stream>>>((unsigned long long *)Q.phi, nn);
+        if (Q.rhs) k_zero_u64<<<blocks_for(nn), kBlk, 0, S->stream>>>((unsigned long long *)Q.rhs, nn);
         SCHK(hipGetLastError());
     }
     SCHK(hipMemcpyAsync(Q.sp_dev, &Q.sp, sizeof(Species), hipMemcpyHostToDevice, S->stream));
@@ -295,7 +302,6 @@ static int32_t admit_query(mc_server *S, Query &Q) {
 template <class P, class Tab, class D>
 static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
     const int64_t nn = (int64_t)S->nr * S->nz;
-    const int32_t m = S->nz - 2, nu = S->nr - 1;
     k_zero_u64<<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.qgrid, nn);
     if (Q.n_slots > 0) {
         DepositArgs<typename P::T> a{};
@@ -309,20 +315,40 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         k_deposit<P><<<(unsigned)std::min<int64_t>(blocks_for(Q.n_slots), kDepositBlocks), kBlk, 0, S->stream>>>(a);
     }
     D *bh = static_cast<D *>(Q.bh);
-    const Bluestein &B = S->blu;
-    if (B.L > 0)
-        k_dst_bluestein<D, true><<<nu, 1024, B.lds, S->stream>>>(Q.qgrid, bh, nullptr, (const Cx<D> *)B.chirp,
-                                                                 (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, S->nr,
-                                                                 S->nz, B.L, S->dr, S->dz);
-    else
-        k_dst_rows<D><<<nu, kBlk, m * sizeof(D), S->stream>>>(Q.qgrid, S->sine, bh, S->nr, S->nz, S->dr, S->dz);
-    k_thomas<D><<<blocks_for(m), kBlk, 0, S->stream>>>(bh, S->tcp, S->tinv, S->nr, S->nz, S->dr);
-    if (B.L > 0)
-        k_dst_bluestein<D, false><<<nu, 1024, B.lds, S->stream>>>(nullptr, bh, Q.phi, (const Cx<D> *)B.chirp,
-                                                                  (const Cx<D> *)B.fb, (const Cx<D> *)B.tw, S->nr,
-                                                                  S->nz, B.L, S->dr, S->dz);
-    else
-        k_idst_rows<D><<<nu, kBlk, m * sizeof(D), S->stream>>>(bh, S->sine, Q.phi, S->nr, S->nz);
+    SCHK(poisson_solve<D>(S->pg, Q.qgrid, nullptr, bh, Q.phi, false, S->stream));
+    if (Q.q.op.sc_mask) {
+        if (!S->cap.ready) {
+            // first masked query: the capacitance matrix, using this query's
+            // work arrays (its potential is recomputed right after)
+            // (always in FP64: the inverse capacitance matrix needs the digits)
+            const int32_t M = (int32_t)S->mask_nodes.size();
+            const int32_t m = S->nz - 2, nu = S->nr - 1;
+            if (M > kMaxMaskNodes) return sfail(S, MC_EINVAL, "too many metal-mask nodes for the correction");
+            if (M > 0 && (salloc_t(S, &S->cap.nodes, M) || salloc_t(S, &S->cap.cinv, (size_t)M * M)))
+                return MC_ENOMEM;
+            PoissonGrid g64 = S->pg;
+            double *bh64 = reinterpret_cast<double *>(bh);
+            Bluestein b64;
+            if (S->fp32()) {
+                const int32_t L = bluestein_length(m);
+                const size_t cx = 2 * sizeof(double);
+                if (salloc_t(S, &bh64, (size_t)nu * m)) return MC_ENOMEM;
+                if ((size_t)L * cx <= lds_per_block()) {
+                    b64.L = L;
+                    b64.lds = (size_t)L * cx;
+                    if (salloc(S, &b64.chirp, (size_t)m * cx) || salloc(S, &b64.tw, (size_t)std::max(L / 2, 1) * cx) ||
+                        salloc(S, &b64.fb, (size_t)L * cx))
+                        return MC_ENOMEM;
+                    if (bluestein_prepare<double>(b64, m, S->stream) != hipSuccess) b64.L = 0;
+                }
+                g64.blu = &b64;
+            }
+            const std::string err = mask_prepare<double>(g64, S->cap, S->mask_nodes, bh64, Q.rhs, Q.phi, S->stream);
+            if (!err.empty()) return sfail(S, MC_EDEVICE, err);
+            SCHK(poisson_solve<D>(S->pg, Q.qgrid, nullptr, bh, Q.phi, false, S->stream));
+        }
+        SCHK(mask_correct<D>(S->pg, S->cap, bh, Q.rhs, Q.phi, S->stream));
+    }
     k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.phi, Q.e_sc, S->nr, S->nz, S->dr, S->dz);
     SCHK(hipGetLastError());
     return fold_query<Tab>(S, Q);
@@ -725,6 +751,15 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
             if (e != hipSuccess) B.L = 0;
         }
     }
+    S->pg.nr = g->nr;
+    S->pg.nz = g->nz;
+    S->pg.dr = g->dr;
+    S->pg.dz = g->dz;
+    S->pg.sine = S->sine;
+    S->pg.tcp = S->tcp;
+    S->pg.tinv = S->tinv;
+    S->pg.blu = &S->blu;
+    S->mask_nodes = mask_unknowns(t->mask, g->nr, g->nz);
     SC2(hipStreamSynchronize(S->stream));
     if (S->bf16()) {
         std::vector<double2> h(nn);

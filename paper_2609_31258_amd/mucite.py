@@ -62,7 +62,7 @@ class Operating(C.Structure):
     _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
-                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64)]
+                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32)]
 
 
 class Packs(C.Structure):

@@ -101,6 +101,7 @@ class Operating:
     lv_z_lo: float = 0.0          # axial window [lv_z_lo, lv_z_hi); none when lv_z_hi <= lv_z_lo
     lv_z_hi: float = 0.0
     lv_switch: float = 0.05       # switch when lambda dt >= lv_switch
+    sc_mask: int = 0              # space charge: Phi = 0 on the metal-mask nodes
 
 
 @dataclasses.dataclass
