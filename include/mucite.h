@@ -83,6 +83,7 @@ typedef struct mc_options {
     void *alloc_user;
     int32_t timing;          /* non-zero: record HIP events around every kernel (mc_read_timing) */
     int32_t fp32_tables;     /* FP32 form only: FP32 field tables instead of BF16 with per-table scale */
+    int64_t sample_capacity; /* trajectory-sample buffer size in records (0 = none; see mc_read_samples) */
 } mc_options;
 
 typedef struct mc_grid {
@@ -162,7 +163,15 @@ typedef struct mc_source {
  * whose potentials the static field already holds).  Imposed by a
  * capacitance-matrix correction built at the first such update (one solve
  * per interior mask node, at most 2048 of them, else MC_EINVAL) and then
- * applied with one extra solve per update. */
+ * applied with one extra solve per update.
+ *
+ * sample_every/sample_stride: time-resolved snapshots (the paper's
+ * ion-distribution snapshots).  At the start of every step n with
+ * n % sample_every == 0 (before the space-charge update and emission), each
+ * active pack whose id is a multiple of sample_stride is recorded
+ * (mc_sample_rec) into the buffer sized by mc_options.sample_capacity.
+ * 0 turns sampling off; both must be >= 0.  Single contexts only: the
+ * serving runtime returns tallies and ignores these two fields. */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
     int32_t collisions_on, sc_on, sc_every;
@@ -171,6 +180,7 @@ typedef struct mc_operating {
     int32_t langevin_on;
     double lv_z_lo, lv_z_hi, lv_switch;
     int32_t sc_mask;
+    int32_t sample_every, sample_stride;
 } mc_operating;
 
 /* Pack population (host arrays of length n) for snapshot read/write.
@@ -213,6 +223,13 @@ typedef struct mc_exit_rec {
     int32_t cls, inode, jnode, tag;
     double x, y, z, vx, vy, vz, t_cross, r_cross, ke_ev, t_eff, h, w;
 } mc_exit_rec;
+
+/* One trajectory sample (state at the start of step `step`, t = step dt). */
+typedef struct mc_sample_rec {
+    int64_t id, step;
+    int32_t tag, reserved;
+    double x, y, z, vx, vy, vz, ke_ev, t_eff, h, w;
+} mc_sample_rec;
 
 typedef struct mc_info {
     int64_t step, n_slots, capacity, exit_capacity, device_bytes;
@@ -264,6 +281,9 @@ int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out);
 /* Copy up to cap exit records (sorted by pack id) into buf; *n receives the
  * total number recorded (may exceed cap). */
 int32_t mc_read_exits(mc_ctx *ctx, mc_exit_rec *buf, int64_t cap, int64_t *n);
+/* Copy up to cap trajectory samples, sorted by (step, id), into buf; *n
+ * receives the number taken (may exceed the buffer: the rest were dropped). */
+int32_t mc_read_samples(mc_ctx *ctx, mc_sample_rec *buf, int64_t cap, int64_t *n);
 int32_t mc_read_packs(mc_ctx *ctx, mc_packs *out);
 int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in);
 /* int64 charge grid of the last deposit, nz*nr, units of 2^-32 e. */

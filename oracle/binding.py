@@ -33,7 +33,8 @@ class Operating(C.Structure):
     _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
-                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32)]
+                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32),
+                ("sample_every", I32), ("sample_stride", I32)]
 
 
 class Packs(C.Structure):
@@ -47,6 +48,10 @@ class Tallies(C.Structure):
                 ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
                 ("exit_bins", PI64), ("loss_map", PI64), ("hist_ke", PI64), ("hist_teff", PI64), ("hist_r", PI64),
                 ("act_hist_ke", PI64), ("act_hist_teff", PI64)]
+
+
+SAMPLE_DTYPE = np.dtype([("id", np.int64), ("step", np.int64), ("tag", np.int32), ("pad", np.int32)] +
+                        [(f, np.float64) for f in ("x", "y", "z", "vx", "vy", "vz", "ke_ev", "t_eff", "h", "w")])
 
 
 class Exit(C.Structure):
@@ -96,6 +101,7 @@ def lib():
         "orc_write_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
         "orc_read_tallies": (I32, [C.c_void_p, C.POINTER(Tallies)]),
         "orc_read_exits": (I64, [C.c_void_p, C.POINTER(Exit), I64]),
+        "orc_read_samples": (I64, [C.c_void_p, C.c_void_p, I64]),
         "orc_read_charge": (I32, [C.c_void_p, PI64]),
         "orc_read_sc": (I32, [C.c_void_p, PD, PD, PD]),
         "orc_read_hit": (I32, [C.c_void_p, PU8]),
@@ -346,6 +352,12 @@ class OracleSim:
         out["class_n"] = np.array(list(T.class_n), np.int64)
         out["class_w"] = np.array(list(T.class_w), np.int64)
         return out
+
+    def read_samples(self) -> np.ndarray:
+        n = lib().orc_read_samples(self._h, None, 0)
+        buf = np.zeros(max(n, 1), dtype=SAMPLE_DTYPE)
+        lib().orc_read_samples(self._h, buf.ctypes.data_as(C.c_void_p), n)
+        return buf[:n]
 
     def read_exits(self) -> np.ndarray:
         n = lib().orc_read_exits(self._h, None, 0)

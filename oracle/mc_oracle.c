@@ -634,6 +634,9 @@ struct orc_sim {
     /* per-step counters */
     int64_t n_cand, n_coll, n_cap, n_clamp, n_lang;
     int64_t emitted_n, emitted_w;
+    /* snapshot records (time-resolved ion distributions) */
+    orc_sample *samples;
+    int64_t n_samples, cap_samples;
 };
 
 static void *xrealloc(void *p, size_t n) { return realloc(p, n ? n : 1); }
@@ -663,7 +666,7 @@ void orc_destroy(orc_sim *s) {
     void *fs[] = {s->er_dc, s->ez_dc, s->er_off, s->ez_off, s->er_rf, s->ez_rf, s->gur, s->guz, s->gp, s->gt,
                   s->mask, s->hit, s->phi_sc, s->er_sc, s->ez_sc, s->qgrid, s->x, s->y, s->z, s->vx, s->vy,
                   s->vz, s->eint, s->h, s->w, s->id, s->q, s->tag, s->status, s->ex_step, s->ex_i, s->ex_j,
-                  s->ex_t, s->ex_r};
+                  s->ex_t, s->ex_r, s->samples};
     for (size_t k = 0; k < sizeof(fs) / sizeof(fs[0]); ++k) free(fs[k]);
     free(s);
 }
@@ -769,6 +772,7 @@ int32_t orc_define_source(orc_sim *s, const orc_source *in) {
 int32_t orc_set_operating(orc_sim *s, const orc_operating *op) {
     if (!(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1) return -1;
     if (op->langevin_on && !(op->lv_switch >= 0.0)) return -1;
+    if (op->sample_every < 0 || op->sample_stride < 0) return -1;
     s->op = *op;
     s->has_op = 1;
     for (int k = 0; k < s->n_ion; ++k) set_alpha(s, &s->ion[k]);
@@ -1093,10 +1097,46 @@ static void advance(orc_sim *s, int64_t k, int64_t step, const double cst[3], co
     s->h[k] += orc_rate(I->in.act_kind, I->in.act_p1, I->in.act_p2, te) * dt;
 }
 
+/* Snapshot of the active packs with id % stride == 0 at the start of `step`. */
+static void take_samples(orc_sim *s, int64_t step) {
+    for (int64_t k = 0; k < s->n; ++k) {
+        if (s->status[k] != ORC_ACTIVE || s->id[k] % s->op.sample_stride != 0) continue;
+        if (s->n_samples == s->cap_samples) {
+            s->cap_samples = s->cap_samples ? 2 * s->cap_samples : 1024;
+            s->samples = (orc_sample *)xrealloc(s->samples, sizeof(orc_sample) * (size_t)s->cap_samples);
+        }
+        const ion_t *I = &s->ion[s->tag[k]];
+        orc_sample *r = &s->samples[s->n_samples++];
+        double v2 = s->vx[k] * s->vx[k] + s->vy[k] * s->vy[k] + s->vz[k] * s->vz[k];
+        r->id = s->id[k]; r->step = step; r->tag = s->tag[k]; r->pad = 0;
+        r->x = s->x[k]; r->y = s->y[k]; r->z = s->z[k];
+        r->vx = s->vx[k]; r->vy = s->vy[k]; r->vz = s->vz[k];
+        r->ke_ev = 0.5 * I->m * v2 / QE;
+        r->t_eff = orc_einstein_t(s->eint[k], I->in.n_atoms, I->in.theta_e);
+        r->h = s->h[k]; r->w = s->w[k];
+    }
+}
+
+static int cmp_sample(const void *a, const void *b) {
+    const orc_sample *x = (const orc_sample *)a, *y = (const orc_sample *)b;
+    if (x->step != y->step) return x->step < y->step ? -1 : 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+int64_t orc_read_samples(const orc_sim *s, orc_sample *buf, int64_t cap) {
+    if (buf && cap > 0) {
+        int64_t m = cap < s->n_samples ? cap : s->n_samples;
+        memcpy(buf, s->samples, sizeof(orc_sample) * (size_t)m);
+        qsort(buf, (size_t)m, sizeof(orc_sample), cmp_sample);
+    }
+    return s->n_samples;
+}
+
 int32_t orc_step(orc_sim *s, int64_t n_steps) {
     if (!s->has_fields || !s->has_op) return -2;
     for (int64_t it = 0; it < n_steps; ++it) {
         int64_t step = s->step;
+        if (s->op.sample_every > 0 && s->op.sample_stride > 0 && step % s->op.sample_every == 0) take_samples(s, step);
         if (s->op.sc_on && step % s->op.sc_every == 0 && orc_pic_update(s) < 0) return -3;
         for (int si = 0; si < s->n_src; ++si) emit(s, si, due(&s->src[si], step), step);
         const double dt = s->op.dt, w2 = 2.0 * PI * s->op.f_rf, t0 = (double)step * dt;

@@ -61,6 +61,9 @@ typedef struct orc_operating {
     int32_t langevin_on;
     double lv_z_lo, lv_z_hi, lv_switch;
     int32_t sc_mask; /* space charge: Phi = 0 on the metal-mask nodes */
+    /* snapshots: at the start of step n with n % sample_every == 0, every
+     * active pack whose id is a multiple of sample_stride (0 = off) */
+    int32_t sample_every, sample_stride;
 } orc_operating;
 
 typedef struct orc_packs {
@@ -86,6 +89,13 @@ typedef struct orc_exit {
     int32_t cls, inode, jnode, tag;
     double x, y, z, vx, vy, vz, t_cross, r_cross, ke_ev, t_eff, h, w;
 } orc_exit;
+
+/* One snapshot record: the pack's state at the start of step `step`. */
+typedef struct orc_sample {
+    int64_t id, step;
+    int32_t tag, pad;
+    double x, y, z, vx, vy, vz, ke_ev, t_eff, h, w;
+} orc_sample;
 
 typedef struct orc_probe {
     int64_t n_cand, n_acc;
@@ -133,6 +143,8 @@ int32_t orc_read_packs(const orc_sim *s, orc_packs *out);
 int32_t orc_write_packs(orc_sim *s, const orc_packs *in);
 int32_t orc_read_tallies(const orc_sim *s, orc_tallies *out);
 int64_t orc_read_exits(const orc_sim *s, orc_exit *buf, int64_t cap);
+/* Snapshot records in (step, id) order; returns how many there are. */
+int64_t orc_read_samples(const orc_sim *s, orc_sample *buf, int64_t cap);
 int32_t orc_read_charge(const orc_sim *s, int64_t *q);
 int32_t orc_read_sc(const orc_sim *s, double *phi, double *er, double *ez);
 int32_t orc_read_hit(const orc_sim *s, uint8_t *hit);

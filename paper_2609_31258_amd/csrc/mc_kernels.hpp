@@ -785,6 +785,53 @@ static __global__ __launch_bounds__(256) void k_reduce_partials(const double *pa
         for (int c = 0; c < 3; ++c) out[c] = red[c][0];
 }
 
+// Trajectory samples: active packs with id % stride == 0, one record each;
+// buffer slots are claimed once per wavefront (ballot + prefix count).
+template <class T>
+__global__ __launch_bounds__(256) void k_sample(PackPtrs<T> p, const Species *sp, int64_t n_slots, int64_t step,
+                                                int64_t stride, mc_sample_rec *out, unsigned long long *count,
+                                                int64_t cap) {
+#pragma clang fp contract(off)
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool take = false;
+    if (s < n_slots && p.status[s] == ST_ACTIVE) take = p.id[s] % stride == 0;
+    const uint64_t mask = __ballot(take);
+    if (mask == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (!take) return;
+    const unsigned long long slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+    if ((int64_t)slot >= cap) return;
+    const Species S = sp[p.tag[s]];
+    double x = p.x[s], y = p.y[s], z = p.z[s], e = p.e[s];
+    if constexpr (sizeof(T) == 4) {
+        x += (double)p.xl[s];
+        y += (double)p.yl[s];
+        z += (double)p.zl[s];
+        e += (double)p.el[s];
+    }
+    const double vx = p.vx[s], vy = p.vy[s], vz = p.vz[s];
+    mc_sample_rec r;
+    r.id = p.id[s];
+    r.step = step;
+    r.tag = p.tag[s];
+    r.reserved = 0;
+    r.x = x;
+    r.y = y;
+    r.z = z;
+    r.vx = vx;
+    r.vy = vy;
+    r.vz = vz;
+    r.ke_ev = 0.5 * S.m * (vx * vx + vy * vy + vz * vz) / kQe;
+    r.t_eff = e > 0.0 ? S.theta / log1p(S.skt / e) : 0.0;
+    r.h = p.h[s];
+    r.w = p.w[s];
+    out[slot] = r;
+}
+
 // Small utilities.
 static __global__ __launch_bounds__(256) void k_zero_u64(unsigned long long *p, int64_t n) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

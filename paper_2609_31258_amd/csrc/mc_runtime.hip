@@ -64,6 +64,10 @@ struct mc_ctx {
     std::vector<int32_t> mask_nodes;
     MaskCap mcap;
     double *rhs = nullptr, *phi_tmp = nullptr;
+    // trajectory samples
+    mc_sample_rec *samples = nullptr;
+    unsigned long long *sample_count = nullptr;
+    int64_t sample_cap = 0;
 
     std::vector<mc_ion> ions;
     std::vector<Species> sp_host;
@@ -459,7 +463,7 @@ int32_t mc_create(const mc_options *o, mc_ctx **out) {
     if (!o || !out) return MC_EINVAL;
     *out = nullptr;
     if (o->pack_capacity <= 0 || (o->precision != MC_PREC_FP64 && o->precision != MC_PREC_FP32) ||
-        (!o->alloc) != (!o->free))
+        (!o->alloc) != (!o->free) || o->sample_capacity < 0)
         return MC_EINVAL;
     mc_ctx *ctx = new (std::nothrow) mc_ctx();
     if (!ctx) return MC_ENOMEM;
@@ -511,6 +515,11 @@ int32_t mc_create(const mc_options *o, mc_ctx **out) {
     if (!rc) rc = dalloc_t(ctx, &ctx->partial, 3 * ctx->partial_len);
     if (!rc) rc = dalloc_t(ctx, &ctx->sums, 4);
     if (!rc) rc = dalloc_t(ctx, &ctx->snap, 2 + MC_HIST_KE + MC_HIST_TEFF);
+    ctx->sample_cap = o->sample_capacity;
+    if (!rc && ctx->sample_cap > 0) rc = dalloc_t(ctx, &ctx->samples, ctx->sample_cap);
+    if (!rc) rc = dalloc_t(ctx, &ctx->sample_count, 1);
+    if (!rc && hipMemsetAsync(ctx->sample_count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
+        rc = fail(ctx, MC_EDEVICE, "clearing the sample counter");
     if (rc) {
         std::string msg = ctx->err;
         mc_destroy(ctx);
@@ -684,7 +693,7 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
     if (!ctx) return MC_EINVAL;
     if (!op || !(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1 || !(op->exit_bin_dt > 0) ||
         !(op->gas_mass_da > 0) || !(op->r_det > 0) || !(op->d_hit >= 0) ||
-        (op->langevin_on && !(op->lv_switch >= 0)))
+        (op->langevin_on && !(op->lv_switch >= 0)) || op->sample_every < 0 || op->sample_stride < 0)
         return fail(ctx, MC_EINVAL, "invalid operating point");
     if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "load fields first");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -755,6 +764,18 @@ int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
     HIPCHK(hipSetDevice(ctx->opt.device));
     for (int64_t it = 0; it < n_steps; ++it) {
         int32_t rc;
+        if (ctx->op.sample_every > 0 && ctx->op.sample_stride > 0 && ctx->step % ctx->op.sample_every == 0 &&
+            ctx->n_slots > 0) {
+            if (ctx->fp32())
+                k_sample<float><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(
+                    ctx->p32, ctx->sp_dev, ctx->n_slots, ctx->step, ctx->op.sample_stride, ctx->samples,
+                    ctx->sample_count, ctx->sample_cap);
+            else
+                k_sample<double><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(
+                    ctx->p64, ctx->sp_dev, ctx->n_slots, ctx->step, ctx->op.sample_stride, ctx->samples,
+                    ctx->sample_count, ctx->sample_cap);
+            LAUNCHCHK();
+        }
         if (ctx->op.sc_on && ctx->step % ctx->op.sc_every == 0) {
             rc = pic_update(ctx);
             if (rc) return rc;
@@ -841,6 +862,24 @@ int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out) {
     if (out->hist_r) HIPCHK(hipMemcpy(out->hist_r, ctx->tp.hist_r, MC_HIST_R * 8, hipMemcpyDeviceToHost));
     if (out->act_hist_ke) std::memcpy(out->act_hist_ke, snap.data() + 2, MC_HIST_KE * 8);
     if (out->act_hist_teff) std::memcpy(out->act_hist_teff, snap.data() + 2 + MC_HIST_KE, MC_HIST_TEFF * 8);
+    return MC_OK;
+}
+
+int32_t mc_read_samples(mc_ctx *ctx, mc_sample_rec *buf, int64_t cap, int64_t *n) {
+    if (!ctx || !n || cap < 0) return MC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    unsigned long long count = 0;
+    HIPCHK(hipMemcpy(&count, ctx->sample_count, sizeof(count), hipMemcpyDeviceToHost));
+    *n = (int64_t)count;
+    if (!buf || cap == 0) return MC_OK;
+    const int64_t have = std::min<int64_t>((int64_t)count, ctx->sample_cap);
+    std::vector<mc_sample_rec> all(have);
+    if (have > 0) HIPCHK(hipMemcpy(all.data(), ctx->samples, have * sizeof(mc_sample_rec), hipMemcpyDeviceToHost));
+    std::sort(all.begin(), all.end(), [](const mc_sample_rec &a, const mc_sample_rec &b) {
+        return a.step != b.step ? a.step < b.step : a.id < b.id;
+    });
+    std::memcpy(buf, all.data(), std::min(have, cap) * sizeof(mc_sample_rec));
     return MC_OK;
 }
 

@@ -36,7 +36,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
 class Options(C.Structure):
     _fields_ = [("precision", I32), ("device", I32), ("seed", U64), ("pack_capacity", I64), ("exit_capacity", I64),
                 ("hbm_budget", I64), ("stream", C.c_void_p), ("alloc", ALLOC_FN), ("free", FREE_FN),
-                ("alloc_user", C.c_void_p), ("timing", I32), ("fp32_tables", I32)]
+                ("alloc_user", C.c_void_p), ("timing", I32), ("fp32_tables", I32), ("sample_capacity", I64)]
 
 
 class Grid(C.Structure):
@@ -62,7 +62,8 @@ class Operating(C.Structure):
     _fields_ = [("dt", F64), ("v_rf", F64), ("f_rf", F64), ("phase_rf", F64), ("v_off", F64),
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
-                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32)]
+                ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32),
+                ("sample_every", I32), ("sample_stride", I32)]
 
 
 class Packs(C.Structure):
@@ -83,6 +84,11 @@ class ExitRec(C.Structure):
     _fields_ = [("id", I64), ("step", I64), ("cls", I32), ("inode", I32), ("jnode", I32), ("tag", I32)] + \
                [(f, F64) for f in ("x", "y", "z", "vx", "vy", "vz", "t_cross", "r_cross", "ke_ev", "t_eff",
                                    "h", "w")]
+
+
+class SampleRec(C.Structure):
+    _fields_ = [("id", I64), ("step", I64), ("tag", I32), ("reserved", I32)] + \
+               [(f, F64) for f in ("x", "y", "z", "vx", "vy", "vz", "ke_ev", "t_eff", "h", "w")]
 
 
 class Info(C.Structure):
@@ -123,6 +129,9 @@ Q_PENDING, Q_RUNNING, Q_DONE, Q_FAILED = 0, 1, 2, 3
 EXIT_DTYPE = np.dtype([(f, np.int64 if t is I64 else (np.int32 if t is I32 else np.float64))
                        for f, t in ExitRec._fields_])
 assert EXIT_DTYPE.itemsize == C.sizeof(ExitRec)
+SAMPLE_DTYPE = np.dtype([(f, np.int64 if t is I64 else (np.int32 if t is I32 else np.float64))
+                         for f, t in SampleRec._fields_])
+assert SAMPLE_DTYPE.itemsize == C.sizeof(SampleRec)
 
 _SIGS = {
     "mc_abi_version": (I32, []),
@@ -140,6 +149,7 @@ _SIGS = {
     "mc_get_info": (I32, [C.c_void_p, C.POINTER(Info)]),
     "mc_read_tallies": (I32, [C.c_void_p, C.POINTER(Tallies)]),
     "mc_read_exits": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
+    "mc_read_samples": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
     "mc_read_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
     "mc_write_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
     "mc_read_charge": (I32, [C.c_void_p, PI64]),
@@ -237,7 +247,7 @@ class Sim:
 
     def __init__(self, *, seed: int = 7, pack_capacity: int, precision: int = PREC_FP64, device: int = 0,
                  exit_capacity: int = 0, hbm_budget: int = 0, timing: bool = False, fp32_tables: bool = False,
-                 use_torch: bool = True):
+                 sample_capacity: int = 0, use_torch: bool = True):
         self.L = load_library()
         self._mem = _TorchMemory(device) if use_torch else None
         o = Options()
@@ -249,6 +259,8 @@ class Sim:
         o.hbm_budget = hbm_budget
         o.timing = int(timing)
         o.fp32_tables = int(fp32_tables)
+        o.sample_capacity = sample_capacity
+        self.sample_capacity = sample_capacity
         if self._mem is not None:
             o.stream = self._mem.stream.cuda_stream
             o.alloc = self._mem.alloc_cb
@@ -378,7 +390,15 @@ class Sim:
         buf = np.zeros(max(n.value, 1), dtype=EXIT_DTYPE)
         self._chk(self.L.mc_read_exits(self._h, buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(n)),
                   "mc_read_exits")
-        return buf[: min(n.value, buf.size)]
+        return buf[: min(n.value, buf.size, self.info()["exit_capacity"])]  # records beyond the buffer were dropped
+
+    def read_samples(self) -> np.ndarray:
+        n = I64()
+        self._chk(self.L.mc_read_samples(self._h, None, 0, C.byref(n)), "mc_read_samples")
+        buf = np.zeros(max(n.value, 1), dtype=SAMPLE_DTYPE)
+        self._chk(self.L.mc_read_samples(self._h, buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(n)),
+                  "mc_read_samples")
+        return buf[: min(n.value, buf.size, self.sample_capacity)]  # records beyond the buffer were dropped
 
     def read_charge(self) -> np.ndarray:
         q = np.zeros((self.nz, self.nr), np.int64)

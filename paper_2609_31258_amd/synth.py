@@ -102,6 +102,8 @@ class Operating:
     lv_z_hi: float = 0.0
     lv_switch: float = 0.05       # switch when lambda dt >= lv_switch
     sc_mask: int = 0              # space charge: Phi = 0 on the metal-mask nodes
+    sample_every: int = 0         # trajectory samples every sample_every steps (0 = off)
+    sample_stride: int = 0        # ... of the packs whose id is a multiple of sample_stride
 
 
 @dataclasses.dataclass
