@@ -34,7 +34,8 @@ class Operating(C.Structure):
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
                 ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32),
-                ("sample_every", I32), ("sample_stride", I32)]
+                ("sample_every", I32), ("sample_stride", I32),
+                ("adaptive", I32), ("lv_dt_max", F64)]
 
 
 class Packs(C.Structure):
@@ -107,6 +108,8 @@ def lib():
         "orc_read_hit": (I32, [C.c_void_p, PU8]),
         "orc_pic_update": (I32, [C.c_void_p]),
         "orc_deposit": (I32, [C.c_void_p]),
+        "orc_current_time": (F64, [C.c_void_p]),
+        "orc_last_dt": (F64, [C.c_void_p]),
         "orc_langevin_gamma": (F64, [F64, F64, F64, F64]),
         "orc_langevin_relax": (None, [F64, F64, F64, PD, F64, PD, PD]),
     }
@@ -301,6 +304,14 @@ class OracleSim:
 
     def pic_update(self):
         self._chk(lib().orc_pic_update(self._h), "pic_update")
+
+    @property
+    def time(self) -> float:
+        return lib().orc_current_time(self._h)
+
+    @property
+    def last_dt(self) -> float:
+        return lib().orc_last_dt(self._h)
 
     def deposit(self):
         self._chk(lib().orc_deposit(self._h), "deposit")

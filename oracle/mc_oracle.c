@@ -634,6 +634,8 @@ struct orc_sim {
     /* per-step counters */
     int64_t n_cand, n_coll, n_cap, n_clamp, n_lang;
     int64_t emitted_n, emitted_w;
+    /* adaptive step (Eq. 1): time, next space-charge time, last step */
+    double t, t_next_pic, last_dt;
     /* snapshot records (time-resolved ion distributions) */
     orc_sample *samples;
     int64_t n_samples, cap_samples;
@@ -752,27 +754,32 @@ int32_t orc_define_ion(orc_sim *s, const orc_ion *in) {
 /* Fixed-point weights and charges (units of 2^-32 real ions / elementary charges). */
 static int64_t fx32(double v) { return llrint(ldexp(v, 32)); }
 
+/* Eq. 5: each step the accumulator receives N_real = I dt / (z e) real ions;
+ * a fixed-rate source splits them over its packs_per_step packs.  With the
+ * adaptive step this is redone for every step's dt. */
+static void source_dt(const orc_sim *s, src_t *S, double dt) {
+    double z = (double)s->ion[S->in.ion].in.charge_z;
+    double n_real = S->in.current_a * dt / (z * QE);
+    if (S->in.kind == 1) S->w = n_real / (double)S->in.packs_per_step;
+    else S->w = S->in.weight;
+    S->w_fx = fx32(S->w);
+    S->q_fx = fx32(z * S->w);
+    S->n_real_fx = fx32(n_real);
+}
+
 int32_t orc_define_source(orc_sim *s, const orc_source *in) {
     if (s->n_src >= MAX_SRC || in->ion < 0 || in->ion >= s->n_ion || !s->has_op) return -1;
     src_t *S = &s->src[s->n_src];
     memset(S, 0, sizeof(*S));
     S->in = *in;
-    const ion_t *I = &s->ion[in->ion];
-    double z = (double)I->in.charge_z;
-    /* Eq. 5: each step the accumulator receives N_real = I dt / (z e) real ions */
-    double n_real = in->current_a * s->op.dt / (z * QE);
-    if (in->kind == 1) S->w = n_real / (double)in->packs_per_step;
-    else S->w = in->weight;
-    S->w_fx = fx32(S->w);
-    S->q_fx = fx32(z * S->w);
-    S->n_real_fx = fx32(n_real);
+    source_dt(s, S, s->op.dt);
     return s->n_src++;
 }
 
 int32_t orc_set_operating(orc_sim *s, const orc_operating *op) {
     if (!(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1) return -1;
     if (op->langevin_on && !(op->lv_switch >= 0.0)) return -1;
-    if (op->sample_every < 0 || op->sample_stride < 0) return -1;
+    if (op->sample_every < 0 || op->sample_stride < 0 || !(op->lv_dt_max >= 0.0)) return -1;
     s->op = *op;
     s->has_op = 1;
     for (int k = 0; k < s->n_ion; ++k) set_alpha(s, &s->ion[k]);
@@ -998,10 +1005,10 @@ static void langevin_normals(const uint32_t key[2], int64_t id, int64_t step, do
 }
 
 /* One pack, one step: RK4 push, classification, collisions, dissociation.  */
-static void advance(orc_sim *s, int64_t k, int64_t step, const double cst[3], coll_count_t *cnt) {
+static void advance(orc_sim *s, int64_t k, int64_t step, double t0, double dt, const double cst[3],
+                    coll_count_t *cnt) {
     const ion_t *I = &s->ion[s->tag[k]];
-    const double dt = s->op.dt, qm = I->qm;
-    const double t0 = (double)step * dt;
+    const double qm = I->qm;
     double x0[3] = {s->x[k], s->y[k], s->z[k]}, v0[3] = {s->vx[k], s->vy[k], s->vz[k]};
     /* classical RK4 on (x, v), stages at t, t+dt/2, t+dt/2, t+dt */
     double kx[4][3], kv[4][3], xs[3], e[3];
@@ -1078,7 +1085,7 @@ static void advance(orc_sim *s, int64_t k, int64_t step, const double cst[3], co
             double rel[3] = {v[0] - E.u[0], v[1] - E.u[1], v[2] - E.u[2]};
             double sv = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
             double lam = E.n_gas * E.sigma * (sv + E.abar);
-            lv = lam * dt >= s->op.lv_switch;
+            lv = lam * s->op.dt >= s->op.lv_switch; /* switch on the reference (largest) step */
         }
         if (lv) {
             double xi[3];
@@ -1132,14 +1139,96 @@ int64_t orc_read_samples(const orc_sim *s, orc_sample *buf, int64_t cap) {
     return s->n_samples;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Adaptive global step, Eq. 1:                                             */
+/*   dt = min(0.05 t_RF, 0.1 tau_collision, dt_acc, dt_CFL, dt_L, dt_rem).   */
+/* Readings, per active pack at the start of the step (time t0):            */
+/*  - tau_collision = 1/lambda, lambda = n sigma (|v - u| + abar) the       */
+/*    candidate rate of the explicit branch, for packs on that branch;     */
+/*  - dt_acc = 0.1 (|v - u| + sqrt(kB T/m)) / |a|, a = (q/m) E(x, t0): the  */
+/*    velocity change of a step stays within a tenth of the pack's speed   */
+/*    relative to the gas plus its thermal speed; a pack with no such speed */
+/*    (at rest, no gas) takes sqrt(min(dr, dz)/|a|) instead, the time to    */
+/*    move half a spacing from rest;                                       */
+/*  - dt_CFL = (1/2) min(dr, dz) / |v| (half the smallest spacing);        */
+/*  - dt_L = lv_dt_max while any active pack takes the Langevin branch,     */
+/*    whose switch compares lambda with the reference step dt_max;         */
+/*  - dt_rem: time left to the next space-charge update, which runs every   */
+/*    sc_every * dt_max of simulated time (dt_max = the operating dt, also  */
+/*    the largest step);                                                   */
+/*  - t_RF = 1/f_RF when an RF amplitude is set.                           */
+/* Pinned: each term alone against its closed form, the space-charge       */
+/* updates landing on their times, and the time sum.  A space-charge       */
+/* update is due once t0 is within 1e-6 dt_max of its time.                */
+/* ------------------------------------------------------------------------ */
+static double pack_dt_limit(const orc_sim *s, int64_t k, double c0, int *langevin) {
+    const ion_t *I = &s->ion[s->tag[k]];
+    double x[3] = {s->x[k], s->y[k], s->z[k]}, v[3] = {s->vx[k], s->vy[k], s->vz[k]}, e[3], u[3], p, tg;
+    double lim = INFINITY;
+    double vn = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (vn > 0.0) lim = fmin(lim, 0.5 * fmin(s->dr, s->dz) / vn);
+    efield(s, x[0], x[1], x[2], c0, e);
+    double an = fabs(I->qm) * sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]);
+    gas_at(s, x[0], x[1], x[2], u, &p, &tg);
+    double rel[3] = {v[0] - u[0], v[1] - u[1], v[2] - u[2]};
+    double sv = sqrt(rel[0] * rel[0] + rel[1] * rel[1] + rel[2] * rel[2]);
+    double vth = tg > 0.0 ? sqrt(KB * tg / I->m) : 0.0;
+    if (an > 0.0) lim = fmin(lim, (sv + vth) > 0.0 ? 0.1 * (sv + vth) / an : sqrt(fmin(s->dr, s->dz) / an));
+    double n_gas = tg > 0.0 ? p / (KB * tg) : 0.0;
+    if (s->op.collisions_on && n_gas > 0.0 && isfinite(n_gas)) {
+        double abar = sqrt(KB * tg / (s->op.gas_mass_da * DALTON)) * sqrt(8.0 / PI);
+        double lam = n_gas * I->in.ccs_m2 * (sv + abar);
+        int in_window = !(s->op.lv_z_hi > s->op.lv_z_lo) || (x[2] >= s->op.lv_z_lo && x[2] < s->op.lv_z_hi);
+        if (s->op.langevin_on && in_window && lam * s->op.dt >= s->op.lv_switch) *langevin = 1;
+        else if (lam > 0.0) lim = fmin(lim, 0.1 / lam);
+    }
+    return lim;
+}
+
+static double global_dt(orc_sim *s, double t0) {
+    double c0 = s->op.v_rf * cos(2.0 * PI * s->op.f_rf * t0 + s->op.phase_rf);
+    double dt = s->op.dt, lim = INFINITY;
+    int lang = 0;
+#pragma omp parallel for reduction(min : lim) reduction(| : lang) schedule(static)
+    for (int64_t k = 0; k < s->n; ++k) {
+        if (s->status[k] != ORC_ACTIVE) continue;
+        int l = 0;
+        double v = pack_dt_limit(s, k, c0, &l);
+        lim = fmin(lim, v);
+        lang |= l;
+    }
+    dt = fmin(dt, lim);
+    if (s->op.v_rf != 0.0 && s->op.f_rf > 0.0) dt = fmin(dt, 0.05 / s->op.f_rf);
+    if (lang && s->op.lv_dt_max > 0.0) dt = fmin(dt, s->op.lv_dt_max);
+    if (s->op.sc_on) dt = fmin(dt, s->t_next_pic - t0);
+    return dt;
+}
+
+double orc_current_time(const orc_sim *s) { return s->t; }
+double orc_last_dt(const orc_sim *s) { return s->last_dt; }
+
 int32_t orc_step(orc_sim *s, int64_t n_steps) {
     if (!s->has_fields || !s->has_op) return -2;
     for (int64_t it = 0; it < n_steps; ++it) {
         int64_t step = s->step;
         if (s->op.sample_every > 0 && s->op.sample_stride > 0 && step % s->op.sample_every == 0) take_samples(s, step);
-        if (s->op.sc_on && step % s->op.sc_every == 0 && orc_pic_update(s) < 0) return -3;
+        double dt = s->op.dt, t0 = (double)step * s->op.dt;
+        if (s->op.adaptive) {
+            t0 = s->t;
+            const double tol = 1e-6 * s->op.dt;
+            if (s->op.sc_on && t0 >= s->t_next_pic - tol) {
+                if (orc_pic_update(s) < 0) return -3;
+                const double period = s->op.sc_every * s->op.dt;
+                while (s->t_next_pic <= t0 + tol) s->t_next_pic += period;
+            }
+            dt = global_dt(s, t0);
+            if (!(dt > 1e-9 * s->op.dt)) return -4; /* step collapsed */
+            for (int si = 0; si < s->n_src; ++si) source_dt(s, &s->src[si], dt);
+        } else if (s->op.sc_on && step % s->op.sc_every == 0 && orc_pic_update(s) < 0) {
+            return -3;
+        }
         for (int si = 0; si < s->n_src; ++si) emit(s, si, due(&s->src[si], step), step);
-        const double dt = s->op.dt, w2 = 2.0 * PI * s->op.f_rf, t0 = (double)step * dt;
+        const double w2 = 2.0 * PI * s->op.f_rf;
         double cst[3] = {s->op.v_rf * cos(w2 * t0 + s->op.phase_rf),
                          s->op.v_rf * cos(w2 * (t0 + 0.5 * dt) + s->op.phase_rf),
                          s->op.v_rf * cos(w2 * (t0 + dt) + s->op.phase_rf)};
@@ -1149,7 +1238,7 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
             if (s->status[k] != ORC_ACTIVE) continue;
             coll_count_t cnt;
             memset(&cnt, 0, sizeof(cnt));
-            advance(s, k, step, cst, &cnt);
+            advance(s, k, step, t0, dt, cst, &cnt);
             nc += cnt.n_cand;
             na += cnt.n_acc;
             ncap += cnt.n_cap;
@@ -1161,6 +1250,8 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
         s->n_cap += ncap;
         s->n_clamp += ncl;
         s->n_lang += nlv;
+        s->last_dt = dt;
+        s->t = s->op.adaptive ? t0 + dt : (double)(step + 1) * s->op.dt;
         s->step++;
     }
     return 0;

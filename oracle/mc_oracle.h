@@ -64,6 +64,12 @@ typedef struct orc_operating {
     /* snapshots: at the start of step n with n % sample_every == 0, every
      * active pack whose id is a multiple of sample_stride (0 = off) */
     int32_t sample_every, sample_stride;
+    /* Eq. 1 adaptive step: off (0) = fixed dt; on (1) = dt is the largest step
+     * and the space-charge update runs every sc_every * dt of simulated time;
+     * lv_dt_max caps the step while any pack takes the Langevin branch
+     * (0 = no cap) */
+    int32_t adaptive;
+    double lv_dt_max;
 } orc_operating;
 
 typedef struct orc_packs {
@@ -139,6 +145,9 @@ int32_t orc_step(orc_sim *s, int64_t n_steps);
 int64_t orc_num_packs(const orc_sim *s);
 int32_t orc_num_threads(void);
 int64_t orc_current_step(const orc_sim *s);
+/* Simulated time at the start of the current step, and the last step taken. */
+double orc_current_time(const orc_sim *s);
+double orc_last_dt(const orc_sim *s);
 int32_t orc_read_packs(const orc_sim *s, orc_packs *out);
 int32_t orc_write_packs(orc_sim *s, const orc_packs *in);
 int32_t orc_read_tallies(const orc_sim *s, orc_tallies *out);

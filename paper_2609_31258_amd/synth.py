@@ -104,6 +104,8 @@ class Operating:
     sc_mask: int = 0              # space charge: Phi = 0 on the metal-mask nodes
     sample_every: int = 0         # trajectory samples every sample_every steps (0 = off)
     sample_stride: int = 0        # ... of the packs whose id is a multiple of sample_stride
+    adaptive: int = 0             # Eq. 1 adaptive step (dt is then the largest step)
+    lv_dt_max: float = 0.0        # adaptive: step cap while any pack is on the Langevin branch
 
 
 @dataclasses.dataclass
