@@ -171,7 +171,20 @@ typedef struct mc_source {
  * active pack whose id is a multiple of sample_stride is recorded
  * (mc_sample_rec) into the buffer sized by mc_options.sample_capacity.
  * 0 turns sampling off; both must be >= 0.  Single contexts only: the
- * serving runtime returns tallies and ignores these two fields. */
+ * serving runtime returns tallies and ignores these two fields.
+ *
+ * adaptive: the global step of Eq. 1, dt_n = min(0.05 t_RF, 0.1 tau_coll,
+ * dt_acc, dt_CFL, dt_L, dt_rem), evaluated on the device at the start of
+ * every step over the active packs (tau_coll = 1/lambda of the packs on the
+ * explicit branch; dt_acc = 0.1 (|v-u| + sqrt(kB T/m))/|qE/m|, or
+ * sqrt(min(dr,dz)/|qE/m|) for a pack with no speed scale; dt_CFL =
+ * min(dr,dz)/(2|v|); dt_L = lv_dt_max (> 0) while any pack takes the
+ * Langevin branch; dt_rem = time to the next space-charge update).  dt is
+ * then the largest step, the space-charge update runs every sc_every * dt
+ * of simulated time, sources emit per step with that step's dt (Eq. 5), and
+ * the Langevin switch always compares with dt.  The step's length costs one
+ * small device-to-host read per step.  A step that collapses below 1e-9 dt
+ * fails with MC_ENUMERIC.  Single contexts only (the server rejects it). */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
     int32_t collisions_on, sc_on, sc_every;
@@ -181,6 +194,8 @@ typedef struct mc_operating {
     double lv_z_lo, lv_z_hi, lv_switch;
     int32_t sc_mask;
     int32_t sample_every, sample_stride;
+    int32_t adaptive;
+    double lv_dt_max;
 } mc_operating;
 
 /* Pack population (host arrays of length n) for snapshot read/write.
@@ -234,6 +249,8 @@ typedef struct mc_sample_rec {
 typedef struct mc_info {
     int64_t step, n_slots, capacity, exit_capacity, device_bytes;
     int32_t nr, nz, n_exit_bins, precision, n_ions, n_sources;
+    double time;             /* simulated time at the start of the next step [s] */
+    double last_dt;          /* length of the last step [s] */
 } mc_info;
 
 /* Per-kernel timing from HIP events (requires mc_options.timing). */

@@ -54,16 +54,22 @@ struct Src {
     int64_t w_fx, q_fx, n_real_fx, acc_fx, emitted;
 };
 
-inline Src make_source(const mc_source &in, int32_t charge_z, double dt) {
-    Src S{};
-    S.in = in;
+// Eq. 5: each step the accumulator receives N_real = I dt / (z e) real ions;
+// a fixed-rate source splits them over its packs_per_step packs.  Redone for
+// every step's dt under the adaptive step.
+inline void source_dt(Src &S, int32_t charge_z, double dt) {
     const double z = (double)charge_z;
-    // Eq. 5: each step the accumulator receives N_real = I dt / (z e) real ions
-    const double n_real = in.current_a * dt / (z * kQe);
-    S.w = in.kind == 1 ? n_real / (double)in.packs_per_step : in.weight;
+    const double n_real = S.in.current_a * dt / (z * kQe);
+    S.w = S.in.kind == 1 ? n_real / (double)S.in.packs_per_step : S.in.weight;
     S.w_fx = fx32_host(S.w);
     S.q_fx = fx32_host(z * S.w);
     S.n_real_fx = fx32_host(n_real);
+}
+
+inline Src make_source(const mc_source &in, int32_t charge_z, double dt) {
+    Src S{};
+    S.in = in;
+    source_dt(S, charge_z, dt);
     return S;
 }
 
@@ -85,12 +91,17 @@ inline int64_t due(Src &S, int64_t step) {
 }
 
 // RF coefficients c = V_RF cos(2 pi f t + phase) at t0, t0 + dt/2, t0 + dt (Eq. 4).
-inline void rf_stages(const mc_operating &op, int64_t step, double *t0, double c[3]) {
+inline void rf_stages_at(const mc_operating &op, double t0, double dt, double c[3]) {
     const double w2 = 2.0 * kPi * op.f_rf;
+    c[0] = op.v_rf * std::cos(w2 * t0 + op.phase_rf);
+    c[1] = op.v_rf * std::cos(w2 * (t0 + 0.5 * dt) + op.phase_rf);
+    c[2] = op.v_rf * std::cos(w2 * (t0 + dt) + op.phase_rf);
+}
+
+// The same for fixed steps: t0 = step dt.
+inline void rf_stages(const mc_operating &op, int64_t step, double *t0, double c[3]) {
     *t0 = (double)step * op.dt;
-    c[0] = op.v_rf * std::cos(w2 * *t0 + op.phase_rf);
-    c[1] = op.v_rf * std::cos(w2 * (*t0 + 0.5 * op.dt) + op.phase_rf);
-    c[2] = op.v_rf * std::cos(w2 * (*t0 + op.dt) + op.phase_rf);
+    rf_stages_at(op, *t0, op.dt, c);
 }
 
 }  // namespace mc

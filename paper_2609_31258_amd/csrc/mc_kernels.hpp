@@ -197,7 +197,7 @@ struct StepArgs {
     double z_det, r_det, R, inv_dr, inv_dz, mg, exit_bin_dt;
     int32_t nr, nz, n_exit_bins, collisions_on;
     int32_t langevin_on;
-    double lv_z_lo, lv_z_hi, lv_switch;
+    double lv_z_lo, lv_z_hi, lv_switch, lv_dt_ref;  // switch: lambda lv_dt_ref >= lv_switch
     uint32_t k0, k1;
 };
 
@@ -378,7 +378,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
                 T lam = ngs * (sv + abar);
                 lang = a.langevin_on && (!(a.lv_z_hi > a.lv_z_lo) || (Z1 >= a.lv_z_lo && Z1 < a.lv_z_hi)) &&
-                       lam * dt >= (T)a.lv_switch;
+                       lam * (T)a.lv_dt_ref >= (T)a.lv_switch;
                 if (lang) {
                     // hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward the gas
                     // velocity over dt, hard-sphere friction rate, Box-Muller normals from one block
@@ -523,6 +523,97 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P
     StepCount n{0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n);
     flush_counts(a.t, n);
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive step (Eq. 1): the per-pack limits at the start of a step (state at
+// t0, RF coefficient c0), minimised over the block and added into one of
+// kHotRep replica lines: word 0 holds the limit's bits (positive doubles
+// order like their bit patterns), word 1 flags a pack on the Langevin
+// branch.  Per pack: half a spacing over |v|; a tenth of the speed scale
+// |v - u| + sqrt(kB T/m) over |qE/m| (the time to move half a spacing from
+// rest when there is no speed scale); 0.1 / lambda on the explicit branch.
+// ---------------------------------------------------------------------------
+constexpr unsigned long long kInfBits = 0x7FF0000000000000ull;
+
+template <class P, class Tab>
+__global__ __launch_bounds__(256) void k_dt_limits(StepArgs<P, Tab> a, unsigned long long *rep) {
+    using T = typename P::T;
+    __shared__ double red[256];
+    __shared__ int any_lang;
+    if (threadIdx.x == 0) any_lang = 0;
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double lim = HUGE_VAL;
+    if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
+        const Species sp = a.sp[a.p.tag[s]];
+        const T x = a.p.x[s], y = a.p.y[s], z = a.p.z[s];
+        double Z = (double)z;
+        if constexpr (P::kTwo) Z += (double)a.p.zl[s];
+        const T vx = a.p.vx[s], vy = a.p.vy[s], vz = a.p.vz[s];
+        const T h = (T)(1.0 / fmax(a.inv_dr, a.inv_dz));
+        const T vn = P::sqrt_(vx * vx + vy * vy + vz * vz);
+        if (vn > (T)0) lim = fmin(lim, (double)((T)0.5 * P::div(h, vn)));
+        T ex, ey, ez;
+        efield(a, x, y, z, (T)a.c0, ex, ey, ez);
+        const T an = (T)fabs(sp.qm) * P::sqrt_(ex * ex + ey * ey + ez * ez);
+        const T rr = P::sqrt_(x * x + y * y);
+        const Cell<T> cl = locate<T>(rr, z, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
+        const Q4<T> g = gather4<T>(a.gtab, a.gsc, cl, a.nr);
+        const T sr = rr > (T)0 ? P::div(g.a, rr) : (T)0;
+        const T rx = vx - sr * x, ry = vy - sr * y, rz = vz - g.b, tg = g.d;
+        const T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
+        const T vth = tg > (T)0 ? P::sqrt_(P::div((T)kB * tg, (T)sp.m)) : (T)0;
+        if (an > (T)0)
+            lim = fmin(lim, (double)((sv + vth) > (T)0 ? (T)0.1 * P::div(sv + vth, an) : P::sqrt_(P::div(h, an))));
+        const T ngs = tg > (T)0 ? P::div(g.c, (T)kB * tg) * (T)sp.ccs : (T)0;
+        if (a.collisions_on && ngs > (T)0 && isfinite(ngs)) {
+            const T abar = P::sqrt_(P::div((T)kB * tg, (T)a.mg)) * (T)1.5957691216057308;
+            const T lam = ngs * (sv + abar);
+            const bool in_window = !(a.lv_z_hi > a.lv_z_lo) || (Z >= a.lv_z_lo && Z < a.lv_z_hi);
+            if (a.langevin_on && in_window && lam * (T)a.lv_dt_ref >= (T)a.lv_switch) atomicOr(&any_lang, 1);
+            else if (lam > (T)0) lim = fmin(lim, (double)P::div((T)0.1, lam));
+        }
+    }
+    red[threadIdx.x] = lim;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        unsigned long long *line = rep + (int64_t)(blockIdx.x & (kHotRep - 1)) * kHotStride;
+        atomicMin(line, (unsigned long long)__double_as_longlong(red[0]));
+        if (any_lang) atomicOr(line + 1, 1ull);
+    }
+}
+
+// Replica lines -> out[0] (limit bits), out[1] (Langevin flag); the lines are
+// reset for the next step.  One block of kHotRep threads.
+static __global__ __launch_bounds__(kHotRep) void k_dt_reduce(unsigned long long *rep, unsigned long long *out) {
+    __shared__ unsigned long long mn[kHotRep], fl[kHotRep];
+    const int k = threadIdx.x;
+    mn[k] = rep[(int64_t)k * kHotStride];
+    fl[k] = rep[(int64_t)k * kHotStride + 1];
+    rep[(int64_t)k * kHotStride] = kInfBits;
+    rep[(int64_t)k * kHotStride + 1] = 0ull;
+    __syncthreads();
+    for (int w = kHotRep / 2; w > 0; w >>= 1) {
+        if (k < w) {
+            mn[k] = mn[k] < mn[k + w] ? mn[k] : mn[k + w];
+            fl[k] |= fl[k + w];
+        }
+        __syncthreads();
+    }
+    if (k == 0) {
+        out[0] = mn[0];
+        out[1] = fl[0];
+    }
+}
+
+static __global__ __launch_bounds__(kHotRep) void k_dt_reset(unsigned long long *rep) {
+    rep[(int64_t)threadIdx.x * kHotStride] = kInfBits;
+    rep[(int64_t)threadIdx.x * kHotStride + 1] = 0ull;
 }
 
 // All resident queries of a server advance one step in one launch; each

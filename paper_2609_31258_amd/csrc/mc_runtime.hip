@@ -64,6 +64,9 @@ struct mc_ctx {
     std::vector<int32_t> mask_nodes;
     MaskCap mcap;
     double *rhs = nullptr, *phi_tmp = nullptr;
+    // adaptive step (Eq. 1)
+    unsigned long long *dt_rep = nullptr, *dt_out = nullptr;
+    double t = 0.0, t_next_pic = 0.0, last_dt = 0.0;
     // trajectory samples
     mc_sample_rec *samples = nullptr;
     unsigned long long *sample_count = nullptr;
@@ -292,8 +295,7 @@ static int32_t emit(mc_ctx *ctx, int si, int64_t count) {
 }
 
 template <class P, class Tab>
-static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
-    if (ctx->n_slots == 0) return MC_OK;
+static StepArgs<P, Tab> step_args(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, double dt) {
     StepArgs<P, Tab> a{};
     a.p = p;
     a.etab = etab_as<Tab>(ctx);
@@ -306,9 +308,10 @@ static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     a.n_slots = ctx->n_slots;
     a.step = ctx->step;
     const mc_operating &op = ctx->op;
-    a.dt = op.dt;
+    a.dt = dt;
+    a.t0 = t0;
     double c[3];
-    rf_stages(op, ctx->step, &a.t0, c);
+    rf_stages_at(op, t0, dt, c);
     a.c0 = c[0];
     a.ch = c[1];
     a.c1 = c[2];
@@ -327,18 +330,70 @@ static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     a.lv_z_lo = op.lv_z_lo;
     a.lv_z_hi = op.lv_z_hi;
     a.lv_switch = op.lv_switch;
+    a.lv_dt_ref = op.dt;
     a.k0 = (uint32_t)ctx->opt.seed;
     a.k1 = (uint32_t)(ctx->opt.seed >> 32);
+    return a;
+}
+
+template <class P, class Tab>
+static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, double dt) {
+    if (ctx->n_slots == 0) return MC_OK;
+    const StepArgs<P, Tab> a = step_args<P, Tab>(ctx, p, t0, dt);
     Timer t(ctx, MC_K_STEP);
     k_step<P, Tab><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a);
     LAUNCHCHK();
     return MC_OK;
 }
 
-static int32_t step_once(mc_ctx *ctx) {
-    if (!ctx->fp32()) return launch_step<P64, double4>(ctx, ctx->p64);
-    if (ctx->bf16()) return launch_step<P32, bf16x4>(ctx, ctx->p32);
-    return launch_step<P32, float4>(ctx, ctx->p32);
+static int32_t step_once(mc_ctx *ctx, double t0, double dt) {
+    if (!ctx->fp32()) return launch_step<P64, double4>(ctx, ctx->p64, t0, dt);
+    if (ctx->bf16()) return launch_step<P32, bf16x4>(ctx, ctx->p32, t0, dt);
+    return launch_step<P32, float4>(ctx, ctx->p32, t0, dt);
+}
+
+// Eq. 1 limits over the active packs at t0: returns the smallest per-pack
+// limit (+inf with no packs) and whether a pack takes the Langevin branch.
+template <class P, class Tab>
+static int32_t pack_limits_t(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, double *lim, bool *lang) {
+    if (ctx->n_slots > 0) {
+        const StepArgs<P, Tab> a = step_args<P, Tab>(ctx, p, t0, ctx->op.dt);
+        k_dt_limits<P, Tab><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a, ctx->dt_rep);
+        LAUNCHCHK();
+    }
+    k_dt_reduce<<<1, kHotRep, 0, ctx->stream>>>(ctx->dt_rep, ctx->dt_out);
+    LAUNCHCHK();
+    unsigned long long h[2];
+    HIPCHK(hipMemcpyAsync(h, ctx->dt_out, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::memcpy(lim, &h[0], sizeof(double));
+    *lang = h[1] != 0;
+    return MC_OK;
+}
+
+static int32_t adaptive_dt(mc_ctx *ctx, double t0, double *dt) {
+    double lim = HUGE_VAL;
+    bool lang = false;
+    int32_t rc;
+    if (!ctx->dt_rep) {
+        rc = dalloc_t(ctx, &ctx->dt_rep, (size_t)kHotLen);
+        if (!rc) rc = dalloc_t(ctx, &ctx->dt_out, 2);
+        if (rc) return rc;
+        k_dt_reset<<<1, kHotRep, 0, ctx->stream>>>(ctx->dt_rep);
+        LAUNCHCHK();
+    }
+    if (!ctx->fp32()) rc = pack_limits_t<P64, double4>(ctx, ctx->p64, t0, &lim, &lang);
+    else if (ctx->bf16()) rc = pack_limits_t<P32, bf16x4>(ctx, ctx->p32, t0, &lim, &lang);
+    else rc = pack_limits_t<P32, float4>(ctx, ctx->p32, t0, &lim, &lang);
+    if (rc) return rc;
+    const mc_operating &op = ctx->op;
+    double d = std::min(op.dt, lim);
+    if (op.v_rf != 0.0 && op.f_rf > 0.0) d = std::min(d, 0.05 / op.f_rf);
+    if (lang && op.lv_dt_max > 0.0) d = std::min(d, op.lv_dt_max);
+    if (op.sc_on) d = std::min(d, ctx->t_next_pic - t0);
+    if (!(d > 1e-9 * op.dt)) return fail(ctx, MC_ENUMERIC, "adaptive step collapsed to " + std::to_string(d) + " s");
+    *dt = d;
+    return MC_OK;
 }
 
 // Capacitance matrix of the metal-mask nodes: one FP64 solve per node, once
@@ -693,7 +748,8 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
     if (!ctx) return MC_EINVAL;
     if (!op || !(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1 || !(op->exit_bin_dt > 0) ||
         !(op->gas_mass_da > 0) || !(op->r_det > 0) || !(op->d_hit >= 0) ||
-        (op->langevin_on && !(op->lv_switch >= 0)) || op->sample_every < 0 || op->sample_stride < 0)
+        (op->langevin_on && !(op->lv_switch >= 0)) || op->sample_every < 0 || op->sample_stride < 0 ||
+        !(op->lv_dt_max >= 0))
         return fail(ctx, MC_EINVAL, "invalid operating point");
     if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "load fields first");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -776,7 +832,20 @@ int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
                     ctx->sample_count, ctx->sample_cap);
             LAUNCHCHK();
         }
-        if (ctx->op.sc_on && ctx->step % ctx->op.sc_every == 0) {
+        double t0 = (double)ctx->step * ctx->op.dt, dt = ctx->op.dt;
+        if (ctx->op.adaptive) {
+            t0 = ctx->t;
+            const double tol = 1e-6 * ctx->op.dt;
+            if (ctx->op.sc_on && t0 >= ctx->t_next_pic - tol) {
+                rc = pic_update(ctx);
+                if (rc) return rc;
+                const double period = ctx->op.sc_every * ctx->op.dt;
+                while (ctx->t_next_pic <= t0 + tol) ctx->t_next_pic += period;
+            }
+            rc = adaptive_dt(ctx, t0, &dt);
+            if (rc) return rc;
+            for (auto &S : ctx->srcs) source_dt(S, ctx->ions[S.in.ion].charge_z, dt);
+        } else if (ctx->op.sc_on && ctx->step % ctx->op.sc_every == 0) {
             rc = pic_update(ctx);
             if (rc) return rc;
         }
@@ -784,8 +853,10 @@ int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
             rc = emit(ctx, (int)si, due(ctx->srcs[si], ctx->step));
             if (rc) return rc;
         }
-        rc = step_once(ctx);
+        rc = step_once(ctx, t0, dt);
         if (rc) return rc;
+        ctx->last_dt = dt;
+        ctx->t = ctx->op.adaptive ? t0 + dt : (double)(ctx->step + 1) * ctx->op.dt;
         ctx->step++;
     }
     return MC_OK;
@@ -815,6 +886,8 @@ int32_t mc_get_info(const mc_ctx *ctx, mc_info *info) {
     info->nz = ctx->nz;
     info->n_exit_bins = ctx->has_op ? ctx->op.n_exit_bins : 0;
     info->precision = ctx->opt.precision;
+    info->time = ctx->t;
+    info->last_dt = ctx->last_dt;
     info->n_ions = (int32_t)ctx->ions.size();
     info->n_sources = (int32_t)ctx->srcs.size();
     return MC_OK;

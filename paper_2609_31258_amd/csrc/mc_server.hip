@@ -447,6 +447,7 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
             a.lv_z_lo = op.lv_z_lo;
             a.lv_z_hi = op.lv_z_hi;
             a.lv_switch = op.lv_switch;
+            a.lv_dt_ref = op.dt;
             a.k0 = (uint32_t)Q.q.seed;
             a.k1 = (uint32_t)(Q.q.seed >> 32);
             ps[ns] = bs;
@@ -819,6 +820,7 @@ static bool valid_query(const mc_server *S, const mc_query *q) {
     const mc_operating &op = q->op;
     if (!(op.dt > 0) || op.sc_every < 1 || op.n_exit_bins < 1 || !(op.exit_bin_dt > 0) || !(op.r_det > 0)) return false;
     if (op.langevin_on && !(op.lv_switch >= 0)) return false;
+    if (op.adaptive) return false;  // fixed steps only: queries are co-stepped
     const mc_source &s = q->source;
     if (s.kind < 0 || s.kind > 2 || !(s.sigma_r > 0) || !(s.r_trunc > 0) || s.n_total < 0) return false;
     if ((s.kind == 1 && s.packs_per_step <= 0) || (s.kind != 1 && !(s.weight > 0))) return false;

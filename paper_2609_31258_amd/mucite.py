@@ -63,7 +63,7 @@ class Operating(C.Structure):
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
                 ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32),
-                ("sample_every", I32), ("sample_stride", I32)]
+                ("sample_every", I32), ("sample_stride", I32), ("adaptive", I32), ("lv_dt_max", F64)]
 
 
 class Packs(C.Structure):
@@ -94,7 +94,7 @@ class SampleRec(C.Structure):
 class Info(C.Structure):
     _fields_ = [("step", I64), ("n_slots", I64), ("capacity", I64), ("exit_capacity", I64), ("device_bytes", I64),
                 ("nr", I32), ("nz", I32), ("n_exit_bins", I32), ("precision", I32), ("n_ions", I32),
-                ("n_sources", I32)]
+                ("n_sources", I32), ("time", F64), ("last_dt", F64)]
 
 
 class Timing(C.Structure):
