@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mc_math64.hpp"
+
 namespace mc {
 
 // Exact SI constants and CODATA 2022 values.
@@ -66,7 +68,8 @@ struct P64 {
     static constexpr bool kTwo = false;
     // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double
     static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
-    static __device__ __forceinline__ double ln(double x) { return log(x); }
+    // every call site passes x in (0, 1] (uniform variates and their products)
+    static __device__ __forceinline__ double ln(double x) { return ln_unit(x); }
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
