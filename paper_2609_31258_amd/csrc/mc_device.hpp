@@ -67,10 +67,24 @@ struct P64 {
     using T = double;
     static constexpr bool kTwo = false;
     // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double
-    static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
+    static __device__ __forceinline__ double u01(uint32_t w) { return fma((double)w, 0x1p-32, 0x1p-33); }  // exact
     // every call site passes x in (0, 1] (uniform variates and their products)
     static __device__ __forceinline__ double ln(double x) { return ln_unit(x); }
-    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    // x >= 0 and zero or normal at every call site: the reciprocal square
+    // root seed refined by two coupled Newton (Goldschmidt) iterations for
+    // y = sqrt(x), h = 1/(2 sqrt(x)), then one residual correction
+    static __device__ __forceinline__ double sqrt_(double x) {
+        const double r = __builtin_amdgcn_rsq(x);
+        double y = x * r, h = 0.5 * r;
+        double e = fma(-y, h, 0.5);
+        y = fma(y, e, y);
+        h = fma(h, e, h);
+        e = fma(-y, h, 0.5);
+        y = fma(y, e, y);
+        h = fma(h, e, h);
+        y = fma(fma(-y, y, x), h, y);
+        return x > 0.0 ? y : 0.0;
+    }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
     static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
@@ -85,7 +99,9 @@ struct P32 {
     using T = float;
     static constexpr bool kTwo = true;
     // the top 24 bits of the same word: ((w >> 8) + 1/2) 2^-24, exact in float
-    static __device__ __forceinline__ float u01(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 0x1p-24f; }
+    static __device__ __forceinline__ float u01(uint32_t w) {
+        return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-25f);  // exact
+    }
     static __device__ __forceinline__ float ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
