@@ -511,11 +511,12 @@ __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount
 }
 
 // Waves per SIMD the step kernel is compiled for (its register budget):
-// the FP64 form holds its loop state in register pairs and fits three
-// waves; the FP32 form with BF16 tables fits five without spilling.
+// the FP64 form holds its loop state in register pairs and runs two waves
+// (three force spills to scratch, which measured slower); the FP32 form
+// with BF16 tables fits five without spilling.
 template <class P, class Tab>
 constexpr int step_waves() {
-    return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 3;
+    return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 2;
 }
 
 template <class P, class Tab>
