@@ -303,6 +303,16 @@ int32_t mc_read_exits(mc_ctx *ctx, mc_exit_rec *buf, int64_t cap, int64_t *n);
 int32_t mc_read_samples(mc_ctx *ctx, mc_sample_rec *buf, int64_t cap, int64_t *n);
 int32_t mc_read_packs(mc_ctx *ctx, mc_packs *out);
 int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in);
+/* Checkpoint and resume.  mc_save_state writes the context's dynamic state
+ * (pack slots, tallies, exit records and samples taken, space-charge field,
+ * step, time, source accumulators) to the file `path`; mc_load_state reads
+ * it into a context whose fields, ions, sources, operating point, seed and
+ * precision were set up exactly as when it was saved (checked against a
+ * fingerprint: MC_EINVAL on a mismatch, a truncated file or a capacity too
+ * small).  Stepping on after a load continues the saved run bit for bit.
+ * Both synchronise the stream. */
+int32_t mc_save_state(mc_ctx *ctx, const char *path);
+int32_t mc_load_state(mc_ctx *ctx, const char *path);
 /* int64 charge grid of the last deposit, nz*nr, units of 2^-32 e. */
 int32_t mc_read_charge(mc_ctx *ctx, int64_t *q);
 /* Space-charge potential and field of the last update (nz*nr each; nullable). */

@@ -508,6 +508,88 @@ static int32_t snapshot_t(mc_ctx *ctx, PackPtrs<T> p) {
 // ---------------------------------------------------------------------------
 // ABI.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Checkpoint and resume.  The file holds the dynamic state of a context: a
+// header (configuration fingerprint, step, time, emission counters), each
+// source's accumulator, then the device arrays -- pack slots, the tally
+// block (counters, exit bins, loss map, histograms), the exit records taken,
+// the space-charge field, potential and charge grid, and the samples.  The
+// configuration itself (fields, ions, sources, operating point) is the
+// caller's to set up identically before mc_load_state; the fingerprint is
+// checked so that a mismatch fails instead of resuming a different run.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct CkptHeader {
+    char magic[8];
+    int32_t abi, precision, nr, nz, n_ions, n_srcs, n_exit_bins, fp32_tables;
+    int64_t cap, n_slots, step, emitted_n, emitted_w, tal_len, n_exits, n_samples;
+    double t, t_next_pic, last_dt;
+    uint64_t seed;
+};
+constexpr char kCkptMagic[8] = {'M', 'U', 'C', 'K', 'P', 'T', '0', '1'};
+
+struct Blob {
+    void *dev;
+    size_t bytes;
+};
+
+// The device arrays of a checkpoint, in file order.
+std::vector<Blob> ckpt_blobs(mc_ctx *ctx, int64_t n_slots, int64_t n_exits, int64_t n_samples) {
+    std::vector<Blob> v;
+    const size_t n = (size_t)n_slots, nn = (size_t)ctx->nr * ctx->nz;
+    if (!ctx->fp32()) {
+        const PackPtrs<double> &p = ctx->p64;
+        for (double *a : {p.x, p.y, p.z, p.vx, p.vy, p.vz, p.e, p.h, p.w}) v.push_back({a, n * 8});
+        v.push_back({p.id, n * 8});
+        v.push_back({p.q, n * 8});
+        v.push_back({p.tag, n * 4});
+        v.push_back({p.status, n * 4});
+    } else {
+        const PackPtrs<float> &p = ctx->p32;
+        for (float *a : {p.x, p.y, p.z, p.xl, p.yl, p.zl, p.vx, p.vy, p.vz, p.e, p.el, p.h}) v.push_back({a, n * 4});
+        v.push_back({p.w, n * 8});
+        v.push_back({p.id, n * 8});
+        v.push_back({p.q, n * 8});
+        v.push_back({p.tag, n * 4});
+        v.push_back({p.status, n * 4});
+    }
+    v.push_back({ctx->tal, (size_t)ctx->tal_len * 8});
+    v.push_back({ctx->tp.exits, (size_t)n_exits * sizeof(mc_exit_rec)});
+    v.push_back({ctx->e_sc, nn * sizeof(double2)});
+    v.push_back({ctx->phi_sc, nn * 8});
+    v.push_back({ctx->qgrid, nn * 8});
+    v.push_back({ctx->samples, (size_t)n_samples * sizeof(mc_sample_rec)});
+    v.push_back({ctx->sample_count, 8});
+    return v;
+}
+
+CkptHeader ckpt_header(const mc_ctx *ctx) {
+    CkptHeader h{};
+    std::memcpy(h.magic, kCkptMagic, 8);
+    h.abi = MC_ABI_VERSION;
+    h.precision = ctx->opt.precision;
+    h.nr = ctx->nr;
+    h.nz = ctx->nz;
+    h.n_ions = (int32_t)ctx->ions.size();
+    h.n_srcs = (int32_t)ctx->srcs.size();
+    h.n_exit_bins = ctx->op.n_exit_bins;
+    h.fp32_tables = ctx->opt.fp32_tables;
+    h.cap = ctx->cap;
+    h.n_slots = ctx->n_slots;
+    h.step = ctx->step;
+    h.emitted_n = ctx->emitted_n;
+    h.emitted_w = ctx->emitted_w;
+    h.tal_len = ctx->tal_len;
+    h.t = ctx->t;
+    h.t_next_pic = ctx->t_next_pic;
+    h.last_dt = ctx->last_dt;
+    h.seed = ctx->opt.seed;
+    return h;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t mc_abi_version(void) { return MC_ABI_VERSION; }
@@ -1072,6 +1154,99 @@ int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in) {
         LAUNCHCHK();
     }
     ctx->n_slots = n;
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return MC_OK;
+}
+
+
+int32_t mc_save_state(mc_ctx *ctx, const char *path) {
+    if (!ctx || !path) return MC_EINVAL;
+    if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    CkptHeader h = ckpt_header(ctx);
+    unsigned long long ne = 0, ns = 0;
+    HIPCHK(hipMemcpy(&ne, ctx->tp.cnt + TC_EXCOUNT, 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&ns, ctx->sample_count, 8, hipMemcpyDeviceToHost));
+    h.n_exits = std::min<int64_t>((int64_t)ne, ctx->tp.exit_cap);
+    h.n_samples = std::min<int64_t>((int64_t)ns, ctx->sample_cap);
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(ctx, MC_EINVAL, std::string("cannot write ") + path);
+    bool ok = std::fwrite(&h, sizeof(h), 1, f) == 1;
+    for (const Src &S : ctx->srcs) {
+        const int64_t st[2] = {S.acc_fx, S.emitted};
+        ok = ok && std::fwrite(st, sizeof(st), 1, f) == 1;
+    }
+    std::vector<char> buf;
+    for (const Blob &b : ckpt_blobs(ctx, h.n_slots, h.n_exits, h.n_samples)) {
+        const int64_t nb = (int64_t)b.bytes;
+        ok = ok && std::fwrite(&nb, 8, 1, f) == 1;
+        if (!ok || nb == 0) continue;
+        buf.resize(b.bytes);
+        if (hipMemcpy(buf.data(), b.dev, b.bytes, hipMemcpyDeviceToHost) != hipSuccess) {
+            std::fclose(f);
+            return fail(ctx, MC_EDEVICE, "reading device state");
+        }
+        ok = std::fwrite(buf.data(), 1, b.bytes, f) == b.bytes;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(ctx, MC_EINVAL, std::string("short write to ") + path);
+    return MC_OK;
+}
+
+int32_t mc_load_state(mc_ctx *ctx, const char *path) {
+    if (!ctx || !path) return MC_EINVAL;
+    if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(ctx, MC_EINVAL, std::string("cannot read ") + path);
+    CkptHeader h{};
+    const CkptHeader want = ckpt_header(ctx);
+    bool ok = std::fread(&h, sizeof(h), 1, f) == 1;
+    std::string why;
+    if (!ok || std::memcmp(h.magic, kCkptMagic, 8) != 0 || h.abi != MC_ABI_VERSION) why = "not a checkpoint of this library";
+    else if (h.precision != want.precision || h.nr != want.nr || h.nz != want.nz || h.n_ions != want.n_ions ||
+             h.n_srcs != want.n_srcs || h.n_exit_bins != want.n_exit_bins || h.fp32_tables != want.fp32_tables ||
+             h.tal_len != want.tal_len || h.seed != want.seed)
+        why = "checkpoint of a different configuration";
+    else if (h.n_slots < 0 || h.n_slots > ctx->cap || h.n_exits < 0 || h.n_exits > ctx->tp.exit_cap ||
+             h.n_samples < 0 || h.n_samples > ctx->sample_cap)
+        why = "checkpoint larger than this context's capacities";
+    std::vector<int64_t> src_state(2 * h.n_srcs);
+    if (why.empty() && h.n_srcs > 0) ok = std::fread(src_state.data(), 16, h.n_srcs, f) == (size_t)h.n_srcs;
+    std::vector<char> buf;
+    if (why.empty()) {
+        for (const Blob &b : ckpt_blobs(ctx, h.n_slots, h.n_exits, h.n_samples)) {
+            int64_t nb = -1;
+            ok = ok && std::fread(&nb, 8, 1, f) == 1 && nb == (int64_t)b.bytes;
+            if (!ok) break;
+            if (nb == 0) continue;
+            buf.resize(b.bytes);
+            ok = std::fread(buf.data(), 1, b.bytes, f) == b.bytes;
+            if (!ok) break;
+            if (hipMemcpy(b.dev, buf.data(), b.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+                std::fclose(f);
+                return fail(ctx, MC_EDEVICE, "writing device state");
+            }
+        }
+        if (!ok) why = "truncated or inconsistent checkpoint";
+    }
+    std::fclose(f);
+    if (!why.empty()) return fail(ctx, MC_EINVAL, why + ": " + path);
+    for (size_t k = 0; k < ctx->srcs.size(); ++k) {
+        ctx->srcs[k].acc_fx = src_state[2 * k];
+        ctx->srcs[k].emitted = src_state[2 * k + 1];
+    }
+    ctx->n_slots = h.n_slots;
+    ctx->step = h.step;
+    ctx->emitted_n = h.emitted_n;
+    ctx->emitted_w = h.emitted_w;
+    ctx->t = h.t;
+    ctx->t_next_pic = h.t_next_pic;
+    ctx->last_dt = h.last_dt;
+    const int32_t rc = fold(ctx);  // static field plus the restored space-charge field
+    if (rc) return rc;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return MC_OK;
 }

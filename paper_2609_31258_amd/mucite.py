@@ -150,6 +150,8 @@ _SIGS = {
     "mc_read_tallies": (I32, [C.c_void_p, C.POINTER(Tallies)]),
     "mc_read_exits": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
     "mc_read_samples": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
+    "mc_save_state": (I32, [C.c_void_p, C.c_char_p]),
+    "mc_load_state": (I32, [C.c_void_p, C.c_char_p]),
     "mc_read_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
     "mc_write_packs": (I32, [C.c_void_p, C.POINTER(Packs)]),
     "mc_read_charge": (I32, [C.c_void_p, PI64]),
@@ -391,6 +393,12 @@ class Sim:
         self._chk(self.L.mc_read_exits(self._h, buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(n)),
                   "mc_read_exits")
         return buf[: min(n.value, buf.size, self.info()["exit_capacity"])]  # records beyond the buffer were dropped
+
+    def save_state(self, path: str) -> None:
+        self._chk(self.L.mc_save_state(self._h, os.fsencode(path)), "mc_save_state")
+
+    def load_state(self, path: str) -> None:
+        self._chk(self.L.mc_load_state(self._h, os.fsencode(path)), "mc_load_state")
 
     def read_samples(self) -> np.ndarray:
         n = I64()
