@@ -273,7 +273,9 @@ void mc_destroy(mc_ctx *ctx);
 const char *mc_last_error(const mc_ctx *ctx);
 
 /* Load and bake the field tables (coordinate-system and gas sections).  May
- * be called once per ctx.  Errors: MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET. */
+ * be called once per ctx.  Errors: MC_EINVAL (also for a non-finite table
+ * value or a negative gas pressure or temperature), MC_ESTATE, MC_ENOMEM,
+ * MC_EBUDGET. */
 int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *grid, const mc_field_tables *tables);
 /* Define an ion template; *ion_id receives its index (species tag of packs). */
 int32_t mc_define_ion(mc_ctx *ctx, const mc_ion *ion, int32_t *ion_id);

@@ -43,6 +43,21 @@ inline void species_alpha(Species &S, const mc_ion &in, double gas_mass_da) {
     S.alpha = in.alpha >= 0.0 ? in.alpha : 4.0 * mg * ma / ((mg + ma) * (mg + ma));
 }
 
+// Every field table present must be finite (a NaN or infinity would turn
+// into non-finite packs at the first gather); gas pressure and temperature
+// must not be negative.
+inline bool valid_tables(const mc_field_tables *t, int64_t nn) {
+    const double *all[] = {t->phi_dc, t->phi_off, t->phi_rf, t->gas_ur, t->gas_uz, t->gas_p, t->gas_t};
+    for (const double *a : all) {
+        if (!a) continue;
+        for (int64_t k = 0; k < nn; ++k)
+            if (!std::isfinite(a[k])) return false;
+    }
+    for (int64_t k = 0; k < nn; ++k)
+        if (t->gas_p[k] < 0.0 || t->gas_t[k] < 0.0) return false;
+    return true;
+}
+
 inline bool valid_ion(const mc_ion *ion) {
     return ion && ion->n_atoms >= 3 && ion->mass_da > 0 && ion->charge_z != 0 && ion->ccs_m2 >= 0 &&
            ion->theta_e > 0 && ion->act_kind >= 0 && ion->act_kind <= 2;

@@ -694,6 +694,8 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     if (!g || !t || !t->phi_dc || !t->gas_p || !t->gas_t) return fail(ctx, MC_EINVAL, "missing grid or tables");
     if (g->nr < 3 || g->nz < 3 || !(g->dr > 0) || !(g->dz > 0)) return fail(ctx, MC_EINVAL, "bad grid");
     if (ctx->has_fields) return fail(ctx, MC_ESTATE, "fields already loaded");
+    if (!valid_tables(t, (int64_t)g->nr * g->nz))
+        return fail(ctx, MC_EINVAL, "field table with a non-finite value or a negative pressure or temperature");
     HIPCHK(hipSetDevice(ctx->opt.device));
     ctx->nr = g->nr;
     ctx->nz = g->nz;

@@ -658,6 +658,7 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
         (o->precision != MC_PREC_FP64 && o->precision != MC_PREC_FP32) || (!o->alloc) != (!o->free) ||
         !(o->gas_mass_da > 0) || !(o->d_hit >= 0) || g->nr < 3 || g->nz < 3 || !(g->dr > 0) || !(g->dz > 0))
         return MC_EINVAL;
+    if (!valid_tables(t, (int64_t)g->nr * g->nz)) return MC_EINVAL;
     mc_server *S = new (std::nothrow) mc_server();
     if (!S) return MC_ENOMEM;
     S->opt = *o;

@@ -116,3 +116,17 @@ def test_capacity_and_argument_errors_leave_the_context_usable():
     t = g.read_tallies()
     assert t["emitted_n"] == 400 and t["class_n"].sum() == 400 and t["pack_steps"] == 800
     g.close()
+
+
+def test_non_finite_field_tables_are_refused():
+    from paper_2609_31258_amd import mucite
+    f, ions, srcs, op, _ = synth.config_c1(100)
+    for name, value in (("phi_dc", np.nan), ("gas_uz", np.inf), ("gas_p", -1.0)):
+        bad = synth.Fields(**{**f.__dict__, name: getattr(f, name).copy()})
+        getattr(bad, name)[7, 3] = value
+        g = mucite.Sim(seed=7, pack_capacity=16, precision=0)
+        with pytest.raises(mucite.MucateError) as e:
+            g.load_fields(bad)
+        assert e.value.code == mucite.MC_EINVAL, name
+        g.load_fields(f)  # the context is still usable
+        g.close()
