@@ -351,7 +351,7 @@ def copy_calibration():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it"}))
+        print(json.dumps({"error": "the path runs on one GPU: multi-GPU runs are not implemented"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"

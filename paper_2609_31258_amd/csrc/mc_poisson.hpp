@@ -95,29 +95,66 @@ static __global__ __launch_bounds__(256) void k_thomas_coef(double *cp, double *
     }
 }
 
+// One tridiagonal system per mode k (one thread each, coalesced across k).
+// The sweeps are a chain of dependent updates, so each group of kThomasGroup
+// rows has all of its loads issued before its updates: one memory latency per
+// group instead of one per row.
+constexpr int kThomasGroup = 16;
+
 template <class D>
 __global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const double *inv, int32_t nr, int32_t nz,
                                                 double dr) {
+    constexpr int U = kThomasGroup;
     const int32_t m = nz - 2, nu = nr - 1;
     const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
     // forward sweep in FP64
     double dprev = 0.0;
-    for (int32_t i = 0; i < nu; ++i) {
-        const int64_t o = (int64_t)i * m + k;
-        double lo = 0.0;
-        if (i > 0) {
-            const double ri = (double)i * dr;
-            lo = (ri - 0.5 * dr) / (ri * dr * dr);
+    for (int32_t i0 = 0; i0 < nu; i0 += U) {
+        double b[U], v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t i = i0 + u;
+            if (i < nu) {
+                const int64_t o = (int64_t)i * m + k;
+                b[u] = (double)bh[o];
+                v[u] = inv[o];
+            }
         }
-        dprev = ((double)bh[o] - lo * dprev) * inv[o];
-        bh[o] = (D)dprev;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t i = i0 + u;
+            if (i < nu) {
+                double lo = 0.0;
+                if (i > 0) {
+                    const double ri = (double)i * dr;
+                    lo = (ri - 0.5 * dr) / (ri * dr * dr);
+                }
+                dprev = (b[u] - lo * dprev) * v[u];
+                bh[(int64_t)i * m + k] = (D)dprev;
+            }
+        }
     }
     double x = 0.0;
-    for (int32_t i = nu - 1; i >= 0; --i) {
-        const int64_t o = (int64_t)i * m + k;
-        x = (i == nu - 1) ? (double)bh[o] : (double)bh[o] - cp[o] * x;
-        bh[o] = (D)x;
+    for (int32_t i1 = nu - 1; i1 >= 0; i1 -= U) {
+        double b[U], c[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t i = i1 - u;
+            if (i >= 0) {
+                const int64_t o = (int64_t)i * m + k;
+                b[u] = (double)bh[o];
+                c[u] = cp[o];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t i = i1 - u;
+            if (i >= 0) {
+                x = (i == nu - 1) ? b[u] : b[u] - c[u] * x;
+                bh[(int64_t)i * m + k] = (D)x;
+            }
+        }
     }
 }
 
