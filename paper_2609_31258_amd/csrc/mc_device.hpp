@@ -71,8 +71,9 @@ __device__ __forceinline__ W4 draw(int64_t id, int64_t step, uint32_t purpose, u
 struct P64 {
     using T = double;
     static constexpr bool kTwo = false;
-    // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double
-    static __device__ __forceinline__ double u01(uint32_t w) { return fma((double)w, 0x1p-32, 0x1p-33); }  // exact
+    // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double (an add of an
+    // inline constant and an exponent shift: no 64-bit constant in a register)
+    static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
     // every call site passes x in (0, 1] (uniform variates and their products)
     static __device__ __forceinline__ double ln(double x) { return ln_unit(x); }
     // x >= 0 and zero or normal at every call site: the reciprocal square

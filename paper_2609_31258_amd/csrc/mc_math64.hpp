@@ -8,6 +8,7 @@
 // host against the C library) in about half the instructions, which makes
 // the FP64 step 12 % faster.
 //
+//   div_mid(n, d)    n / d for d in [1, 4), |n| < 1 (its quotient step)
 //   ln_unit(x)       natural logarithm, 0 < x <= 1, x normal
 //
 // Plain C++ (host and device).
@@ -22,6 +23,25 @@
 
 namespace mc {
 
+// num / den for den in [1, 4) and |num| < 1, where no operand scaling or
+// special case can arise.  On the device: the reciprocal estimate refined by
+// two Newton steps, the quotient and one residual correction, which is the
+// arithmetic of the compiler's double division without its range scaling and
+// fix-up (so the same quotient in four fewer instructions).
+MC_HD double div_mid(double num, double den) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rcp(den);
+    double e = std::fma(-den, r, 1.0);
+    r = std::fma(r, e, r);
+    e = std::fma(-den, r, 1.0);
+    r = std::fma(r, e, r);
+    const double q = num * r;
+    return std::fma(std::fma(-den, q, num), r, q);
+#else
+    return num / den;
+#endif
+}
+
 // ln x = e ln 2 + ln m, x = m 2^e with m in [sqrt(1/2), sqrt(2)); then
 // ln m = 2 atanh f = 2 (f + f^3/3 + f^5/5 + ...), f = (m - 1)/(m + 1),
 // |f| <= 0.1716, so f^2 <= 0.0295 and ten terms after the first leave a
@@ -35,7 +55,7 @@ MC_HD double ln_unit(double x) {
         --e;
     }
     const double num = m - 1.0, den = m + 1.0;  // both exact
-    const double f = num / den;
+    const double f = div_mid(num, den);
     const double g = f * f;
     double p = 1.0 / 21.0;
     p = std::fma(p, g, 1.0 / 19.0);
