@@ -19,6 +19,8 @@
 #include "../../include/mucite.h"
 #include "mc_device.hpp"
 
+#include <type_traits>
+
 namespace mc {
 
 template <class T>
@@ -268,12 +270,16 @@ struct StepCount {
 
 // One pack, one step.
 template <class P, class Tab>
-__device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n) {
+__device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n, uint32_t k0, uint32_t k1) {
     using T = typename P::T;
     uint32_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0;  // per pack and step: < 2^32
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
         n.act = 1;
-        const Species sp = a.sp[a.p.tag[s]];
+        // FP32 form: a reference, so each field is read where it is used and the
+        // dissociation constants hold no registers through the collision loop
+        // (at five waves they would spill); FP64: one copy of the record
+        using SpeciesRef = std::conditional_t<P::kTwo, const Species &, const Species>;
+        SpeciesRef sp = a.sp[a.p.tag[s]];
         const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
         const T x0 = a.p.x[s], y0 = a.p.y[s], z0 = a.p.z[s];
         T xl = 0, yl = 0, zl = 0;
@@ -382,7 +388,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 if (lang) {
                     // hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward the gas
                     // velocity over dt, hard-sphere friction rate, Box-Muller normals from one block
-                    const W4 w = draw(a.p.id[s], a.step, kPurposeLangevin, 0u, a.k0, a.k1);
+                    const W4 w = draw(a.p.id[s], a.step, kPurposeLangevin, 0u, k0, k1);
                     const T r0 = P::sqrt_((T)-2 * P::ln(P::u01(w.w0)));
                     const T r1 = P::sqrt_((T)-2 * P::ln(P::u01(w.w2)));
                     T s0, c0;
@@ -407,12 +413,12 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                         ++ncap;
                         break;
                     }
-                    const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), a.k0, a.k1);
+                    const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), k0, k1);
                     const T tau = -P::div(P::ln(P::u01(wa.w0)), lam);
                     if (!(tau < tleft)) break;
                     tleft -= tau;
                     ++ncand;
-                    const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), a.k0, a.k1);
+                    const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), k0, k1);
                     // partner thermal velocity: E = |w|^2/(2 a^2) ~ Gamma(3/2) (Maxwellian branch)
                     // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
                     const bool maxw = P::u01(wa.w1) * (sv + abar) < sv;  // u < s/(s + abar)
@@ -430,7 +436,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     const T uacc = P::u01(wb.w3);
                     if (!(uacc * (sv + wn) < gn)) continue;
                     ++nacc;
-                    const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), a.k0, a.k1);
+                    const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), k0, k1);
                     // centre of mass of the ion and the partner (lab velocity u + w)
                     const T vcx = fi * vx + fm * (ux + wx), vcy = fi * vy + fm * (uy + wy), vcz = fi * vz + fm * (uz + wz);
                     const T et = (T)0.5 * mu * g2;
@@ -522,7 +528,7 @@ constexpr int step_waves() {
 template <class P, class Tab>
 __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
     StepCount n{0, 0, 0, 0, 0, 0};
-    step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n);
+    step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
     flush_counts(a.t, n);
 }
 
@@ -625,7 +631,9 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(cons
     const int q = block_query(prefix, nq);
     const StepArgs<P, Tab> &a = descs[q];
     StepCount n{0, 0, 0, 0, 0, 0};
-    step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n);
+    // the random key is the query's, the same for the whole block: scalar
+    step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n,
+             __builtin_amdgcn_readfirstlane(a.k0), __builtin_amdgcn_readfirstlane(a.k1));
     flush_counts(a.t, n);
 }
 

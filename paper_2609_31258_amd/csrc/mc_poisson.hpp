@@ -101,6 +101,12 @@ static __global__ __launch_bounds__(256) void k_thomas_coef(double *cp, double *
 // group instead of one per row.
 constexpr int kThomasGroup = 16;
 
+// Lower diagonal of the radial operator in row i >= 1.
+__device__ __forceinline__ double thomas_lower(int32_t i, double dr) {
+    const double ri = (double)i * dr;
+    return (ri - 0.5 * dr) / (ri * dr * dr);
+}
+
 template <class D>
 __global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const double *inv, int32_t nr, int32_t nz,
                                                 double dr) {
@@ -108,53 +114,51 @@ __global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const d
     const int32_t m = nz - 2, nu = nr - 1;
     const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= m) return;
-    // forward sweep in FP64
+    // forward sweep in FP64: whole groups (loads first), then the remaining rows
     double dprev = 0.0;
-    for (int32_t i0 = 0; i0 < nu; i0 += U) {
+    int32_t i = 0;
+    for (; i + U <= nu; i += U) {
         double b[U], v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t i = i0 + u;
-            if (i < nu) {
-                const int64_t o = (int64_t)i * m + k;
-                b[u] = (double)bh[o];
-                v[u] = inv[o];
-            }
+            const int64_t o = (int64_t)(i + u) * m + k;
+            b[u] = (double)bh[o];
+            v[u] = inv[o];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t i = i0 + u;
-            if (i < nu) {
-                double lo = 0.0;
-                if (i > 0) {
-                    const double ri = (double)i * dr;
-                    lo = (ri - 0.5 * dr) / (ri * dr * dr);
-                }
-                dprev = (b[u] - lo * dprev) * v[u];
-                bh[(int64_t)i * m + k] = (D)dprev;
-            }
+            const double lo = (i + u > 0) ? thomas_lower(i + u, dr) : 0.0;
+            dprev = (b[u] - lo * dprev) * v[u];
+            bh[(int64_t)(i + u) * m + k] = (D)dprev;
         }
     }
-    double x = 0.0;
-    for (int32_t i1 = nu - 1; i1 >= 0; i1 -= U) {
+    for (; i < nu; ++i) {
+        const int64_t o = (int64_t)i * m + k;
+        const double lo = (i > 0) ? thomas_lower(i, dr) : 0.0;
+        dprev = ((double)bh[o] - lo * dprev) * inv[o];
+        bh[o] = (D)dprev;
+    }
+    // back substitution: the last row, then whole groups downwards, then the rest
+    double x = (double)bh[(int64_t)(nu - 1) * m + k];
+    i = nu - 2;
+    for (; i - U + 1 >= 0; i -= U) {
         double b[U], c[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t i = i1 - u;
-            if (i >= 0) {
-                const int64_t o = (int64_t)i * m + k;
-                b[u] = (double)bh[o];
-                c[u] = cp[o];
-            }
+            const int64_t o = (int64_t)(i - u) * m + k;
+            b[u] = (double)bh[o];
+            c[u] = cp[o];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t i = i1 - u;
-            if (i >= 0) {
-                x = (i == nu - 1) ? b[u] : b[u] - c[u] * x;
-                bh[(int64_t)i * m + k] = (D)x;
-            }
+            x = b[u] - c[u] * x;
+            bh[(int64_t)(i - u) * m + k] = (D)x;
         }
+    }
+    for (; i >= 0; --i) {
+        const int64_t o = (int64_t)i * m + k;
+        x = (double)bh[o] - cp[o] * x;
+        bh[o] = (D)x;
     }
 }
 
