@@ -70,14 +70,15 @@ def test_query_result_is_the_same_alone_and_in_a_mix(precision):
     assert ra["tallies"]["pack_steps"] > 0 and ra["tallies"]["emitted_n"] == 2000
 
 
-def test_query_equals_the_single_context_run():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_query_equals_the_single_context_run(precision):
     from paper_2609_31258_amd import mucite
     f = _fields()
     ion, src, op, steps, seed = _query(f)
-    _say("serving vs single context")
-    with mucite.Server(f, hbm_budget=1 << 30, precision=0, max_resident=4, steps_per_sync=5) as s:
+    _say("serving vs single context, precision", precision)
+    with mucite.Server(f, hbm_budget=1 << 30, precision=precision, max_resident=4, steps_per_sync=5) as s:
         r = s.wait(s.submit(ion, src, op, n_steps=steps, seed=seed))
-    sim = mucite.Sim(seed=seed, pack_capacity=src.n_total, precision=0)
+    sim = mucite.Sim(seed=seed, pack_capacity=src.n_total, precision=precision)
     sim.setup(f, [ion], [src], op)
     sim.step(steps)
     t = sim.read_tallies()
