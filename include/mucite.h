@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 2
+#define MC_ABI_VERSION 3
 
 enum {
     MC_OK = 0,
@@ -358,7 +358,10 @@ typedef struct mc_server_options {
 
 /* A design query.  source.ion is ignored (the query's own ion); op.d_hit and
  * op.gas_mass_da are ignored (the server's).  kind 0 sources emit n_total
- * packs at the query's first step.  exit_capacity: exit records kept (0 = none). */
+ * packs at the query's first step.  exit_capacity: exit records kept (0 = none);
+ * sample_capacity: trajectory samples kept (0 = none), taken on the schedule of
+ * op.sample_every / op.sample_stride as in a single run.  op.adaptive must be 0
+ * (queries are co-stepped with fixed steps). */
 typedef struct mc_query {
     mc_ion ion;
     mc_source source;
@@ -366,18 +369,29 @@ typedef struct mc_query {
     int64_t n_steps;
     uint64_t seed;
     int64_t exit_capacity;
+    int64_t sample_capacity;
 } mc_query;
 
 enum { MC_Q_PENDING = 0, MC_Q_RUNNING = 1, MC_Q_DONE = 2, MC_Q_FAILED = 3 };
 
 /* Result of a query.  Before polling, set the tally array pointers you want
- * (sizes as for mc_read_tallies with the query's n_exit_bins) or NULL.
- * Times are seconds on the server clock (0 at creation). */
+ * (sizes as for mc_read_tallies with the query's n_exit_bins) or NULL, and
+ * the exit-record and sample buffers with their lengths in records (or NULL).
+ * Once the query is done, n_exits / n_samples give the records it kept (at
+ * most its capacities) and the first min(n, length) of them, in the order the
+ * device appended them, are copied into the buffers.  Times are seconds on the
+ * server clock (0 at creation). */
 typedef struct mc_query_result {
     int32_t state, error;
     double t_submit, t_admit, t_done;
     int64_t device_bytes;
     mc_tallies tallies;
+    mc_exit_rec *exits;        /* in: buffer or NULL */
+    int64_t exits_len;         /* in: its length in records */
+    int64_t n_exits;           /* out */
+    mc_sample_rec *samples;    /* in: buffer or NULL */
+    int64_t samples_len;       /* in */
+    int64_t n_samples;         /* out */
 } mc_query_result;
 
 typedef struct mc_server_stats {

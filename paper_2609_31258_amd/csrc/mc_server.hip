@@ -52,12 +52,16 @@ struct Query {
     double *phi = nullptr, *partial = nullptr, *sums = nullptr, *rhs = nullptr;
     unsigned long long *qgrid = nullptr, *tal = nullptr, *snap = nullptr;
     int64_t tal_len = 0;
+    mc_sample_rec *samples = nullptr;
+    unsigned long long *scount = nullptr;
     TallyPtrs tp{};
     Species *sp_dev = nullptr;
     int32_t *charge_dev = nullptr;
     // host result
     mc_tallies r{};
     std::vector<int64_t> r_bins, r_loss, r_hke, r_hte, r_hr, r_ahke, r_ahte;
+    std::vector<mc_exit_rec> r_exits;
+    std::vector<mc_sample_rec> r_samples;
 };
 
 }  // namespace
@@ -187,6 +191,8 @@ static int64_t query_layout(const mc_server *S, const Query &Q, F &&place) {
     place("sp", 0, L.take(sizeof(Species)));
     place("charge", 0, L.take(4));
     place("exits", 0, L.take(std::max<int64_t>(Q.q.exit_capacity, 0) * (int64_t)sizeof(mc_exit_rec)));
+    place("samples", 0, L.take(std::max<int64_t>(Q.q.sample_capacity, 0) * (int64_t)sizeof(mc_sample_rec)));
+    place("scount", 0, L.take(8));
     return L.off;
 }
 
@@ -238,6 +244,10 @@ static void bind_query(mc_server *S, Query &Q) {
             Q.charge_dev = (int32_t *)p;
         } else if (w == "exits") {
             Q.tp.exits = (mc_exit_rec *)p;
+        } else if (w == "samples") {
+            Q.samples = (mc_sample_rec *)p;
+        } else if (w == "scount") {
+            Q.scount = (unsigned long long *)p;
         }
     });
     if (S->fp32()) {
@@ -283,6 +293,7 @@ template <class P, class Tab>
 static int32_t admit_query(mc_server *S, Query &Q) {
     bind_query(S, Q);
     k_zero_u64<<<blocks_for(Q.tal_len), kBlk, 0, S->stream>>>(Q.tal, Q.tal_len);
+    k_zero_u64<<<1, kBlk, 0, S->stream>>>(Q.scount, 1);
     SCHK(hipGetLastError());
     const int64_t nn = (int64_t)S->nr * S->nz;
     if (Q.q.op.sc_on) {
@@ -377,6 +388,15 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
     int ne = 0, ns = 0, be = 0, bs = 0;
     for (Query *Qp : act) {
         Query &Q = *Qp;
+        // trajectory samples at the start of the step, before the space-charge update and emission
+        const mc_operating &qo = Q.q.op;
+        if (qo.sample_every > 0 && qo.sample_stride > 0 && Q.step % qo.sample_every == 0 && Q.n_slots > 0 &&
+            Q.q.sample_capacity > 0) {
+            k_sample<D><<<blocks_for(Q.n_slots), kBlk, 0, S->stream>>>(packs_of<P, Tab>(Q), Q.sp_dev, Q.n_slots,
+                                                                      Q.step, qo.sample_stride, Q.samples,
+                                                                      Q.scount, Q.q.sample_capacity);
+            SCHK(hipGetLastError());
+        }
         if (Q.q.op.sc_on && Q.step % Q.q.op.sc_every == 0) {
             int32_t rc = pic_query<P, Tab, D>(S, Q, packs_of<P, Tab>(Q));
             if (rc) return rc;
@@ -491,10 +511,24 @@ static int32_t retire_query(mc_server *S, Query &Q, PackPtrs<T> p) {
     SCHK(hipGetLastError());
     std::vector<unsigned long long> tal(Q.tal_len), snap(ns);
     double sums[4];
+    unsigned long long nsamp = 0;
     SCHK(hipMemcpyAsync(tal.data(), Q.tal, Q.tal_len * 8, hipMemcpyDeviceToHost, S->stream));
     SCHK(hipMemcpyAsync(snap.data(), Q.snap, ns * 8, hipMemcpyDeviceToHost, S->stream));
     SCHK(hipMemcpyAsync(sums, Q.sums, 4 * 8, hipMemcpyDeviceToHost, S->stream));
+    SCHK(hipMemcpyAsync(&nsamp, Q.scount, 8, hipMemcpyDeviceToHost, S->stream));
     SCHK(hipStreamSynchronize(S->stream));
+    // exit records and samples the query kept (appends beyond the capacity were counted, not stored)
+    const int64_t nex = std::min<int64_t>((int64_t)tal[TC_EXCOUNT], Q.tp.exit_cap);
+    Q.r_exits.resize((size_t)std::max<int64_t>(nex, 0));
+    if (nex > 0)
+        SCHK(hipMemcpyAsync(Q.r_exits.data(), Q.tp.exits, nex * sizeof(mc_exit_rec), hipMemcpyDeviceToHost,
+                            S->stream));
+    const int64_t nsm = std::min<int64_t>((int64_t)nsamp, std::max<int64_t>(Q.q.sample_capacity, 0));
+    Q.r_samples.resize((size_t)std::max<int64_t>(nsm, 0));
+    if (nsm > 0)
+        SCHK(hipMemcpyAsync(Q.r_samples.data(), Q.samples, nsm * sizeof(mc_sample_rec), hipMemcpyDeviceToHost,
+                            S->stream));
+    if (nex > 0 || nsm > 0) SCHK(hipStreamSynchronize(S->stream));
     fold_hot(tal.data() + (Q.tal_len - kHotLen), tal.data());
     mc_tallies &r = Q.r;
     r.emitted_n = Q.emitted_n;
@@ -822,6 +856,7 @@ static bool valid_query(const mc_server *S, const mc_query *q) {
     if (!(op.dt > 0) || op.sc_every < 1 || op.n_exit_bins < 1 || !(op.exit_bin_dt > 0) || !(op.r_det > 0)) return false;
     if (op.langevin_on && !(op.lv_switch >= 0)) return false;
     if (op.adaptive) return false;  // fixed steps only: queries are co-stepped
+    if (op.sample_every < 0 || op.sample_stride < 0 || q->sample_capacity < 0) return false;
     const mc_source &s = q->source;
     if (s.kind < 0 || s.kind > 2 || !(s.sigma_r > 0) || !(s.r_trunc > 0) || s.n_total < 0) return false;
     if ((s.kind == 1 && s.packs_per_step <= 0) || (s.kind != 1 && !(s.weight > 0))) return false;
@@ -894,6 +929,17 @@ static int32_t poll_locked(mc_server *S, uint64_t qid, mc_query_result *out) {
         copy_arr(o.hist_r, Q.r_hr);
         copy_arr(o.act_hist_ke, Q.r_ahke);
         copy_arr(o.act_hist_teff, Q.r_ahte);
+        out->n_exits = (int64_t)Q.r_exits.size();
+        if (out->exits && out->exits_len > 0)
+            std::memcpy(out->exits, Q.r_exits.data(),
+                        (size_t)std::min<int64_t>(out->n_exits, out->exits_len) * sizeof(mc_exit_rec));
+        out->n_samples = (int64_t)Q.r_samples.size();
+        if (out->samples && out->samples_len > 0)
+            std::memcpy(out->samples, Q.r_samples.data(),
+                        (size_t)std::min<int64_t>(out->n_samples, out->samples_len) * sizeof(mc_sample_rec));
+    } else {
+        out->n_exits = 0;
+        out->n_samples = 0;
     }
     return MC_OK;
 }

@@ -23,7 +23,7 @@ PD, PI64, PI32, PU8 = C.POINTER(F64), C.POINTER(I64), C.POINTER(I32), C.POINTER(
 
 MC_OK, MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE, MC_ENUMERIC, MC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PREC_FP64, PREC_FP32 = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 NCLASS = 6
 HIST_KE, HIST_TEFF, HIST_R = 202, 202, 102
 K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY = range(6)
@@ -110,12 +110,13 @@ class ServerOptions(C.Structure):
 
 class Query(C.Structure):
     _fields_ = [("ion", Ion), ("source", Source), ("op", Operating), ("n_steps", I64), ("seed", U64),
-                ("exit_capacity", I64)]
+                ("exit_capacity", I64), ("sample_capacity", I64)]
 
 
 class QueryResult(C.Structure):
     _fields_ = [("state", I32), ("error", I32), ("t_submit", F64), ("t_admit", F64), ("t_done", F64),
-                ("device_bytes", I64), ("tallies", Tallies)]
+                ("device_bytes", I64), ("tallies", Tallies), ("exits", C.c_void_p), ("exits_len", I64),
+                ("n_exits", I64), ("samples", C.c_void_p), ("samples_len", I64), ("n_samples", I64)]
 
 
 class ServerStats(C.Structure):
@@ -473,6 +474,7 @@ class Server:
         if rc != MC_OK:
             raise MucateError(rc, "mc_server_create", "server creation failed")
         self._bins: Dict[int, int] = {}
+        self._caps: Dict[int, tuple] = {}
 
     def close(self):
         if getattr(self, "_h", None):
@@ -495,7 +497,8 @@ class Server:
         if rc != MC_OK:
             raise MucateError(rc, where, (self.L.mc_server_last_error(self._h) or b"").decode())
 
-    def submit(self, ion, source, op, n_steps: int, seed: int, exit_capacity: int = 0) -> int:
+    def submit(self, ion, source, op, n_steps: int, seed: int, exit_capacity: int = 0,
+               sample_capacity: int = 0) -> int:
         q = Query()
         q.ion = _struct(Ion, ion)
         q.source = _struct(Source, source)
@@ -503,9 +506,11 @@ class Server:
         q.n_steps = n_steps
         q.seed = seed
         q.exit_capacity = exit_capacity
+        q.sample_capacity = sample_capacity
         out = U64()
         self._chk(self.L.mc_server_submit(self._h, C.byref(q), C.byref(out)), "mc_server_submit")
         self._bins[out.value] = op.n_exit_bins
+        self._caps[out.value] = (exit_capacity, sample_capacity)
         return out.value
 
     def _result(self, qid: int, fn, *args):
@@ -513,6 +518,11 @@ class Server:
         bufs = _tally_buffers(self.nz, self.nr, self._bins.get(qid, 1))
         for k, a in bufs.items():
             setattr(r.tallies, k, _p(a, I64))
+        ecap, scap = self._caps.get(qid, (0, 0))
+        exits = np.zeros(max(ecap, 1), dtype=EXIT_DTYPE)
+        samples = np.zeros(max(scap, 1), dtype=SAMPLE_DTYPE)
+        r.exits, r.exits_len = exits.ctypes.data, ecap
+        r.samples, r.samples_len = samples.ctypes.data, scap
         self._chk(fn(self._h, qid, *args, C.byref(r)), fn.__name__)
         out = dict(state=r.state, error=r.error, t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done,
                    device_bytes=r.device_bytes)
@@ -526,6 +536,8 @@ class Server:
             tal["class_n"] = np.array(list(T.class_n), np.int64)
             tal["class_w"] = np.array(list(T.class_w), np.int64)
             out["tallies"] = tal
+            out["exits"] = exits[: min(r.n_exits, ecap)]
+            out["samples"] = samples[: min(r.n_samples, scap)]
         return out
 
     def poll(self, qid: int) -> Dict[str, object]:

@@ -134,3 +134,52 @@ def test_many_queries_of_uneven_size():
         assert t["class_w"].sum() == t["emitted_w"]
     lat = np.array([r["t_done"] - r["t_submit"] for r in rs])
     _say(f"  latency p50 {np.median(lat):.3f} s p99 {np.quantile(lat, 0.99):.3f} s, co-steps {st['co_steps']}")
+
+
+def test_query_returns_exits_and_samples_of_the_single_context_run():
+    """Exit records and trajectory samples kept by a query are those of the
+    same run as a single context: the same packs and steps, states within
+    1e-12 (FP64)."""
+    from paper_2609_31258_amd import mucite
+    f = _fields()
+    ion, src, op, steps, seed = _query(f)
+    # a detector plane 20 um downstream of the source, so that packs exit within the run
+    op = synth.Operating(**{**op.__dict__, "sample_every": 25, "sample_stride": 7, "z_det": 2e-5, "r_det": 2e-4})
+    ecap, scap = 4000, 20000
+    _say("serving exits and samples vs single context")
+    with mucite.Server(f, hbm_budget=1 << 30, precision=0, max_resident=4, steps_per_sync=5) as s:
+        qid = s.submit(ion, src, op, n_steps=steps, seed=seed, exit_capacity=ecap, sample_capacity=scap)
+        other = s.submit(*_query(f, m=3000.0, z=4, seed=5)[:3], n_steps=200, seed=5)  # shares the launches
+        r = s.wait(qid)
+        s.wait(other)
+    sim = mucite.Sim(seed=seed, pack_capacity=src.n_total, precision=0, exit_capacity=ecap, sample_capacity=scap)
+    sim.setup(f, [ion], [src], op)
+    sim.step(steps)
+    ea, sa = sim.read_exits(), sim.read_samples()
+    sim.close()
+    eb, sb = r["exits"], r["samples"]
+    _say("  exits", len(eb), "samples", len(sb))
+    assert len(eb) == len(ea) > 0 and len(sb) == len(sa) > 0
+    ea, eb = ea[np.argsort(ea["id"], kind="stable")], eb[np.argsort(eb["id"], kind="stable")]
+    sa = sa[np.lexsort((sa["id"], sa["step"]))]
+    sb = sb[np.lexsort((sb["id"], sb["step"]))]
+    for a, b in ((ea, eb), (sa, sb)):
+        for k in a.dtype.names:
+            if a.dtype[k].kind == "f":
+                assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-300), k
+            else:
+                assert np.array_equal(a[k], b[k]), k
+
+
+def test_query_keeps_records_up_to_its_capacities():
+    from paper_2609_31258_amd import mucite
+    f = _fields()
+    ion, src, op, steps, seed = _query(f, steps=300)
+    op = synth.Operating(**{**op.__dict__, "sample_every": 10, "sample_stride": 3, "z_det": 2e-5, "r_det": 2e-4})
+    with mucite.Server(f, hbm_budget=1 << 30, precision=1, max_resident=2) as s:
+        qid = s.submit(ion, src, op, n_steps=steps, seed=seed, exit_capacity=50, sample_capacity=100)
+        r = s.wait(qid)
+    assert len(r["samples"]) == 100  # the schedule takes more than the capacity keeps
+    assert r["tallies"]["class_n"][1:].sum() > 50
+    assert r["tallies"]["exit_dropped"] == max(0, r["tallies"]["class_n"][1:].sum() - 50)
+    assert len(r["exits"]) == min(50, r["tallies"]["class_n"][1:].sum())
