@@ -360,8 +360,10 @@ typedef struct mc_server_options {
  * op.gas_mass_da are ignored (the server's).  kind 0 sources emit n_total
  * packs at the query's first step.  exit_capacity: exit records kept (0 = none);
  * sample_capacity: trajectory samples kept (0 = none), taken on the schedule of
- * op.sample_every / op.sample_stride as in a single run.  op.adaptive must be 0
- * (queries are co-stepped with fixed steps). */
+ * op.sample_every / op.sample_stride as in a single run.  op.adaptive selects
+ * the Eq. 1 step as in mc_step: each co-step then reduces the query's step
+ * limits and reads them back (one synchronisation per co-step for all adaptive
+ * queries); a query whose step collapses fails with MC_ENUMERIC alone. */
 typedef struct mc_query {
     mc_ion ion;
     mc_source source;

@@ -54,6 +54,11 @@ struct Query {
     int64_t tal_len = 0;
     mc_sample_rec *samples = nullptr;
     unsigned long long *scount = nullptr;
+    // adaptive step (Eq. 1): simulated time, time of the next space-charge
+    // update, this step's length, the limit reduction's replicated lines
+    double t = 0.0, t_next_pic = 0.0, dt_now = 0.0;
+    unsigned long long *dt_rep = nullptr, *dt_out = nullptr;
+    int32_t fail_code = MC_OK;  // set when the query stops on its own error (its step collapsed)
     TallyPtrs tp{};
     Species *sp_dev = nullptr;
     int32_t *charge_dev = nullptr;
@@ -87,6 +92,7 @@ struct mc_server {
     char *pool_base = nullptr;
     Pool pool;
     char *h_ring = nullptr, *d_ring = nullptr;
+    unsigned long long *h_dt = nullptr;  // pinned: step limits of the adaptive queries, two words each
     hipEvent_t ring_ev[kRing] = {};
     bool ring_used[kRing] = {};
     size_t ring_slot = 0;
@@ -193,6 +199,10 @@ static int64_t query_layout(const mc_server *S, const Query &Q, F &&place) {
     place("exits", 0, L.take(std::max<int64_t>(Q.q.exit_capacity, 0) * (int64_t)sizeof(mc_exit_rec)));
     place("samples", 0, L.take(std::max<int64_t>(Q.q.sample_capacity, 0) * (int64_t)sizeof(mc_sample_rec)));
     place("scount", 0, L.take(8));
+    if (Q.q.op.adaptive) {
+        place("dtrep", 0, L.take(kHotLen * 8));
+        place("dtout", 0, L.take(16));
+    }
     return L.off;
 }
 
@@ -248,6 +258,10 @@ static void bind_query(mc_server *S, Query &Q) {
             Q.samples = (mc_sample_rec *)p;
         } else if (w == "scount") {
             Q.scount = (unsigned long long *)p;
+        } else if (w == "dtrep") {
+            Q.dt_rep = (unsigned long long *)p;
+        } else if (w == "dtout") {
+            Q.dt_out = (unsigned long long *)p;
         }
     });
     if (S->fp32()) {
@@ -294,6 +308,7 @@ static int32_t admit_query(mc_server *S, Query &Q) {
     bind_query(S, Q);
     k_zero_u64<<<blocks_for(Q.tal_len), kBlk, 0, S->stream>>>(Q.tal, Q.tal_len);
     k_zero_u64<<<1, kBlk, 0, S->stream>>>(Q.scount, 1);
+    if (Q.dt_rep) k_dt_reset<<<1, kHotRep, 0, S->stream>>>(Q.dt_rep);
     SCHK(hipGetLastError());
     const int64_t nn = (int64_t)S->nr * S->nz;
     if (Q.q.op.sc_on) {
@@ -371,6 +386,119 @@ static PackPtrs<typename P::T> packs_of(Query &Q) {
     else return Q.p64;
 }
 
+// The step kernel's arguments for one query, a step of length dt from t0.
+template <class P, class Tab>
+static StepArgs<P, Tab> query_step_args(mc_server *S, Query &Q, double t0, double dt) {
+    StepArgs<P, Tab> a{};
+    a.p = packs_of<P, Tab>(Q);
+    a.etab = static_cast<const Tab *>(Q.etab);
+    a.gtab = static_cast<const Tab *>(S->gtab);
+    std::memcpy(a.esc, S->esc, sizeof(a.esc));
+    std::memcpy(a.gsc, S->gsc, sizeof(a.gsc));
+    a.hit = S->hit;
+    a.sp = Q.sp_dev;
+    a.t = Q.tp;
+    a.n_slots = Q.n_slots;
+    a.step = Q.step;
+    const mc_operating &op = Q.q.op;
+    a.dt = dt;
+    a.t0 = t0;
+    double c[3];
+    rf_stages_at(op, t0, dt, c);
+    a.c0 = c[0];
+    a.ch = c[1];
+    a.c1 = c[2];
+    a.z_det = op.z_det;
+    a.r_det = op.r_det;
+    a.R = S->R;
+    a.inv_dr = S->inv_dr;
+    a.inv_dz = S->inv_dz;
+    a.mg = S->opt.gas_mass_da * kDa;
+    a.exit_bin_dt = op.exit_bin_dt;
+    a.nr = S->nr;
+    a.nz = S->nz;
+    a.n_exit_bins = op.n_exit_bins;
+    a.collisions_on = op.collisions_on;
+    a.langevin_on = op.langevin_on;
+    a.lv_z_lo = op.lv_z_lo;
+    a.lv_z_hi = op.lv_z_hi;
+    a.lv_switch = op.lv_switch;
+    a.lv_dt_ref = op.dt;
+    a.k0 = (uint32_t)Q.q.seed;
+    a.k1 = (uint32_t)(Q.q.seed >> 32);
+    return a;
+}
+
+// Trajectory samples at the start of the query's step (before the
+// space-charge update and emission), on the query's schedule.
+template <class P, class Tab>
+static int32_t sample_query(mc_server *S, Query &Q) {
+    const mc_operating &qo = Q.q.op;
+    if (qo.sample_every > 0 && qo.sample_stride > 0 && Q.step % qo.sample_every == 0 && Q.n_slots > 0 &&
+        Q.q.sample_capacity > 0) {
+        k_sample<typename P::T><<<blocks_for(Q.n_slots), kBlk, 0, S->stream>>>(
+            packs_of<P, Tab>(Q), Q.sp_dev, Q.n_slots, Q.step, qo.sample_stride, Q.samples, Q.scount,
+            Q.q.sample_capacity);
+        SCHK(hipGetLastError());
+    }
+    return MC_OK;
+}
+
+// Adaptive queries (Eq. 1): their samples and the space-charge updates due by
+// simulated time, then the per-pack limit reductions of all of them, and one
+// synchronisation for their limits; a query whose step collapses stops with
+// MC_ENUMERIC (the others go on).
+template <class P, class Tab>
+static int32_t adaptive_steps(mc_server *S, std::vector<Query *> &act) {
+    int na = 0;
+    for (Query *Qp : act) {
+        Query &Q = *Qp;
+        if (!Q.q.op.adaptive) continue;
+        const mc_operating &op = Q.q.op;
+        int32_t rc = sample_query<P, Tab>(S, Q);
+        if (rc) return rc;
+        const double tol = 1e-6 * op.dt;
+        if (op.sc_on && Q.t >= Q.t_next_pic - tol) {
+            rc = pic_query<P, Tab, typename P::T>(S, Q, packs_of<P, Tab>(Q));
+            if (rc) return rc;
+            const double period = op.sc_every * op.dt;
+            while (Q.t_next_pic <= Q.t + tol) Q.t_next_pic += period;
+        }
+        if (Q.n_slots > 0) {
+            const StepArgs<P, Tab> a = query_step_args<P, Tab>(S, Q, Q.t, op.dt);
+            k_dt_limits<P, Tab><<<blocks_for(Q.n_slots), kBlk, 0, S->stream>>>(a, Q.dt_rep);
+        }
+        k_dt_reduce<<<1, kHotRep, 0, S->stream>>>(Q.dt_rep, Q.dt_out);
+        SCHK(hipGetLastError());
+        SCHK(hipMemcpyAsync(S->h_dt + 2 * na, Q.dt_out, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            S->stream));
+        ++na;
+    }
+    if (na == 0) return MC_OK;
+    SCHK(hipStreamSynchronize(S->stream));
+    int k = 0;
+    for (Query *Qp : act) {
+        Query &Q = *Qp;
+        if (!Q.q.op.adaptive) continue;
+        const mc_operating &op = Q.q.op;
+        double lim;
+        std::memcpy(&lim, &S->h_dt[2 * k], sizeof(double));
+        const bool lang = S->h_dt[2 * k + 1] != 0ull;
+        ++k;
+        double d = std::min(op.dt, lim);
+        if (op.v_rf != 0.0 && op.f_rf > 0.0) d = std::min(d, 0.05 / op.f_rf);
+        if (lang && op.lv_dt_max > 0.0) d = std::min(d, op.lv_dt_max);
+        if (op.sc_on) d = std::min(d, Q.t_next_pic - Q.t);
+        if (!(d > 1e-9 * op.dt)) {
+            Q.fail_code = MC_ENUMERIC;
+            continue;
+        }
+        Q.dt_now = d;
+        source_dt(Q.src, Q.q.ion.charge_z, d);
+    }
+    return MC_OK;
+}
+
 template <class P, class Tab>
 static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
     using D = typename P::T;
@@ -386,18 +514,16 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
     EmitArgs<P, Tab> *ed = (EmitArgs<P, Tab> *)(h + pre);
     StepArgs<P, Tab> *sd = (StepArgs<P, Tab> *)(h + pre + maxres * sizeof(EmitArgs<P, Tab>));
     int ne = 0, ns = 0, be = 0, bs = 0;
+    int32_t rc0 = adaptive_steps<P, Tab>(S, act);
+    if (rc0) return rc0;
     for (Query *Qp : act) {
         Query &Q = *Qp;
-        // trajectory samples at the start of the step, before the space-charge update and emission
-        const mc_operating &qo = Q.q.op;
-        if (qo.sample_every > 0 && qo.sample_stride > 0 && Q.step % qo.sample_every == 0 && Q.n_slots > 0 &&
-            Q.q.sample_capacity > 0) {
-            k_sample<D><<<blocks_for(Q.n_slots), kBlk, 0, S->stream>>>(packs_of<P, Tab>(Q), Q.sp_dev, Q.n_slots,
-                                                                      Q.step, qo.sample_stride, Q.samples,
-                                                                      Q.scount, Q.q.sample_capacity);
-            SCHK(hipGetLastError());
+        if (Q.fail_code) continue;
+        if (!Q.q.op.adaptive) {
+            int32_t rc = sample_query<P, Tab>(S, Q);
+            if (rc) return rc;
         }
-        if (Q.q.op.sc_on && Q.step % Q.q.op.sc_every == 0) {
+        if (!Q.q.op.adaptive && Q.q.op.sc_on && Q.step % Q.q.op.sc_every == 0) {
             int32_t rc = pic_query<P, Tab, D>(S, Q, packs_of<P, Tab>(Q));
             if (rc) return rc;
         }
@@ -434,46 +560,14 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
             Q.emitted_w += cnt * Q.src.w_fx;
         }
         if (Q.n_slots > 0) {
-            StepArgs<P, Tab> a{};
-            a.p = packs_of<P, Tab>(Q);
-            a.etab = static_cast<const Tab *>(Q.etab);
-            a.gtab = static_cast<const Tab *>(S->gtab);
-            std::memcpy(a.esc, S->esc, sizeof(a.esc));
-            std::memcpy(a.gsc, S->gsc, sizeof(a.gsc));
-            a.hit = S->hit;
-            a.sp = Q.sp_dev;
-            a.t = Q.tp;
-            a.n_slots = Q.n_slots;
-            a.step = Q.step;
-            const mc_operating &op = Q.q.op;
-            a.dt = op.dt;
-            double c[3];
-            rf_stages(op, Q.step, &a.t0, c);
-            a.c0 = c[0];
-            a.ch = c[1];
-            a.c1 = c[2];
-            a.z_det = op.z_det;
-            a.r_det = op.r_det;
-            a.R = S->R;
-            a.inv_dr = S->inv_dr;
-            a.inv_dz = S->inv_dz;
-            a.mg = S->opt.gas_mass_da * kDa;
-            a.exit_bin_dt = op.exit_bin_dt;
-            a.nr = S->nr;
-            a.nz = S->nz;
-            a.n_exit_bins = op.n_exit_bins;
-            a.collisions_on = op.collisions_on;
-            a.langevin_on = op.langevin_on;
-            a.lv_z_lo = op.lv_z_lo;
-            a.lv_z_hi = op.lv_z_hi;
-            a.lv_switch = op.lv_switch;
-            a.lv_dt_ref = op.dt;
-            a.k0 = (uint32_t)Q.q.seed;
-            a.k1 = (uint32_t)(Q.q.seed >> 32);
+            const StepArgs<P, Tab> a = Q.q.op.adaptive ? query_step_args<P, Tab>(S, Q, Q.t, Q.dt_now)
+                                                       : query_step_args<P, Tab>(S, Q, (double)Q.step * Q.q.op.dt,
+                                                                                 Q.q.op.dt);
             ps[ns] = bs;
             sd[ns++] = a;
             bs += (int)blocks_for(Q.n_slots);
         }
+        if (Q.q.op.adaptive) Q.t += Q.dt_now;
         Q.step++;
     }
     pe[ne] = be;
@@ -623,25 +717,33 @@ static int32_t worker_round(mc_server *S) {
     for (int k = 0; k < S->opt.steps_per_sync; ++k) {
         std::vector<Query *> live;
         for (Query *Q : act)
-            if (Q->step < Q->q.n_steps) live.push_back(Q);
+            if (Q->step < Q->q.n_steps && !Q->fail_code) live.push_back(Q);
         if (live.empty()) break;
         int32_t rc = co_step<P, Tab>(S, live);
         if (rc) return rc;
     }
     SCHK(hipStreamSynchronize(S->stream));
     for (Query *Q : act) {
-        if (Q->step < Q->q.n_steps) continue;
-        int32_t rc;
-        if constexpr (P::kTwo) rc = retire_query<float>(S, *Q, Q->p32);
-        else rc = retire_query<double>(S, *Q, Q->p64);
-        if (rc) return rc;
+        if (Q->step < Q->q.n_steps && !Q->fail_code) continue;
+        if (!Q->fail_code) {
+            int32_t rc;
+            if constexpr (P::kTwo) rc = retire_query<float>(S, *Q, Q->p32);
+            else rc = retire_query<double>(S, *Q, Q->p64);
+            if (rc) return rc;
+        }
         std::lock_guard<std::mutex> lk(S->mu);
         S->pool.release(Q->pool_off);
         Q->pool_off = -1;
-        Q->state = MC_Q_DONE;
         Q->t_done = S->now();
-        S->st.completed++;
-        S->st.pack_steps += Q->r.pack_steps;
+        if (Q->fail_code) {
+            Q->state = MC_Q_FAILED;
+            Q->err = Q->fail_code;
+            S->st.failed++;
+        } else {
+            Q->state = MC_Q_DONE;
+            S->st.completed++;
+            S->st.pack_steps += Q->r.pack_steps;
+        }
         S->resident.erase(std::find(S->resident.begin(), S->resident.end(), Q));
         if (S->resident.empty() && S->busy_since >= 0) {
             S->st.busy_s += S->now() - S->busy_since;
@@ -815,6 +917,9 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
                                                     o->max_resident * (emit_sz + step_sz)));
     if (hipHostMalloc((void **)&S->h_ring, kRing * S->ring_slot, hipHostMallocDefault) != hipSuccess)
         return bail(sfail(S, MC_ENOMEM, "pinned descriptor ring"));
+    if (hipHostMalloc((void **)&S->h_dt, 2 * (size_t)o->max_resident * sizeof(unsigned long long),
+                      hipHostMallocDefault) != hipSuccess)
+        return bail(sfail(S, MC_ENOMEM, "pinned step-limit buffer"));
     if (salloc(S, (void **)&S->d_ring, kRing * S->ring_slot)) return bail(MC_ENOMEM);
     for (int k = 0; k < kRing; ++k) SC2(hipEventCreateWithFlags(&S->ring_ev[k], hipEventDisableTiming));
     // the query pool
@@ -845,6 +950,7 @@ void mc_server_destroy(mc_server *S) {
     for (int k = 0; k < kRing; ++k)
         if (S->ring_ev[k]) (void)hipEventDestroy(S->ring_ev[k]);
     if (S->h_ring) (void)hipHostFree(S->h_ring);
+    if (S->h_dt) (void)hipHostFree(S->h_dt);
     if (S->own_stream && S->stream) (void)hipStreamDestroy(S->stream);
     for (auto &kv : S->all) delete kv.second;
     delete S;
@@ -855,7 +961,7 @@ static bool valid_query(const mc_server *S, const mc_query *q) {
     const mc_operating &op = q->op;
     if (!(op.dt > 0) || op.sc_every < 1 || op.n_exit_bins < 1 || !(op.exit_bin_dt > 0) || !(op.r_det > 0)) return false;
     if (op.langevin_on && !(op.lv_switch >= 0)) return false;
-    if (op.adaptive) return false;  // fixed steps only: queries are co-stepped
+    if (!(op.lv_dt_max >= 0)) return false;
     if (op.sample_every < 0 || op.sample_stride < 0 || q->sample_capacity < 0) return false;
     const mc_source &s = q->source;
     if (s.kind < 0 || s.kind > 2 || !(s.sigma_r > 0) || !(s.r_trunc > 0) || s.n_total < 0) return false;

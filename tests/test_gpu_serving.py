@@ -183,3 +183,55 @@ def test_query_keeps_records_up_to_its_capacities():
     assert r["tallies"]["class_n"][1:].sum() > 50
     assert r["tallies"]["exit_dropped"] == max(0, r["tallies"]["class_n"][1:].sum() - 50)
     assert len(r["exits"]) == min(50, r["tallies"]["class_n"][1:].sum())
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_adaptive_query_equals_the_single_context_run(precision):
+    """Eq. 1 steps in the server: a query's limit reduction, space-charge times
+    and emission per step follow the single-context run, next to a
+    fixed-step query sharing its launches."""
+    from paper_2609_31258_amd import mucite
+    f = _fields()
+    ion, src, op, steps, seed = _query(f, steps=200)
+    op = synth.Operating(**{**op.__dict__, "adaptive": 1})
+    _say("adaptive query vs single context, precision", precision)
+    with mucite.Server(f, hbm_budget=1 << 30, precision=precision, max_resident=4, steps_per_sync=5) as s:
+        qa = s.submit(ion, src, op, n_steps=steps, seed=seed, exit_capacity=4000)
+        qb = s.submit(*_query(f, m=3000.0, z=4, seed=5)[:3], n_steps=150, seed=5)
+        r, rb = s.wait(qa), s.wait(qb)
+    assert r["state"] == rb["state"] == mucite.Q_DONE
+    sim = mucite.Sim(seed=seed, pack_capacity=src.n_total, precision=precision, exit_capacity=4000)
+    sim.setup(f, [ion], [src], op)
+    sim.step(steps)
+    t, ea, info = sim.read_tallies(), sim.read_exits(), sim.info()
+    sim.close()
+    _say("  simulated time", info["time"], "exits", len(ea))
+    # the collision limit (about 4 ps at 1e5 Pa) sets the steps, far below the largest step
+    assert info["time"] < 0.1 * steps * op.dt
+    _same(r["tallies"], t, exact_fp=False)
+    assert r["tallies"]["pack_steps"] > 0
+    eb = r["exits"]
+    ea, eb = ea[np.argsort(ea["id"], kind="stable")], eb[np.argsort(eb["id"], kind="stable")]
+    assert len(eb) == len(ea)
+    for k in ea.dtype.names:
+        if ea.dtype[k].kind == "f":
+            assert np.allclose(ea[k], eb[k], rtol=1e-12, atol=1e-300), k
+        else:
+            assert np.array_equal(ea[k], eb[k]), k
+
+
+def test_collapsing_adaptive_query_fails_alone():
+    """A query whose Eq. 1 step collapses (largest step 1 s, collision limit
+    about 1e-12 s) stops with MC_ENUMERIC; the query beside it completes."""
+    from paper_2609_31258_amd import mucite
+    f = _fields()
+    ion, src, op, steps, seed = _query(f, steps=50)
+    bad = synth.Operating(**{**op.__dict__, "adaptive": 1, "dt": 1.0})
+    with mucite.Server(f, hbm_budget=1 << 30, precision=0, max_resident=4, steps_per_sync=5) as s:
+        qb = s.submit(ion, src, bad, n_steps=steps, seed=seed)
+        qg = s.submit(ion, src, op, n_steps=steps, seed=seed)
+        rb, rg = s.wait(qb), s.wait(qg)
+        st = s.stats()
+    assert rb["state"] == mucite.Q_FAILED and rb["error"] == mucite.MC_ENUMERIC
+    assert rg["state"] == mucite.Q_DONE and rg["tallies"]["pack_steps"] > 0
+    assert st["failed"] == 1 and st["completed"] == 1
