@@ -6,7 +6,7 @@ per-pack terms), the states then agree pathwise within 1e-6 for 99 % of the
 packs; space-charge updates land on their times; the FP32 form's first step
 is within 1e-5 of the oracle's and every step within 5 % (its trajectories,
 and so the extreme pack that sets the step, drift apart statistically); the
-server refuses adaptive queries."""
+server runs adaptive queries (their parity with single runs is in test_gpu_serving.py)."""
 import sys
 
 import numpy as np
@@ -89,13 +89,15 @@ def test_space_charge_times_and_langevin_cap_on_gpu():
     g.close()
 
 
-def test_server_refuses_adaptive_queries():
+def test_server_runs_adaptive_queries_and_refuses_a_negative_langevin_cap():
     from paper_2609_31258_amd import mucite
     f = synth.ring_fields(64, 256)
     ion = synth.Ion(500.0, 1, 2e-18, 150)
     src = synth.Source(kind=1, current_a=1e-9, packs_per_step=10, n_total=100, sigma_r=1e-4, r_trunc=3e-4)
     op = synth.Operating(dt=1e-9, z_det=f.grid.L, r_det=f.grid.R, adaptive=1)
     with mucite.Server(f, hbm_budget=1 << 28, precision=0, max_resident=2) as s:
+        r = s.wait(s.submit(ion, src, op, n_steps=10, seed=1))
+        assert r["state"] == mucite.Q_DONE and r["tallies"]["pack_steps"] > 0
         with pytest.raises(mucite.MucateError) as e:
-            s.submit(ion, src, op, n_steps=10, seed=1)
+            s.submit(ion, src, synth.Operating(**{**op.__dict__, "lv_dt_max": -1.0}), n_steps=10, seed=1)
         assert e.value.code == mucite.MC_EINVAL
