@@ -657,11 +657,15 @@ struct DepositArgs {
 // removes almost all contention on the global grid; integer sums make the
 // result independent of the order.
 constexpr int kDepHash = 2048;
-// Grid of the deposit: one block per CU.  Every block flushes one device
-// atomic per distinct node it saw, and the packs of a step crowd into a few
-// hundred nodes, so the flush is bound by same-address atomics; more blocks
-// than CUs only add flushes.
+// Grid of the deposit: one block of 16 wavefronts per CU.  Every block
+// flushes one device atomic per distinct node it saw, and the packs of a step
+// crowd into a few hundred nodes, so the flush is bound by same-address
+// atomics: more blocks only add flushes, while more wavefronts per block hide
+// the latency of the pack loads and LDS atomics (measured on the 256x1024
+// workload at 1e6 packs: 0.052 ms with 256-thread blocks, 0.039 ms with
+// 1024, 0.065 ms with twice the blocks).
 constexpr int64_t kDepositBlocks = 256;
+constexpr int kDepositThreads = 1024;
 
 __device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
                                            int32_t node, int64_t v) {
@@ -679,7 +683,7 @@ __device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *va
 }
 
 template <class P>
-__global__ __launch_bounds__(256) void k_deposit(DepositArgs<typename P::T> a) {
+__global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typename P::T> a) {
     __shared__ int32_t keys[kDepHash];
     __shared__ unsigned long long vals[kDepHash];
     for (int k = threadIdx.x; k < kDepHash; k += blockDim.x) {

@@ -456,8 +456,9 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
             a.inv_dz = ctx->inv_dz;
             a.nr = ctx->nr;
             a.nz = ctx->nz;
-            const unsigned nb = (unsigned)std::min<int64_t>(grid_for(ctx->n_slots), kDepositBlocks);
-            k_deposit<P><<<nb, kBlock, 0, ctx->stream>>>(a);
+            const unsigned nb = (unsigned)std::min<int64_t>((ctx->n_slots + kDepositThreads - 1) / kDepositThreads,
+                                                            kDepositBlocks);
+            k_deposit<P><<<nb, kDepositThreads, 0, ctx->stream>>>(a);
             LAUNCHCHK();
         }
     }

@@ -338,7 +338,9 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         a.inv_dz = S->inv_dz;
         a.nr = S->nr;
         a.nz = S->nz;
-        k_deposit<P><<<(unsigned)std::min<int64_t>(blocks_for(Q.n_slots), kDepositBlocks), kBlk, 0, S->stream>>>(a);
+        k_deposit<P><<<(unsigned)std::min<int64_t>((Q.n_slots + kDepositThreads - 1) / kDepositThreads,
+                                                   kDepositBlocks),
+                       kDepositThreads, 0, S->stream>>>(a);
     }
     D *bh = static_cast<D *>(Q.bh);
     SCHK(poisson_solve<D>(S->pg, Q.qgrid, nullptr, bh, Q.phi, false, S->stream));
