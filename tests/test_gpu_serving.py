@@ -235,3 +235,23 @@ def test_collapsing_adaptive_query_fails_alone():
     assert rb["state"] == mucite.Q_FAILED and rb["error"] == mucite.MC_ENUMERIC
     assert rg["state"] == mucite.Q_DONE and rg["tallies"]["pack_steps"] > 0
     assert st["failed"] == 1 and st["completed"] == 1
+
+
+def test_empty_queries_complete_with_zero_tallies():
+    """A query of zero steps, and one whose source holds no packs, finish with
+    empty tallies next to a normal query."""
+    from paper_2609_31258_amd import mucite
+    f = _fields()
+    ion, src, op, steps, seed = _query(f, steps=20)
+    empty_src = synth.Source(**{**src.__dict__, "n_total": 0})
+    with mucite.Server(f, hbm_budget=1 << 30, precision=1, max_resident=4, steps_per_sync=3) as s:
+        q0 = s.submit(ion, src, op, n_steps=0, seed=seed, exit_capacity=10, sample_capacity=10)
+        q1 = s.submit(ion, empty_src, op, n_steps=steps, seed=seed)
+        q2 = s.submit(ion, src, op, n_steps=steps, seed=seed)
+        r0, r1, r2 = s.wait(q0), s.wait(q1), s.wait(q2)
+    for r in (r0, r1):
+        assert r["state"] == mucite.Q_DONE
+        assert r["tallies"]["pack_steps"] == 0 and r["tallies"]["emitted_n"] == 0
+        assert r["tallies"]["class_n"].sum() == 0
+    assert len(r0["exits"]) == 0 and len(r0["samples"]) == 0
+    assert r2["state"] == mucite.Q_DONE and r2["tallies"]["pack_steps"] > 0
