@@ -214,8 +214,10 @@ __device__ void fft_lds(Cx<D> *a, int32_t L, const Cx<D> *tw) {
     if (!kInverse) {
         for (int32_t len = L; len >= 2; len >>= 1) {
             const int32_t half = len >> 1, stride = L / len;
+#pragma unroll 4
             for (int32_t b = threadIdx.x; b < half_total; b += blockDim.x) {
-                const int32_t k = b % half, i0 = (b / half) * len + k, i1 = i0 + half;
+                // butterfly b of this stage: k = b mod half, i0 = (b div half) len + k = 2b - k
+                const int32_t k = b & (half - 1), i0 = 2 * b - k, i1 = i0 + half;
                 const Cx<D> u = a[i0], v = a[i1];
                 a[i0] = Cx<D>{u.re + v.re, u.im + v.im};
                 a[i1] = cmul(Cx<D>{u.re - v.re, u.im - v.im}, tw[k * stride]);
@@ -225,8 +227,9 @@ __device__ void fft_lds(Cx<D> *a, int32_t L, const Cx<D> *tw) {
     } else {
         for (int32_t len = 2; len <= L; len <<= 1) {
             const int32_t half = len >> 1, stride = L / len;
+#pragma unroll 4
             for (int32_t b = threadIdx.x; b < half_total; b += blockDim.x) {
-                const int32_t k = b % half, i0 = (b / half) * len + k, i1 = i0 + half;
+                const int32_t k = b & (half - 1), i0 = 2 * b - k, i1 = i0 + half;
                 const Cx<D> w = tw[k * stride];
                 const Cx<D> t = cmul(a[i1], Cx<D>{w.re, -w.im});
                 const Cx<D> u = a[i0];
