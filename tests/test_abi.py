@@ -57,3 +57,11 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.mc_server_submit(None, None, None) == mucite.MC_EINVAL
     assert L.mc_server_poll(None, 1, None) == mucite.MC_EINVAL
     L.mc_server_destroy(None)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; nothing falls back."""
+    monkeypatch.setattr(mucite, "_LIB", None)
+    monkeypatch.setattr(mucite, "LIB_PATH", str(tmp_path / "libmucite.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        mucite.load_library()
