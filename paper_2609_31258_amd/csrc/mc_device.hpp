@@ -45,11 +45,13 @@ __device__ __forceinline__ W4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
     for (int r = 0; r < 10; ++r) {
         const uint64_t pa = (uint64_t)0xD2511F53u * c0;
         const uint64_t pb = (uint64_t)0xCD9E8D57u * c2;
-        // first round: plain XORs, so that the words that are the same across
-        // the wavefront (step, purpose and block, key) stay in scalar
-        // instructions; later rounds mix per-lane words only
-        const uint32_t n0 = r == 0 ? ((uint32_t)(pb >> 32) ^ c1 ^ k0) : xor3((uint32_t)(pb >> 32), c1, k0);
-        const uint32_t n2 = r == 0 ? ((uint32_t)(pa >> 32) ^ c3 ^ k1) : xor3((uint32_t)(pa >> 32), c3, k1);
+        // the first rounds still mix words that are the same across the
+        // wavefront (step, purpose and block, the key and what the first
+        // products make of them): plain XORs there let the compiler keep those
+        // in scalar instructions; the three-input XOR takes the rounds where
+        // both mixed words differ per lane
+        const uint32_t n0 = r <= 1 ? ((uint32_t)(pb >> 32) ^ c1 ^ k0) : xor3((uint32_t)(pb >> 32), c1, k0);
+        const uint32_t n2 = r <= 2 ? ((uint32_t)(pa >> 32) ^ c3 ^ k1) : xor3((uint32_t)(pa >> 32), c3, k1);
         c1 = (uint32_t)pb;
         c3 = (uint32_t)pa;
         c0 = n0;
