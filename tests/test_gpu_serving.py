@@ -255,3 +255,20 @@ def test_empty_queries_complete_with_zero_tallies():
         assert r["tallies"]["class_n"].sum() == 0
     assert len(r0["exits"]) == 0 and len(r0["samples"]) == 0
     assert r2["state"] == mucite.Q_DONE and r2["tallies"]["pack_steps"] > 0
+
+
+def test_fp32_table_server_equals_the_single_context_run():
+    """The FP32 form with FP32 (instead of BF16) field tables, served."""
+    from paper_2609_31258_amd import mucite
+    f = _fields()
+    ion, src, op, steps, seed = _query(f, steps=150)
+    with mucite.Server(f, hbm_budget=1 << 30, precision=1, max_resident=4, steps_per_sync=5,
+                       fp32_tables=True) as s:
+        r = s.wait(s.submit(ion, src, op, n_steps=steps, seed=seed))
+    sim = mucite.Sim(seed=seed, pack_capacity=src.n_total, precision=1, fp32_tables=True)
+    sim.setup(f, [ion], [src], op)
+    sim.step(steps)
+    t = sim.read_tallies()
+    sim.close()
+    assert r["state"] == mucite.Q_DONE and t["pack_steps"] > 0
+    _same(r["tallies"], t, exact_fp=False)
