@@ -64,6 +64,7 @@ BYTES_DEPOSIT = {"fp64": 36, "fp32": 36}
 HBM_PEAK = 8.0e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_step_c2_valu.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_31258_amd", "csrc", f) for f in ("mc_kernels.hpp", "mc_device.hpp")]
 
 
@@ -75,20 +76,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(precision: str):
-    """HBM bytes per step launch from the committed rocprofv3 counter summary,
-    or None when the kernels changed after the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
+def _profile_values(path: str):
+    """key: value lines of a committed rocprofv3 summary, or {} when the
+    kernels changed after it was taken."""
+    if not os.path.exists(path):
+        return {}
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    v = kv.get(f"{precision}_hbm_bytes_per_launch")
+    return kv if kv.get("kernel_source_sha256") == kernel_source_hash() else {}
+
+
+def measured_traffic(precision: str):
+    """HBM bytes per step launch from the committed rocprofv3 counter summary,
+    or None when the kernels changed after the counters were taken."""
+    v = _profile_values(TRAFFIC_FILE).get(f"{precision}_hbm_bytes_per_launch")
     return float(v) if v else None
+
+
+def measured_issue(form: str):
+    """Vector-ALU busy share and lane utilisation of the step kernel from the
+    committed rocprofv3 summary (None when stale)."""
+    kv = _profile_values(VALU_FILE)
+    b, u = kv.get(f"{form}_valu_busy"), kv.get(f"{form}_lane_utilization")
+    return {"valu_busy": float(b), "lane_utilization": float(u)} if b and u else None
 
 
 def parse():
@@ -170,7 +183,8 @@ def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": measured_traffic(traffic_key) if traffic_key else None,
             "kernel": kernel, "avg_launch_ms": avg_s * 1e3,
-            "launches": launches, "bytes_per_launch": nbytes}
+            "launches": launches, "bytes_per_launch": nbytes,
+            "issue": measured_issue(traffic_key) if kernel == "step" and traffic_key else None}
 
 
 def run_large(fill_steps: int, steps: int, n_packs: int = 16_000_000):
@@ -227,7 +241,7 @@ def roofline(r, precision: str, alpha: float):
     return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12, "unit": "Top/s",
             "frac": achieved / PEAK_OPS, "traffic": measured_traffic(precision),
             "kernel": "k_step (fused push/classify/collide)", "avg_launch_ms": avg_s * 1e3, "launches": launches,
-            "ops_per_launch": ops_per_launch}
+            "ops_per_launch": ops_per_launch, "issue": measured_issue(precision)}
 
 
 def precision_report(t64, t32):
