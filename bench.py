@@ -114,7 +114,7 @@ def parse():
                          "two-float positions), hybrid (FP32 form with the Langevin branch in 0-1 mm)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-packs", type=int, default=400_000)
-    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--cpu-steps", type=int, default=40)
     ap.add_argument("--serving-queries", type=int, default=256)
     ap.add_argument("--serving-rate", type=float, default=20.0)
     ap.add_argument("--serving-steps", type=int, default=2000)
