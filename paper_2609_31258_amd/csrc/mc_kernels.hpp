@@ -290,6 +290,12 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         }
         const T xl0 = xl, yl0 = yl, zl0 = zl;
         const T vx0 = a.p.vx[s], vy0 = a.p.vy[s], vz0 = a.p.vz[s];
+        // the random-stream key: in the FP32 form read with the state (a read
+        // issued where the draws start would stall a Langevin step on memory a
+        // second time); the FP64 form reads it where the draws start, which
+        // keeps its registers free through the push
+        int64_t id = 0;
+        if constexpr (P::kTwo) id = a.p.id[s];
 
         // ---- classical RK4 on (x, v); stages at t, t + dt/2, t + dt/2, t + dt ----
         T ex, ey, ez;
@@ -368,13 +374,27 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         if (cls == ST_ACTIVE && a.collisions_on) {
             // ---- collisions with the gas at the new position ----
             const T rr = (T)r1;
+            const T m = (T)sp.m, mg = (T)a.mg, ccs = (T)sp.ccs;
             const Cell<T> cl = locate<T>(rr, z1, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
             const Q4<T> g = gather4<T>(a.gtab, a.gsc, cl, a.nr);
             const T sr = rr > (T)0 ? P::div(g.a, rr) : (T)0;
             const T ux = sr * x1, uy = sr * y1, uz = g.b, tg = g.d;
-            const T m = (T)sp.m, mg = (T)a.mg;
-            const T ngs = tg > (T)0 ? P::div(g.c, (T)kB * tg) * (T)sp.ccs : (T)0;  // n_gas * sigma
-            if (ngs > (T)0 && isfinite(ngs)) {
+            // n_gas * sigma.  FP32 form: evaluated on every lane and then
+            // selected, so that all four gas components and the cross-section
+            // are read at once rather than behind a branch on the temperature
+            // (its quotient is one reciprocal); FP64: the division stays behind
+            // the branch, where the compiler keeps it without stack use
+            T ngs;
+            if constexpr (P::kTwo) {
+                const T ngs_any = P::div(g.c, (T)kB * (tg > (T)0 ? tg : (T)1)) * ccs;
+                ngs = tg > (T)0 ? ngs_any : (T)0;
+            } else {
+                ngs = tg > (T)0 ? P::div(g.c, (T)kB * tg) * ccs : (T)0;
+            }
+            // (FP32 form: the mass, positive by definition, enters the test so
+            // that its read is issued with the gas gather instead of after it)
+            const bool gas = P::kTwo ? (ngs > (T)0) & (bool)isfinite(ngs) & (m > (T)0) : ngs > (T)0 && isfinite(ngs);
+            if (gas) {
                 const T ag = P::sqrt_(P::div((T)kB * tg, mg));
                 const T abar = ag * (T)1.5957691216057308;  // sqrt(8/pi)
                 const T M = m + mg, fm = P::div(mg, M), fi = P::div(m, M), mu = mg * fi;  // no m*mg product (FP32 range)
@@ -388,7 +408,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 if (lang) {
                     // hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward the gas
                     // velocity over dt, hard-sphere friction rate, Box-Muller normals from one block
-                    const W4 w = draw(a.p.id[s], a.step, kPurposeLangevin, 0u, k0, k1);
+                    const W4 w = draw(P::kTwo ? id : a.p.id[s], a.step, kPurposeLangevin, 0u, k0, k1);
                     const T r0 = P::sqrt_((T)-2 * P::ln(P::u01(w.w0)));
                     const T r1 = P::sqrt_((T)-2 * P::ln(P::u01(w.w2)));
                     T s0, c0;
@@ -407,7 +427,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                 const T nexp = lang ? (T)0 : lam * dt;
                 const int32_t cap = (nexp < (T)1e6) ? 64 + 8 * (int32_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
                 T tleft = lang ? (T)0 : dt;
-                const int64_t id = a.p.id[s];
+                if constexpr (!P::kTwo) id = a.p.id[s];
                 for (int32_t c = 0; !lang; ++c) {
                     if (c == cap) {
                         ++ncap;
