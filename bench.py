@@ -39,8 +39,8 @@ WORKLOAD = ("256x1024 ring-electrode grid (0.05 mm), 1e6 packs injected at 500/s
 # 64 lanes x 2.4 GHz, an FMA counted as two operations (the FP64 vector peak,
 # 78.6 TFLOP/s; unpacked FP32 issues at the same rate -- packed FP32 is not
 # used).  The issue_probe program beside the library measures it: one wave64
-# instruction per SIMD every 4.07 clocks for v_fma_f32, 4.32 for v_fma_f64,
-# 4.10 for v_mad_u64_u32 and 4.05 for v_bitop3_b32.
+# instruction per SIMD about every 4.1 clocks for v_fma_f32, v_mad_u64_u32 and
+# v_bitop3_b32 and 4.3 for v_fma_f64.
 PEAK_OPS = 256 * 64 * 2 * 2.4e9
 
 # Algorithmic operation counts of the fused step kernel: each add, multiply,
@@ -67,7 +67,8 @@ HBM_PEAK = 8.0e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_traffic.txt")
 VALU_FILE = os.path.join(ROOT, "profiles", "k_step_c2_valu.txt")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_31258_amd", "csrc", f) for f in ("mc_kernels.hpp", "mc_device.hpp")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_31258_amd", "csrc", f)
+                  for f in ("mc_kernels.hpp", "mc_device.hpp", "mc_math64.hpp")]
 
 
 def kernel_source_hash() -> str:

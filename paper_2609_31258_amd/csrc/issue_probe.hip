@@ -15,6 +15,9 @@
 //   fp64 fma      v_fma_f64
 //   mad_u64_u32   the 32x32->64 product-add of the Philox rounds
 //   bitop3        the three-input XOR of the Philox rounds
+//   log/sqrt/sin/rcp_f32, rcp/rsq_f64   the hardware transcendental and
+//                 reciprocal instructions of the FP32 form's elementary
+//                 functions and the FP64 form's quotients and square roots
 //
 // Build: hipcc --offload-arch=gfx950 -O3 (with packed FP32 disabled, as for
 // the library); run: ./issue_probe.  Exit status 0 on success.
@@ -91,6 +94,51 @@ __global__ __launch_bounds__(256) void k_bitop3(uint32_t *out, int iters, uint32
     out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// transcendental and reciprocal classes: one hardware instruction per step
+// (|x| is a free source modifier; the values may reach infinities or NaN,
+// which does not change the issue rate)
+template <int kOp>
+__global__ __launch_bounds__(256) void k_trans32(float *out, int iters) {
+    float x[kChains];
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) x[k] = threadIdx.x * 1e-7f + k + 0.5f;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) {
+                if constexpr (kOp == 0) x[k] = __builtin_amdgcn_logf(fabsf(x[k]));
+                if constexpr (kOp == 1) x[k] = __builtin_amdgcn_sqrtf(fabsf(x[k]));
+                if constexpr (kOp == 2) x[k] = __builtin_amdgcn_sinf(x[k]);
+                if constexpr (kOp == 3) x[k] = __builtin_amdgcn_rcpf(x[k]);
+            }
+    }
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) s += x[k];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+template <int kOp>
+__global__ __launch_bounds__(256) void k_trans64(double *out, int iters) {
+    double x[kChains];
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) x[k] = threadIdx.x * 1e-7 + k + 0.5;
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int k = 0; k < kChains; ++k) {
+                if constexpr (kOp == 0) x[k] = __builtin_amdgcn_rcp(x[k]);
+                if constexpr (kOp == 1) x[k] = __builtin_amdgcn_rsq(fabs(x[k]));
+            }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kChains; ++k) s += x[k];
+    out[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 bool ok(hipError_t e, const char *what) {
     if (e == hipSuccess) return true;
     std::fprintf(stderr, "issue_probe: %s: %s\n", what, hipGetErrorString(e));
@@ -107,15 +155,22 @@ int main() {
     hipEvent_t e0, e1;
     if (!ok(hipEventCreate(&e0), "hipEventCreate") || !ok(hipEventCreate(&e1), "hipEventCreate")) return 1;
     const double lane_instr = (double)n * iters * kUnroll * kChains;
-    const char *names[4] = {"fp32 fma", "fp64 fma", "mad_u64_u32", "bitop3"};
+    const char *names[10] = {"fp32 fma", "fp64 fma", "mad_u64_u32", "bitop3", "log_f32", "sqrt_f32",
+                             "sin_f32", "rcp_f32", "rcp_f64", "rsq_f64"};
     std::printf("%-12s %10s %22s %30s\n", "class", "ms", "lane-instr/s (1e12)", "clocks per wave64 instr/SIMD");
     for (int rep = 0; rep < 2; ++rep) {
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < 10; ++w) {
             if (!ok(hipEventRecord(e0, 0), "hipEventRecord")) return 1;
             if (w == 0) hipLaunchKernelGGL(k_fp32, dim3(blocks), dim3(threads), 0, 0, (float *)buf, iters, 0.999f, 1e-3f);
             if (w == 1) hipLaunchKernelGGL(k_fp64, dim3(blocks), dim3(threads), 0, 0, (double *)buf, iters, 0.999, 1e-3);
             if (w == 2) hipLaunchKernelGGL(k_mad_u64, dim3(blocks), dim3(threads), 0, 0, (uint64_t *)buf, iters, 0xD2511F53u);
             if (w == 3) hipLaunchKernelGGL(k_bitop3, dim3(blocks), dim3(threads), 0, 0, (uint32_t *)buf, iters, 0x9E3779B9u);
+            if (w == 4) hipLaunchKernelGGL(k_trans32<0>, dim3(blocks), dim3(threads), 0, 0, (float *)buf, iters);
+            if (w == 5) hipLaunchKernelGGL(k_trans32<1>, dim3(blocks), dim3(threads), 0, 0, (float *)buf, iters);
+            if (w == 6) hipLaunchKernelGGL(k_trans32<2>, dim3(blocks), dim3(threads), 0, 0, (float *)buf, iters);
+            if (w == 7) hipLaunchKernelGGL(k_trans32<3>, dim3(blocks), dim3(threads), 0, 0, (float *)buf, iters);
+            if (w == 8) hipLaunchKernelGGL(k_trans64<0>, dim3(blocks), dim3(threads), 0, 0, (double *)buf, iters);
+            if (w == 9) hipLaunchKernelGGL(k_trans64<1>, dim3(blocks), dim3(threads), 0, 0, (double *)buf, iters);
             if (!ok(hipGetLastError(), "launch") || !ok(hipEventRecord(e1, 0), "hipEventRecord") ||
                 !ok(hipEventSynchronize(e1), "kernel"))
                 return 1;

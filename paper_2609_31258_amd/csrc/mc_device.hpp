@@ -80,7 +80,7 @@ struct P64 {
     // inline constant and an exponent shift: no 64-bit constant in a register)
     static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
     // every call site passes x in (0, 1] (uniform variates and their products)
-    static __device__ __forceinline__ double ln(double x) { return ln_unit(x); }
+    static __device__ __forceinline__ double ln(double x) { return ln_pos(x); }
     // x >= 0 and zero or normal at every call site: the reciprocal square
     // root seed refined by two coupled Newton (Goldschmidt) iterations for
     // y = sqrt(x), h = 1/(2 sqrt(x)), then one residual correction
@@ -98,10 +98,12 @@ struct P64 {
     }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
-    static __device__ __forceinline__ double log1p_(double x) { return log1p(x); }
-    // sin(2 pi u), cos(2 pi u) without a large-argument reduction
-    static __device__ __forceinline__ void sc2pi(double u, double *s, double *c) { sincospi(2.0 * u, s, c); }
-    static __device__ __forceinline__ double cos2pi(double u) { return cospi(2.0 * u); }
+    // every call site passes a positive ratio (the Einstein-model inverse)
+    static __device__ __forceinline__ double log1p_(double x) { return ln1p_pos(x); }
+    // sin(2 pi u), cos(2 pi u) of uniform variates u in (0, 1): a quarter-turn
+    // reduction and two short series instead of the library's general reduction
+    static __device__ __forceinline__ void sc2pi(double u, double *s, double *c) { sincos_turn(u, s, c); }
+    static __device__ __forceinline__ double cos2pi(double u) { return cos_turn(u); }
 };
 
 // FP32 form: the hardware transcendental instructions (v_log_f32 = log2,

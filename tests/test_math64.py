@@ -1,6 +1,10 @@
-"""The restricted FP64 logarithm of the step kernel (mc_math64.hpp), compiled
-on the host with g++: within 2 ulp of the C library's log over uniform
-variates (w + 1/2) 2^-32, their products, and the ends of its domain."""
+"""The restricted FP64 elementary functions of the step kernel
+(mc_math64.hpp), compiled on the host with g++ and checked against
+extended-precision (x87 long double) references: each within 2 ulp (log1p
+2.5) over the arguments the step takes -- uniform variates (w + 1/2) 2^-32 and their
+products for the logarithm, positive ratios over the whole double range for
+log1p, uniform turns for the sine and cosine -- and at the ends of each
+domain."""
 import os
 import subprocess
 
@@ -10,37 +14,81 @@ HARNESS = r'''
 #include <cstdint>
 #include <cstdio>
 #include <random>
-static double ulps(double a, double b) {
-    if (a == b) return 0;
+// distance in units of the last place of the correctly rounded reference
+static double ulps(double a, long double ref) {
+    const double b = (double)ref;
     const double u = std::nextafter(std::fabs(b), INFINITY) - std::fabs(b);
-    return std::fabs(a - b) / u;
+    return (double)(std::fabs((long double)a - ref) / u);
 }
+static long double two_pi_l() { return 2.0L * 3.14159265358979323846264338327950288L; }
 int main() {
     std::mt19937_64 rng(3);
-    double worst = 0;
-    for (long k = 0; k < 4000000; ++k) {
+    double w_ln = 0, w_ln1p = 0, w_sin = 0, w_cos = 0, w_sin2 = 0, w_cos2 = 0;
+    for (long k = 0; k < 2000000; ++k) {
         const double u = ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
         const double v = ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
-        worst = std::fmax(worst, ulps(mc::ln_unit(u), std::log(u)));
-        worst = std::fmax(worst, ulps(mc::ln_unit(u * v), std::log(u * v)));
-        const double w = std::ldexp(0.5 + 0.5 * u, -(int)(rng() % 1000));  // exponents down to 2^-1000
-        worst = std::fmax(worst, ulps(mc::ln_unit(w), std::log(w)));
+        // logarithm: uniforms, their products, and the whole normal range
+        w_ln = std::fmax(w_ln, ulps(mc::ln_pos(u), logl(u)));
+        w_ln = std::fmax(w_ln, ulps(mc::ln_pos(u * v), logl((long double)(u * v))));
+        const double x = std::ldexp(0.5 + 0.5 * u, (int)(rng() % 2040) - 1020);
+        w_ln = std::fmax(w_ln, ulps(mc::ln_pos(x), logl(x)));
+        // log1p: positive ratios from 2^-1020 to 2^1020, and near the
+        // switch at sqrt 2 - 1
+        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_pos(x), log1pl(x)));
+        const double y = 0.41421356237309503 * (1.0 + (v - 0.5) * 1e-3);
+        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_pos(y), log1pl(y)));
+        // sine and cosine of a turn: against the reference on the same exact
+        // reduction (all arguments), and against the unreduced extended
+        // argument where the result is not near a zero (checks the quadrants)
+        double s, c;
+        mc::sincos_turn(u, &s, &c);
+        const double q = std::rint(4.0 * u);
+        const long double t = (long double)u - 0.25L * (long double)q;
+        if (t != (long double)(u - 0.25 * q)) { std::puts("FAIL reduction not exact"); return 1; }
+        const long double th = two_pi_l() * t;
+        const int kq = (int)q & 3;
+        const long double st = sinl(th), ct = cosl(th);
+        const long double rs = kq == 0 ? st : kq == 1 ? ct : kq == 2 ? -st : -ct;
+        const long double rc = kq == 0 ? ct : kq == 1 ? -st : kq == 2 ? -ct : st;
+        w_sin = std::fmax(w_sin, ulps(s, rs));
+        w_cos = std::fmax(w_cos, ulps(c, rc));
+        if (mc::cos_turn(u) != c) { std::puts("FAIL cos_turn differs from sincos_turn"); return 1; }
+        const long double ds = sinl(two_pi_l() * u), dc = cosl(two_pi_l() * u);
+        if (fabsl(ds) > 0.01L) w_sin2 = std::fmax(w_sin2, ulps(s, ds));
+        if (fabsl(dc) > 0.01L) w_cos2 = std::fmax(w_cos2, ulps(c, dc));
     }
     const double ends[] = {1.0, 0.5, 0x1p-66, 0x1p-1022, 0.70710678118654746, 0.70710678118654757,
-                           1.0 - 0x1p-53, 0.9999999};
-    for (double x : ends) worst = std::fmax(worst, ulps(mc::ln_unit(x), std::log(x)));
-    if (mc::ln_unit(1.0) != 0.0) { std::puts("FAIL ln 1"); return 1; }
-    std::printf(worst <= 2.0 ? "OK %.3f\n" : "FAIL %.3f\n", worst);
+                           1.0 - 0x1p-53, 0.9999999, 0x1p1000, 1.7976931348623157e308};
+    for (double x : ends) w_ln = std::fmax(w_ln, ulps(mc::ln_pos(x), logl(x)));
+    if (mc::ln_pos(1.0) != 0.0) { std::puts("FAIL ln 1"); return 1; }
+    const double ends1p[] = {0x1p-1074, 0x1p-60, 1e-17, 1e-9, 0.41421356237309492, 0.41421356237309515, 1.0,
+                             3.0, 1e15, 0x1p53, 1.7976931348623157e308};
+    for (double x : ends1p) w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_pos(x), log1pl(x)));
+    if (mc::ln1p_pos(0.0) != 0.0 || mc::ln1p_pos(INFINITY) != INFINITY) { std::puts("FAIL ln1p 0 / inf"); return 1; }
+    // exact values at the quarter turns
+    const double turns[] = {0.0, 0.25, 0.5, 0.75, 1.0};
+    const double want_s[] = {0.0, 1.0, 0.0, -1.0, 0.0}, want_c[] = {1.0, 0.0, -1.0, 0.0, 1.0};
+    for (int i = 0; i < 5; ++i) {
+        double s, c;
+        mc::sincos_turn(turns[i], &s, &c);
+        if (s != want_s[i] || c != want_c[i]) { std::printf("FAIL turn %g: %g %g\n", turns[i], s, c); return 1; }
+    }
+    // bounds: 2 ulp, and 2.5 for log1p (its correction for the rounding of
+    // 1 + x adds a rounding where e ln 2 and ln m nearly cancel)
+    const bool ok = w_ln <= 2.0 && w_ln1p <= 2.5 && std::fmax(std::fmax(w_sin, w_cos), std::fmax(w_sin2, w_cos2)) <= 2.0;
+    std::printf("%s ln %.3f ln1p %.3f sin %.3f cos %.3f sin(unreduced) %.3f cos(unreduced) %.3f\n",
+                ok ? "OK" : "FAIL", w_ln, w_ln1p, w_sin, w_cos, w_sin2, w_cos2);
     return 0;
 }
 '''
 
 
-def test_restricted_log_within_two_ulp(tmp_path):
+def test_restricted_functions_within_two_ulp(tmp_path):
     csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2609_31258_amd", "csrc")
-    src = tmp_path / "ln_test.cpp"
+    src = tmp_path / "math64_test.cpp"
     src.write_text(HARNESS)
-    exe = tmp_path / "ln_test"
+    exe = tmp_path / "math64_test"
     subprocess.run(["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-I" + csrc, str(src), "-o", str(exe)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.strip()
+    print(out)
     assert out.startswith("OK"), out
