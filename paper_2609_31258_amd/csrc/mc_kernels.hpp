@@ -19,8 +19,6 @@
 #include "../../include/mucite.h"
 #include "mc_device.hpp"
 
-#include <type_traits>
-
 namespace mc {
 
 template <class T>
@@ -275,11 +273,11 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
     uint32_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0;  // per pack and step: < 2^32
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
         n.act = 1;
-        // FP32 form: a reference, so each field is read where it is used and the
-        // dissociation constants hold no registers through the collision loop
-        // (at five waves they would spill); FP64: one copy of the record
-        using SpeciesRef = std::conditional_t<P::kTwo, const Species &, const Species>;
-        SpeciesRef sp = a.sp[a.p.tag[s]];
+        // the species record by reference, so each field is read where it is
+        // used and the dissociation constants hold no registers through the
+        // collision loop (at five waves in the FP32 form and three in the FP64
+        // form they would spill)
+        const Species &sp = a.sp[a.p.tag[s]];
         const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
         const T x0 = a.p.x[s], y0 = a.p.y[s], z0 = a.p.z[s];
         T xl = 0, yl = 0, zl = 0;
@@ -537,12 +535,14 @@ __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount
 }
 
 // Waves per SIMD the step kernel is compiled for (its register budget):
-// the FP64 form holds its loop state in register pairs and runs two waves
-// (three force spills to scratch, which measured slower); the FP32 form
-// with BF16 tables fits five without spilling.
+// the FP64 form holds its loop state in register pairs and runs three waves
+// in 167 registers (one pair, a species constant of the internal-energy
+// exchange, is reloaded from scratch there; measured 3 % faster than two
+// waves without spills); the FP32 form with BF16 tables fits five without
+// spilling.
 template <class P, class Tab>
 constexpr int step_waves() {
-    return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 2;
+    return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 3;
 }
 
 template <class P, class Tab>
