@@ -15,8 +15,10 @@ reported beside it, and so is the hybrid form (the FP32 form with the
 Langevin branch taking the dense first millimetre).
 
 Also reported: the dominant kernel's roofline (HIP events around every
-launch of the fused step kernel), and the CPU oracle's rate on a bounded
-sample of the same workload on this host's cores.
+launch of the fused step kernel), windows of the masked Poisson solve, the
+snapshots and the adaptive step on the full-occupancy state (`next_rows`),
+the serving leg, and the CPU oracle's rate on a bounded sample of the same
+workload on this host's cores.
 """
 from __future__ import annotations
 
@@ -123,6 +125,8 @@ def parse():
     ap.add_argument("--serving-steps", type=int, default=2000)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the windows of the masked Poisson solve, the snapshots and the adaptive step")
     ap.add_argument("--large", action="store_true",
                     help="also time a window of the large configuration (1024x8192 grid, 1.6e7 packs of ten "
                          "species, FP32 form) at full occupancy")
@@ -285,9 +289,7 @@ def cpu_baseline(n_packs: int, n_steps: int):
     n_steps steps including the space-charge updates."""
     from oracle.binding import OracleSim, num_threads
     from paper_2609_31258_amd import synth
-    f, ions, srcs, op, _ = synth.config_c2()
-    snap = synth.pack_snapshot(n_packs, f, seed=synth.SEED, z_hi=3e-4, r_hi=3e-4, v_sigma=22.0, v_drift=300.0,
-                               e_lo=1.7e-18, e_hi=1.9e-18, weight=srcs[0].current_a * op.dt / (5 * 1.602176634e-19) / 500)
+    f, ions, op, snap = full_occupancy_snapshot(n_packs)
     o = OracleSim(synth.SEED)
     o.setup(f, ions, [], op)
     o.write_packs(snap)
@@ -314,6 +316,86 @@ def serving_query(f, q, steps: int):
     op = synth.Operating(dt=0.5e-9, v_rf=q["v_rf"], f_rf=1e6, v_off=q["v_off"], sc_on=1, sc_every=10,
                          z_det=f.grid.L, r_det=f.grid.R, exit_bin_dt=1e-7, n_exit_bins=100)
     return ion, src, op
+
+
+def full_occupancy_snapshot(n_packs: int):
+    """The workload's full-occupancy state as a pack snapshot: n_packs packs
+    within 0.3 mm of the injection plane, thermal about the gas flow, at the
+    source's pack weight (the state the emission ramp reaches)."""
+    from paper_2609_31258_amd import synth
+    f, ions, srcs, op, _ = synth.config_c2()
+    snap = synth.pack_snapshot(n_packs, f, seed=synth.SEED, z_hi=3e-4, r_hi=3e-4, v_sigma=22.0, v_drift=300.0,
+                               e_lo=1.7e-18, e_hi=1.9e-18, weight=srcs[0].current_a * op.dt / (5 * 1.602176634e-19) / 500)
+    return f, ions, op, snap
+
+
+def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_capacity: int = 0, **op_changes):
+    """One timed window of the full-occupancy state with some operating
+    fields changed (the next rows: masked Poisson, snapshots, adaptive step).
+    The first step (and with it the first space-charge update, where the
+    capacitance matrix of the masked solve is built) is timed on its own."""
+    import torch
+    from paper_2609_31258_amd import mucite, synth
+    f, ions, op, snap = full_occupancy_snapshot(n_packs)
+    for k, v in op_changes.items():
+        setattr(op, k, v)
+    sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=precision, timing=True,
+                     sample_capacity=sample_capacity)
+    sim.setup(f, ions, [], op)
+    sim.write_packs(snap)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(1)
+    sim.synchronize()
+    first = time.perf_counter() - t0
+    sim.step(9)
+    sim.synchronize()
+    sim.reset_timing()
+    before, t_sim0 = sim.read_tallies(), sim.info()["time"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    t2 = time.perf_counter()
+    after, info = sim.read_tallies(), sim.info()
+    tim = sim.read_timing()
+    n_samples = len(sim.read_samples()) if sample_capacity else 0
+    sim.close()
+    wall = t2 - t1
+    ps = after["pack_steps"] - before["pack_steps"]
+    sim_time = info["time"] - t_sim0
+    updates = max(tim["launches"]["poisson"], 1)
+    print(f"[bench] {name}: {ps / wall:.3e} pack-steps/s, {wall * 1e3 / steps:.3f} ms per step", file=sys.stderr,
+          flush=True)
+    return {"value": ps / wall, "unit": "pack-steps/s", "ms_per_step": wall * 1e3 / steps, "steps": steps,
+            "first_step_s": first, "mean_dt_s": sim_time / steps, "simulated_s_per_wall_s": sim_time / wall,
+            "space_charge_updates": tim["launches"]["poisson"],
+            "update_ms": (tim["ms"]["deposit"] + tim["ms"]["poisson"] + tim["ms"]["field"]) / updates,
+            "samples": n_samples, "kernel_ms": tim["ms"]}
+
+
+def run_next_rows(steps: int, n_packs: int = 1_000_000):
+    """The next rows on the full-occupancy state of the workload, FP32 form:
+    a plain window, the masked Poisson solve (potential zero on the ring
+    electrodes' mask nodes), full-population snapshots every 20 steps, and
+    the adaptive step of Eq. 1 with explicit collisions and on the hybrid
+    branch (largest step 2 ns, the Langevin cap)."""
+    from paper_2609_31258_amd import synth
+    f, _, _, _ = full_occupancy_snapshot(1)
+    g = f.grid
+    mask = f.mask.reshape(g.nz, g.nr)
+    out = {"state": f"{n_packs} packs at the full-occupancy state of the workload (FP32 form, BF16 tables)"}
+    out["plain"] = run_variant("plain", steps, n_packs)
+    out["masked_poisson"] = run_variant("masked poisson", steps, n_packs, sc_mask=1)
+    out["masked_poisson"]["mask_nodes"] = int(mask[1:-1, :-1].sum())
+    out["snapshots"] = run_variant("snapshots", steps, n_packs, sample_capacity=n_packs * (steps // 20 + 2),
+                                   sample_every=20, sample_stride=1)
+    out["adaptive_explicit"] = run_variant("adaptive (explicit collisions)", steps, n_packs, adaptive=1)
+    out["hybrid_fixed"] = run_variant("hybrid, fixed 0.5 ns", steps, n_packs, langevin_on=1, lv_z_lo=0.0,
+                                      lv_z_hi=1e-3, lv_switch=0.05)
+    out["adaptive_hybrid"] = run_variant("adaptive hybrid", steps, n_packs, langevin_on=1, lv_z_lo=0.0,
+                                         lv_z_hi=1e-3, lv_switch=0.05, adaptive=1, dt=2e-9, lv_dt_max=2e-9)
+    return out
 
 
 def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budget_gib: float, max_resident: int):
@@ -418,6 +500,8 @@ def main():
                               "speedup_vs_explicit_fp32": (h["pack_steps"] / h["wall"]) / (ref["pack_steps"] / ref["wall"])
                               if ref else None,
                               "roofline": hbm_roofline(h, "fp32", "step", "hybrid"), "kernel_ms": h["timing"]["ms"]}
+    if not args.no_next_rows:
+        out["next_rows"] = run_next_rows(args.steps)
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)

@@ -907,12 +907,13 @@ int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
         int32_t rc;
         if (ctx->op.sample_every > 0 && ctx->op.sample_stride > 0 && ctx->step % ctx->op.sample_every == 0 &&
             ctx->n_slots > 0) {
+            const unsigned sgrid = (unsigned)((ctx->n_slots + kSampleThreads - 1) / kSampleThreads);
             if (ctx->fp32())
-                k_sample<float><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(
+                k_sample<float><<<sgrid, kSampleThreads, 0, ctx->stream>>>(
                     ctx->p32, ctx->sp_dev, ctx->n_slots, ctx->step, ctx->op.sample_stride, ctx->samples,
                     ctx->sample_count, ctx->sample_cap);
             else
-                k_sample<double><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(
+                k_sample<double><<<sgrid, kSampleThreads, 0, ctx->stream>>>(
                     ctx->p64, ctx->sp_dev, ctx->n_slots, ctx->step, ctx->op.sample_stride, ctx->samples,
                     ctx->sample_count, ctx->sample_cap);
             LAUNCHCHK();

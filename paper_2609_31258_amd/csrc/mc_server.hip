@@ -438,7 +438,8 @@ static int32_t sample_query(mc_server *S, Query &Q) {
     const mc_operating &qo = Q.q.op;
     if (qo.sample_every > 0 && qo.sample_stride > 0 && Q.step % qo.sample_every == 0 && Q.n_slots > 0 &&
         Q.q.sample_capacity > 0) {
-        k_sample<typename P::T><<<blocks_for(Q.n_slots), kBlk, 0, S->stream>>>(
+        k_sample<typename P::T><<<(unsigned)((Q.n_slots + kSampleThreads - 1) / kSampleThreads), kSampleThreads, 0,
+                                  S->stream>>>(
             packs_of<P, Tab>(Q), Q.sp_dev, Q.n_slots, Q.step, qo.sample_stride, Q.samples, Q.scount,
             Q.q.sample_capacity);
         SCHK(hipGetLastError());
