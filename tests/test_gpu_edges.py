@@ -2,7 +2,8 @@
 terminal class (against the oracle: classes, nodes, tallies and exit-time
 bins exactly, crossing time and radius within 1e-12), collision-free steps
 within 1e-12 (RK4 with four bilinear gathers, rounding apart), exit-buffer
-overflow, capacity and argument errors, and empty steps."""
+overflow, capacity and argument errors, empty steps, and gas regions where
+the collision rate vanishes (vacuum, zero gas temperature)."""
 import sys
 
 import numpy as np
@@ -130,3 +131,66 @@ def test_non_finite_field_tables_are_refused():
         assert e.value.code == mucite.MC_EINVAL, name
         g.load_fields(f)  # the context is still usable
         g.close()
+
+
+def _degenerate_gas_fields():
+    """The C1 field set with a vacuum third (gas pressure 0), a third at zero
+    gas temperature (pressure kept), and gas beyond: the collision rate is
+    zero in the first two, where a pack must fly free."""
+    f, ions, _, op, _ = synth.config_c1(100)
+    g = f.grid
+    p = f.gas_p.reshape(g.nz, g.nr).copy()
+    t = f.gas_t.reshape(g.nz, g.nr).copy()
+    p[: g.nz // 3, :] = 0.0
+    t[g.nz // 3: 2 * g.nz // 3, :] = 0.0
+    f.gas_p, f.gas_t = p.reshape(-1), t.reshape(-1)
+    return f, ions, op
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_vacuum_and_zero_temperature_gas_match_the_oracle(precision):
+    """Packs spread over the three regions: one step against the oracle
+    (statuses exactly; FP64: state within 1e-6 and candidate count within
+    1e-3; FP32 form: candidate count within 1 %).  Packs only in the vacuum
+    third: three steps with collisions on equal the collision-free steps bit
+    for bit and draw no candidate."""
+    from paper_2609_31258_amd import mucite
+    from tests.parity_util import step_errors, thermal_speed
+    f, ions, op = _degenerate_gas_fields()
+    g = f.grid
+    n = 6000
+    snap = synth.pack_snapshot(n, f, seed=23, z_lo=0.05 * g.L, z_hi=0.95 * g.L, r_hi=0.2 * g.R, v_sigma=300.0)
+    _say("degenerate gas regions, precision", precision)
+    gp, orc = make_pair(f, ions, [], op, cap=n, precision=precision)
+    gp.write_packs(snap)
+    orc.write_packs(snap)
+    gp.step(1)
+    orc.step(1)
+    a, b = by_id(gp.read_packs()), by_id(orc.read_packs())
+    assert np.array_equal(a["status"], b["status"])
+    ta, tb = gp.read_tallies(), orc.read_tallies()
+    _say(f"  candidates gpu {ta['n_cand']} oracle {tb['n_cand']}")
+    assert tb["n_cand"] > 0
+    if precision == 0:
+        r = step_errors(gp.read_packs(), orc.read_packs(), g.dr, thermal_speed(), snap["h"])
+        assert r["ok"].sum() >= n - max(1, n // 10_000)
+        assert abs(ta["n_cand"] - tb["n_cand"]) <= max(2, tb["n_cand"] // 1000)
+    else:
+        assert abs(ta["n_cand"] - tb["n_cand"]) <= 0.01 * tb["n_cand"]
+    gp.close()
+
+    zv = (g.nz // 3 - 2) * g.dz  # below it every gather reads only vacuum nodes
+    snap_v = synth.pack_snapshot(2000, f, seed=29, z_lo=0.1 * zv, z_hi=0.5 * zv, r_hi=0.2 * g.R, v_sigma=300.0)
+    runs = []
+    for coll in (1, 0):
+        op.collisions_on = coll
+        s = mucite.Sim(seed=synth.SEED, pack_capacity=2000, precision=precision)
+        s.setup(f, ions, [], op)
+        s.write_packs(snap_v)
+        s.step(3)
+        runs.append((s.read_packs(), s.read_tallies()))
+        s.close()
+    (pa, ta), (pb, tb) = runs
+    assert ta["n_cand"] == 0 and tb["n_cand"] == 0
+    for k in ("x", "y", "z", "vx", "vy", "vz", "e_int", "h", "status"):
+        assert np.array_equal(pa[k], pb[k]), k
