@@ -73,11 +73,36 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_31258_amd", "csrc", f)
                   for f in ("mc_kernels.hpp", "mc_device.hpp", "mc_math64.hpp")]
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and blank lines (string and character
+    literals kept), so that the hash below changes with the code only."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            i = text.find("\n", i)
+            i = n if i < 0 else i
+        elif text.startswith("/*", i):
+            i = text.find("*/", i + 2)
+            i = n if i < 0 else i + 2
+        else:
+            out.append(c)
+            i += 1
+    return "\n".join(line.rstrip() for line in "".join(out).splitlines() if line.strip())
+
+
 def kernel_source_hash() -> str:
+    """sha256[:16] of the step and deposit kernels' code (comments excluded)."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+        h.update(_code_only(open(f, encoding="utf-8").read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -73,14 +73,25 @@ __device__ __forceinline__ W4 draw(int64_t id, int64_t step, uint32_t purpose, u
 // ---------------------------------------------------------------------------
 // Precision policies.
 // ---------------------------------------------------------------------------
+// The FP64 logarithm table of the block (ln_tab, ln1p_tab): loaded by the
+// kernels that take the step (P::prepare_ln), which are its only readers.
+static __shared__ LnEntry g_ln_tab[kLnBins];
+
 struct P64 {
     using T = double;
     static constexpr bool kTwo = false;
+    // every thread of the block calls this before the first ln_fast/log1p_
+    static __device__ __forceinline__ void prepare_ln(const LnEntry *src) {
+        for (int k = threadIdx.x; k < kLnBins; k += blockDim.x) g_ln_tab[k] = src[k];
+        __syncthreads();
+    }
     // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double (an add of an
     // inline constant and an exponent shift: no 64-bit constant in a register)
     static __device__ __forceinline__ double u01(uint32_t w) { return ((double)w + 0.5) * 0x1p-32; }
     // every call site passes x in (0, 1] (uniform variates and their products)
     static __device__ __forceinline__ double ln(double x) { return ln_pos(x); }
+    // the same from the block's table (step kernels, after prepare_ln)
+    static __device__ __forceinline__ double ln_fast(double x) { return ln_tab(x, g_ln_tab); }
     // x >= 0 and zero or normal at every call site: the reciprocal square
     // root seed refined by two coupled Newton (Goldschmidt) iterations for
     // y = sqrt(x), h = 1/(2 sqrt(x)), then one residual correction
@@ -98,8 +109,9 @@ struct P64 {
     }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
-    // every call site passes a positive ratio (the Einstein-model inverse)
-    static __device__ __forceinline__ double log1p_(double x) { return ln1p_pos(x); }
+    // every call site passes a positive ratio (the Einstein-model inverse,
+    // called in the step kernels only, after prepare_ln)
+    static __device__ __forceinline__ double log1p_(double x) { return ln1p_tab(x, g_ln_tab); }
     // sin(2 pi u), cos(2 pi u) of uniform variates u in (0, 1): a quarter-turn
     // reduction and two short series instead of the library's general reduction
     static __device__ __forceinline__ void sc2pi(double u, double *s, double *c) { sincos_turn(u, s, c); }
@@ -115,7 +127,9 @@ struct P32 {
     static __device__ __forceinline__ float u01(uint32_t w) {
         return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-25f);  // exact
     }
+    static __device__ __forceinline__ void prepare_ln(const LnEntry *) {}
     static __device__ __forceinline__ float ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
+    static __device__ __forceinline__ float ln_fast(float x) { return ln(x); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }

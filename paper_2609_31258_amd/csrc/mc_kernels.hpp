@@ -199,6 +199,7 @@ struct StepArgs {
     int32_t langevin_on;
     double lv_z_lo, lv_z_hi, lv_switch, lv_dt_ref;  // switch: lambda lv_dt_ref >= lv_switch
     uint32_t k0, k1;
+    const LnEntry *ln_tab;  // FP64 logarithm table (kLnBins entries, device memory)
 };
 
 // Total field of Eq. 4 at (x, y, z), radial part projected by Eq. 3.
@@ -407,8 +408,8 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     // hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward the gas
                     // velocity over dt, hard-sphere friction rate, Box-Muller normals from one block
                     const W4 w = draw(P::kTwo ? id : a.p.id[s], a.step, kPurposeLangevin, 0u, k0, k1);
-                    const T r0 = P::sqrt_((T)-2 * P::ln(P::u01(w.w0)));
-                    const T r1 = P::sqrt_((T)-2 * P::ln(P::u01(w.w2)));
+                    const T r0 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w0)));
+                    const T r1 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w2)));
                     T s0, c0;
                     P::sc2pi(P::u01(w.w1), &s0, &c0);
                     const T c1 = P::cos2pi(P::u01(w.w3));
@@ -432,7 +433,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                         break;
                     }
                     const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), k0, k1);
-                    const T tau = -P::div(P::ln(P::u01(wa.w0)), lam);
+                    const T tau = -P::div(P::ln_fast(P::u01(wa.w0)), lam);
                     if (!(tau < tleft)) break;
                     tleft -= tau;
                     ++ncand;
@@ -441,7 +442,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
                     const bool maxw = P::u01(wa.w1) * (sv + abar) < sv;  // u < s/(s + abar)
                     const T cc = P::cos2pi(P::u01(wb.w0));
-                    const T en = -P::ln(P::u01(wa.w2)) - P::ln(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
+                    const T en = -P::ln_fast(P::u01(wa.w2)) - P::ln_fast(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
                     const T wn = ag * P::sqrt_((T)2 * en);
                     const T ct = (T)2 * P::u01(wb.w1) - (T)1;
                     const T st = P::sqrt_(fmax((T)0, (T)1 - ct * ct));
@@ -462,7 +463,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     // exchange select: the acceptance residual, uniform given acceptance
                     if (uacc * (sv + wn) < alpha * gn) {  // residual uacc (s + |w|)/|g| < alpha
                         const T te = einstein_t<P>(e + el, skt, theta);
-                        etp = -(T)kB * te * P::ln(P::u01(wc.w2) * P::u01(wc.w3));
+                        etp = -(T)kB * te * P::ln_fast(P::u01(wc.w2) * P::u01(wc.w3));
                         const T de = et - etp;
                         if (e + el + de < (T)0) {
                             etp = e + el + et;
@@ -536,10 +537,8 @@ __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount
 
 // Waves per SIMD the step kernel is compiled for (its register budget):
 // the FP64 form holds its loop state in register pairs and runs three waves
-// in 167 registers (one pair, a species constant of the internal-energy
-// exchange, is reloaded from scratch there; measured 3 % faster than two
-// waves without spills); the FP32 form with BF16 tables fits five without
-// spilling.
+// in 161 registers (measured 3 % faster than two); the FP32 form with BF16
+// tables fits five.  Neither spills.
 template <class P, class Tab>
 constexpr int step_waves() {
     return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 3;
@@ -547,6 +546,7 @@ constexpr int step_waves() {
 
 template <class P, class Tab>
 __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
+    P::prepare_ln(a.ln_tab);
     StepCount n{0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
     flush_counts(a.t, n);
@@ -650,6 +650,7 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(cons
                                                     int32_t nq) {
     const int q = block_query(prefix, nq);
     const StepArgs<P, Tab> &a = descs[q];
+    P::prepare_ln(a.ln_tab);
     StepCount n{0, 0, 0, 0, 0, 0};
     // the random key is the query's, the same for the whole block: scalar
     step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n,

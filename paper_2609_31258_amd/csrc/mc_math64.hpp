@@ -7,24 +7,28 @@
 // candidate, three or four logarithms of uniform variates or their products
 // in (0, 1], two sine/cosine pairs and a cosine of 2 pi u for uniform u, and
 // (in the internal-energy exchange) a log1p of a positive ratio.  These
-// restricted versions stay within 2 ulp there (log1p 2.5; tested on the host
-// against extended-precision references) in a third to a half of the
-// instructions.
+// restricted versions stay within 2 ulp there (tested on the host against
+// extended-precision references) in a fifth to a half of the instructions.
 //
 //   div_mid(n, d)        n / d for d in [1, 4), |n| < 1 (its quotient step)
-//   ln_pos(x)            natural logarithm, x > 0 normal and finite
-//   ln1p_pos(x)          ln(1 + x), x >= 0 (+inf gives +inf)
+//   ln_pos(x)            natural logarithm, x > 0 normal and finite (series)
+//   ln_tab(x, tab)       the same from a 256-bin table (ln_table_fill)
+//   ln1p_tab(x, tab)     ln(1 + x), x >= 0 (+inf gives +inf), from the table
 //   sincos_turn(u, s, c) sin(2 pi u), cos(2 pi u), 0 <= u <= 1
 //   cos_turn(u)          cos(2 pi u), 0 <= u <= 1
 //
 // Plain C++ (host and device).
 #pragma once
 #include <cmath>
+#include <cstdint>
+#include <cstring>
 
 #if defined(__HIPCC__)
 #define MC_HD __host__ __device__ __forceinline__
+#define MC_H __host__ inline
 #else
 #define MC_HD inline
+#define MC_H inline
 #endif
 
 namespace mc {
@@ -89,29 +93,80 @@ MC_HD double ln_pos(double x) {
     return add_e_ln2(e, atanh2(m - 1.0, m + 1.0));  // m - 1 and m + 1 are exact
 }
 
-// ln(1 + x) for x >= 0.  With y = 1 + x rounded, y = m 2^e as in ln_pos:
-// for e = 0 (x < sqrt 2 - 1) ln(1 + x) = 2 atanh(x / (2 + x)) exactly, which
-// keeps full relative precision for small x; otherwise ln y plus the
-// first-order correction for the rounding of y, (x - (y - 1)) / y, which is at
-// most 2^-53 against a result of at least ln(sqrt 2) (a reciprocal estimate is
-// ample for it).
-MC_HD double ln1p_pos(double x) {
+// Table-driven logarithm (the step's collision loop, where the table sits in
+// LDS).  x = mm 2^e with mm in [1/2, 1) from frexp; bin j (0..255) = the top
+// eight fraction bits of mm.  Bins below sqrt(1/2) (j < 106) take the reduced
+// argument m = 2 mm and exponent e - 1, the others m = mm; each bin stores
+// c_j = (m / mm) / m_j and t_j = ln m_j for its centre m_j (m_j = 1 for the
+// two bins next to m = 1, so that ln x is exact in its leading term there).
+// Then r = mm c_j - 1 (one rounding; |r| < 2^-8) and
+// ln x = (e or e - 1) ln 2 + t_j + ln(1 + r), the last by its series through
+// r^7 (relative truncation below 2^-58).
+struct LnEntry {
+    double c, t;
+};
+constexpr int kLnBins = 256, kLnDoubled = 106;
+
+// The table, in extended precision on the host (c_j rounded once, t_j the
+// logarithm of the centre that c_j stands for).
+MC_H void ln_table_fill(LnEntry *tab) {
+    for (int j = 0; j < kLnBins; ++j) {
+        const long double lo = 0.5L + (long double)j / (2 * kLnBins), centre = lo + 1.0L / (4 * kLnBins);
+        const long double scale = j < kLnDoubled ? 2.0L : 1.0L;  // m / mm
+        long double mj = scale * centre;
+        if (j == 0 || j == kLnBins - 1) mj = 1.0L;                 // bins next to m = 1
+        tab[j].c = (double)(scale / mj);
+        tab[j].t = (double)logl(scale / (long double)tab[j].c);  // ln of the centre c_j stands for
+    }
+}
+
+// ln(1 + r) - r = r^2 (-1/2 + r/3 - r^2/4 + ... + r^5/7) for |r| < 2^-8.
+MC_HD double log1p_small(double r) {
+    double q = 1.0 / 7.0;
+    q = std::fma(q, r, -1.0 / 6.0);
+    q = std::fma(q, r, 1.0 / 5.0);
+    q = std::fma(q, r, -1.0 / 4.0);
+    q = std::fma(q, r, 1.0 / 3.0);
+    q = std::fma(q, r, -0.5);
+    return std::fma(r * r, q, r);
+}
+
+// Bin of the frexp mantissa mm in [1/2, 1): its top eight fraction bits.
+MC_HD int ln_bin(double mm) {
+    uint64_t b;
+    std::memcpy(&b, &mm, sizeof b);
+    return (int)((b >> 44) & (kLnBins - 1));
+}
+
+// ln x for x > 0 normal and finite, with the table above.
+MC_HD double ln_tab(double x, const LnEntry *tab) {
+    int e;
+    const double mm = std::frexp(x, &e);
+    const int j = ln_bin(mm);
+    const LnEntry en = tab[j];
+    const double r = std::fma(mm, en.c, -1.0);
+    return add_e_ln2(j < kLnDoubled ? e - 1 : e, en.t + log1p_small(r));
+}
+
+// ln(1 + x) for x >= 0 with the table: ln y for y = 1 + x rounded, plus the
+// first-order correction (x - (y - 1)) / y for the rounding of y (exact
+// subtraction; at most 2^-53 relative to y, so a reciprocal estimate is ample);
+// +inf gives +inf.
+MC_HD double ln1p_tab(double x, const LnEntry *tab) {
     const double y = 1.0 + x;
     int e;
-    double m = std::frexp(y, &e);
-    if (m < 0.70710678118654752440) {
-        m += m;
-        --e;
-    }
-    const bool small = e == 0;
+    const double mm = std::frexp(y, &e);
+    const int j = ln_bin(mm);
+    const LnEntry en = tab[j];
+    const double r = std::fma(mm, en.c, -1.0);
 #if defined(__HIP_DEVICE_COMPILE__)
     const double ry = __builtin_amdgcn_rcp(y);
 #else
     const double ry = 1.0 / y;
 #endif
-    const double corr = small ? 0.0 : (x - (y - 1.0)) * ry;
-    const double r = add_e_ln2(e, atanh2(small ? x : m - 1.0, small ? 2.0 + x : m + 1.0) + corr);
-    return y < HUGE_VAL ? r : y;
+    const double corr = (x - (y - 1.0)) * ry;
+    const double v = add_e_ln2(j < kLnDoubled ? e - 1 : e, en.t + (log1p_small(r) + corr));
+    return y < HUGE_VAL ? v : y;
 }
 
 // sin(2 pi u) and cos(2 pi u) for 0 <= u <= 1.  q = rint(4u) is the nearest

@@ -1,10 +1,11 @@
 """The restricted FP64 elementary functions of the step kernel
 (mc_math64.hpp), compiled on the host with g++ and checked against
-extended-precision (x87 long double) references: each within 2 ulp (log1p
-2.5) over the arguments the step takes -- uniform variates (w + 1/2) 2^-32 and their
-products for the logarithm, positive ratios over the whole double range for
-log1p, uniform turns for the sine and cosine -- and at the ends of each
-domain."""
+extended-precision (x87 long double) references: each within 2 ulp over the
+arguments the step takes -- uniform variates (w + 1/2) 2^-32 and their
+products for the logarithms (series and table-driven, the latter also at both
+ends and the centre of every bin), positive ratios over the whole double
+range for log1p, uniform turns for the sine and cosine -- and at the ends of
+each domain."""
 import os
 import subprocess
 
@@ -22,8 +23,10 @@ static double ulps(double a, long double ref) {
 }
 static long double two_pi_l() { return 2.0L * 3.14159265358979323846264338327950288L; }
 int main() {
+    mc::LnEntry tab[mc::kLnBins];
+    mc::ln_table_fill(tab);
     std::mt19937_64 rng(3);
-    double w_ln = 0, w_ln1p = 0, w_sin = 0, w_cos = 0, w_sin2 = 0, w_cos2 = 0;
+    double w_ln = 0, w_lnt = 0, w_ln1p = 0, w_sin = 0, w_cos = 0, w_sin2 = 0, w_cos2 = 0;
     for (long k = 0; k < 2000000; ++k) {
         const double u = ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
         const double v = ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
@@ -32,11 +35,17 @@ int main() {
         w_ln = std::fmax(w_ln, ulps(mc::ln_pos(u * v), logl((long double)(u * v))));
         const double x = std::ldexp(0.5 + 0.5 * u, (int)(rng() % 2040) - 1020);
         w_ln = std::fmax(w_ln, ulps(mc::ln_pos(x), logl(x)));
-        // log1p: positive ratios from 2^-1020 to 2^1020, and near the
-        // switch at sqrt 2 - 1
-        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_pos(x), log1pl(x)));
+        // the table-driven logarithm on the same arguments
+        w_lnt = std::fmax(w_lnt, ulps(mc::ln_tab(u, tab), logl(u)));
+        w_lnt = std::fmax(w_lnt, ulps(mc::ln_tab(u * v, tab), logl((long double)(u * v))));
+        w_lnt = std::fmax(w_lnt, ulps(mc::ln_tab(x, tab), logl(x)));
+        // log1p: positive ratios from 2^-1020 to 2^1020, small ratios, and
+        // near the bins next to 1 + x = 1 and sqrt 2
+        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_tab(x, tab), log1pl(x)));
         const double y = 0.41421356237309503 * (1.0 + (v - 0.5) * 1e-3);
-        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_pos(y), log1pl(y)));
+        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_tab(y, tab), log1pl(y)));
+        const double z = std::ldexp(1.0 + u, -(int)(rng() % 60));
+        w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_tab(z, tab), log1pl(z)));
         // sine and cosine of a turn: against the reference on the same exact
         // reduction (all arguments), and against the unreduced extended
         // argument where the result is not near a zero (checks the quadrants)
@@ -60,11 +69,19 @@ int main() {
     const double ends[] = {1.0, 0.5, 0x1p-66, 0x1p-1022, 0.70710678118654746, 0.70710678118654757,
                            1.0 - 0x1p-53, 0.9999999, 0x1p1000, 1.7976931348623157e308};
     for (double x : ends) w_ln = std::fmax(w_ln, ulps(mc::ln_pos(x), logl(x)));
-    if (mc::ln_pos(1.0) != 0.0) { std::puts("FAIL ln 1"); return 1; }
+    for (double x : ends) w_lnt = std::fmax(w_lnt, ulps(mc::ln_tab(x, tab), logl(x)));
+    if (mc::ln_pos(1.0) != 0.0 || mc::ln_tab(1.0, tab) != 0.0) { std::puts("FAIL ln 1"); return 1; }
+    // every bin of the table, at its ends and centre
+    for (int j = 0; j < mc::kLnBins; ++j)
+        for (double f : {0.0, 0.5, 1.0 - 0x1p-40}) {
+            const double mm = 0.5 + (j + f) / (2.0 * mc::kLnBins);
+            w_lnt = std::fmax(w_lnt, ulps(mc::ln_tab(mm, tab), logl(mm)));
+            w_lnt = std::fmax(w_lnt, ulps(mc::ln_tab(2 * mm, tab), logl(2 * mm)));
+        }
     const double ends1p[] = {0x1p-1074, 0x1p-60, 1e-17, 1e-9, 0.41421356237309492, 0.41421356237309515, 1.0,
                              3.0, 1e15, 0x1p53, 1.7976931348623157e308};
-    for (double x : ends1p) w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_pos(x), log1pl(x)));
-    if (mc::ln1p_pos(0.0) != 0.0 || mc::ln1p_pos(INFINITY) != INFINITY) { std::puts("FAIL ln1p 0 / inf"); return 1; }
+    for (double x : ends1p) w_ln1p = std::fmax(w_ln1p, ulps(mc::ln1p_tab(x, tab), log1pl(x)));
+    if (mc::ln1p_tab(0.0, tab) != 0.0 || mc::ln1p_tab(INFINITY, tab) != INFINITY) { std::puts("FAIL ln1p 0 / inf"); return 1; }
     // exact values at the quarter turns
     const double turns[] = {0.0, 0.25, 0.5, 0.75, 1.0};
     const double want_s[] = {0.0, 1.0, 0.0, -1.0, 0.0}, want_c[] = {1.0, 0.0, -1.0, 0.0, 1.0};
@@ -73,11 +90,10 @@ int main() {
         mc::sincos_turn(turns[i], &s, &c);
         if (s != want_s[i] || c != want_c[i]) { std::printf("FAIL turn %g: %g %g\n", turns[i], s, c); return 1; }
     }
-    // bounds: 2 ulp, and 2.5 for log1p (its correction for the rounding of
-    // 1 + x adds a rounding where e ln 2 and ln m nearly cancel)
-    const bool ok = w_ln <= 2.0 && w_ln1p <= 2.5 && std::fmax(std::fmax(w_sin, w_cos), std::fmax(w_sin2, w_cos2)) <= 2.0;
-    std::printf("%s ln %.3f ln1p %.3f sin %.3f cos %.3f sin(unreduced) %.3f cos(unreduced) %.3f\n",
-                ok ? "OK" : "FAIL", w_ln, w_ln1p, w_sin, w_cos, w_sin2, w_cos2);
+    const bool ok = std::fmax(std::fmax(w_ln, w_lnt), w_ln1p) <= 2.0 &&
+                    std::fmax(std::fmax(w_sin, w_cos), std::fmax(w_sin2, w_cos2)) <= 2.0;
+    std::printf("%s ln %.3f ln(table) %.3f ln1p(table) %.3f sin %.3f cos %.3f sin(unreduced) %.3f cos(unreduced) %.3f\n",
+                ok ? "OK" : "FAIL", w_ln, w_lnt, w_ln1p, w_sin, w_cos, w_sin2, w_cos2);
     return 0;
 }
 '''
