@@ -73,16 +73,21 @@ __device__ __forceinline__ W4 draw(int64_t id, int64_t step, uint32_t purpose, u
 // ---------------------------------------------------------------------------
 // Precision policies.
 // ---------------------------------------------------------------------------
-// The FP64 logarithm table of the block (ln_tab, ln1p_tab): loaded by the
-// kernels that take the step (P::prepare_ln), which are its only readers.
-static __shared__ LnEntry g_ln_tab[kLnBins];
+// The FP64 step's tables in the block's LDS (logarithm and turn tables):
+// loaded by the kernels that take the step (P::prepare_tables), which are
+// their only readers.
+static __shared__ StepTables g_tables;
 
 struct P64 {
     using T = double;
     static constexpr bool kTwo = false;
-    // every thread of the block calls this before the first ln_fast/log1p_
-    static __device__ __forceinline__ void prepare_ln(const LnEntry *src) {
-        for (int k = threadIdx.x; k < kLnBins; k += blockDim.x) g_ln_tab[k] = src[k];
+    // every thread of the block calls this before the first table read
+    // (ln_fast, log1p_, sc2pi_fast, cos2pi_fast)
+    static __device__ __forceinline__ void prepare_tables(const StepTables *src) {
+        static_assert(sizeof(StepTables) % sizeof(double2) == 0, "tables move in 16-byte pieces");
+        const double2 *from = reinterpret_cast<const double2 *>(src);
+        double2 *to = reinterpret_cast<double2 *>(&g_tables);
+        for (int k = threadIdx.x; k < (int)(sizeof(StepTables) / sizeof(double2)); k += blockDim.x) to[k] = from[k];
         __syncthreads();
     }
     // one 32-bit word -> (0,1): (w + 1/2) 2^-32, exact in double (an add of an
@@ -91,7 +96,7 @@ struct P64 {
     // every call site passes x in (0, 1] (uniform variates and their products)
     static __device__ __forceinline__ double ln(double x) { return ln_pos(x); }
     // the same from the block's table (step kernels, after prepare_ln)
-    static __device__ __forceinline__ double ln_fast(double x) { return ln_tab(x, g_ln_tab); }
+    static __device__ __forceinline__ double ln_fast(double x) { return ln_tab(x, g_tables.ln); }
     // x >= 0 and zero or normal at every call site: the reciprocal square
     // root seed refined by two coupled Newton (Goldschmidt) iterations for
     // y = sqrt(x), h = 1/(2 sqrt(x)), then one residual correction
@@ -111,11 +116,16 @@ struct P64 {
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
     // every call site passes a positive ratio (the Einstein-model inverse,
     // called in the step kernels only, after prepare_ln)
-    static __device__ __forceinline__ double log1p_(double x) { return ln1p_tab(x, g_ln_tab); }
+    static __device__ __forceinline__ double log1p_(double x) { return ln1p_tab(x, g_tables.ln); }
     // sin(2 pi u), cos(2 pi u) of uniform variates u in (0, 1): a quarter-turn
     // reduction and two short series instead of the library's general reduction
     static __device__ __forceinline__ void sc2pi(double u, double *s, double *c) { sincos_turn(u, s, c); }
     static __device__ __forceinline__ double cos2pi(double u) { return cos_turn(u); }
+    // the same from the block's turn table (step kernels, after prepare_tables)
+    static __device__ __forceinline__ void sc2pi_fast(double u, double *s, double *c) {
+        sincos_turn_tab(u, g_tables.turn, s, c);
+    }
+    static __device__ __forceinline__ double cos2pi_fast(double u) { return cos_turn_tab(u, g_tables.turn); }
 };
 
 // FP32 form: the hardware transcendental instructions (v_log_f32 = log2,
@@ -127,7 +137,7 @@ struct P32 {
     static __device__ __forceinline__ float u01(uint32_t w) {
         return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-25f);  // exact
     }
-    static __device__ __forceinline__ void prepare_ln(const LnEntry *) {}
+    static __device__ __forceinline__ void prepare_tables(const StepTables *) {}
     static __device__ __forceinline__ float ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
     static __device__ __forceinline__ float ln_fast(float x) { return ln(x); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -139,6 +149,8 @@ struct P32 {
         *c = __builtin_amdgcn_cosf(u);
     }
     static __device__ __forceinline__ float cos2pi(float u) { return __builtin_amdgcn_cosf(u); }
+    static __device__ __forceinline__ void sc2pi_fast(float u, float *s, float *c) { sc2pi(u, s, c); }
+    static __device__ __forceinline__ float cos2pi_fast(float u) { return cos2pi(u); }
 };
 
 // Error-free sum a + b = s + e (Knuth), for two-float accumulation.

@@ -199,7 +199,7 @@ struct StepArgs {
     int32_t langevin_on;
     double lv_z_lo, lv_z_hi, lv_switch, lv_dt_ref;  // switch: lambda lv_dt_ref >= lv_switch
     uint32_t k0, k1;
-    const LnEntry *ln_tab;  // FP64 logarithm table (kLnBins entries, device memory)
+    const StepTables *tables;  // the FP64 step's logarithm and turn tables (device memory)
 };
 
 // Total field of Eq. 4 at (x, y, z), radial part projected by Eq. 3.
@@ -411,8 +411,8 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     const T r0 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w0)));
                     const T r1 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w2)));
                     T s0, c0;
-                    P::sc2pi(P::u01(w.w1), &s0, &c0);
-                    const T c1 = P::cos2pi(P::u01(w.w3));
+                    P::sc2pi_fast(P::u01(w.w1), &s0, &c0);
+                    const T c1 = P::cos2pi_fast(P::u01(w.w3));
                     const T ktm = P::div((T)kB * tg, m);  // kB T / m (no underflow in FP32)
                     const T gam = (T)(16.0 / 3.0) * ngs * P::sqrt_(fm * ktm * (T)0.15915494309189535);
                     const T f = P::exp_(-gam * dt);
@@ -441,13 +441,13 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     // partner thermal velocity: E = |w|^2/(2 a^2) ~ Gamma(3/2) (Maxwellian branch)
                     // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
                     const bool maxw = P::u01(wa.w1) * (sv + abar) < sv;  // u < s/(s + abar)
-                    const T cc = P::cos2pi(P::u01(wb.w0));
+                    const T cc = P::cos2pi_fast(P::u01(wb.w0));
                     const T en = -P::ln_fast(P::u01(wa.w2)) - P::ln_fast(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
                     const T wn = ag * P::sqrt_((T)2 * en);
                     const T ct = (T)2 * P::u01(wb.w1) - (T)1;
                     const T st = P::sqrt_(fmax((T)0, (T)1 - ct * ct));
                     T sph, cph;
-                    P::sc2pi(P::u01(wb.w2), &sph, &cph);
+                    P::sc2pi_fast(P::u01(wb.w2), &sph, &cph);
                     const T wx = wn * st * cph, wy = wn * st * sph, wz = wn * ct;
                     const T gx = rx - wx, gy = ry - wy, gz = rz - wz;
                     const T g2 = gx * gx + gy * gy + gz * gz;
@@ -477,7 +477,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     const T cchi = (T)2 * P::u01(wc.w0) - (T)1;
                     const T schi = P::sqrt_(fmax((T)0, (T)1 - cchi * cchi));
                     T sps, cps;
-                    P::sc2pi(P::u01(wc.w1), &sps, &cps);
+                    P::sc2pi_fast(P::u01(wc.w1), &sps, &cps);
                     const T f = fm * P::sqrt_(etp * two_mu);
                     vx = vcx + f * schi * cps;
                     vy = vcy + f * schi * sps;
@@ -537,7 +537,8 @@ __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount
 
 // Waves per SIMD the step kernel is compiled for (its register budget):
 // the FP64 form holds its loop state in register pairs and runs three waves
-// in 161 registers (measured 3 % faster than two); the FP32 form with BF16
+// in 143 registers (three measured 3 % faster than two and 2 % faster than
+// four, which spill); the FP32 form with BF16
 // tables fits five.  Neither spills.
 template <class P, class Tab>
 constexpr int step_waves() {
@@ -546,7 +547,7 @@ constexpr int step_waves() {
 
 template <class P, class Tab>
 __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
-    P::prepare_ln(a.ln_tab);
+    P::prepare_tables(a.tables);
     StepCount n{0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
     flush_counts(a.t, n);
@@ -650,7 +651,7 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(cons
                                                     int32_t nq) {
     const int q = block_query(prefix, nq);
     const StepArgs<P, Tab> &a = descs[q];
-    P::prepare_ln(a.ln_tab);
+    P::prepare_tables(a.tables);
     StepCount n{0, 0, 0, 0, 0, 0};
     // the random key is the query's, the same for the whole block: scalar
     step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n,

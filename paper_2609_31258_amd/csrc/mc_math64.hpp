@@ -7,15 +7,18 @@
 // candidate, three or four logarithms of uniform variates or their products
 // in (0, 1], two sine/cosine pairs and a cosine of 2 pi u for uniform u, and
 // (in the internal-energy exchange) a log1p of a positive ratio.  These
-// restricted versions stay within 2 ulp there (tested on the host against
-// extended-precision references) in a fifth to a half of the instructions.
+// restricted versions stay within 2 ulp there (the table-driven sine and
+// cosine 2.5; tested on the host against extended-precision references) in
+// a fifth to a half of the instructions.
 //
 //   div_mid(n, d)        n / d for d in [1, 4), |n| < 1 (its quotient step)
 //   ln_pos(x)            natural logarithm, x > 0 normal and finite (series)
 //   ln_tab(x, tab)       the same from a 256-bin table (ln_table_fill)
 //   ln1p_tab(x, tab)     ln(1 + x), x >= 0 (+inf gives +inf), from the table
-//   sincos_turn(u, s, c) sin(2 pi u), cos(2 pi u), 0 <= u <= 1
+//   sincos_turn(u, s, c) sin(2 pi u), cos(2 pi u), 0 <= u <= 1 (series)
 //   cos_turn(u)          cos(2 pi u), 0 <= u <= 1
+//   sincos_turn_tab, cos_turn_tab   the same from a 256-node table
+//                        (turn_table_fill)
 //
 // Plain C++ (host and device).
 #pragma once
@@ -211,6 +214,68 @@ MC_HD double cos_turn(double u) {
     double s, c;
     sincos_turn(u, &s, &c);
     return c;
+}
+
+// Table-driven sine and cosine of a turn (the step's collision loop, where
+// the table sits in LDS).  Node j = rint(256 u) (mod 256) holds sin and cos of
+// 2 pi j / 256 (exact zeros and units at the quarter turns); t = u - j/256 is
+// exact and |t| <= 1/512, so d = 2 pi t is at most pi/256 and
+// sin(2 pi u) = S_j + S_j (cos d - 1) + C_j sin d and
+// cos(2 pi u) = C_j + C_j (cos d - 1) - S_j sin d, with sin d through d^7/7!
+// and cos d - 1 through d^6/6! (next terms below 2^-60 of the result).
+struct TurnEntry {
+    double s, c;
+};
+constexpr int kTurnBins = 256;
+
+MC_H void turn_table_fill(TurnEntry *tab) {
+    const long double two_pi = 6.28318530717958647692528676655900577L;
+    for (int j = 0; j < kTurnBins; ++j) {
+        tab[j].s = (double)sinl(two_pi * j / kTurnBins);
+        tab[j].c = (double)cosl(two_pi * j / kTurnBins);
+    }
+    tab[0].s = tab[kTurnBins / 2].s = 0.0;  // exact at the quarter turns
+    tab[kTurnBins / 4].c = tab[3 * kTurnBins / 4].c = 0.0;
+    tab[0].c = tab[kTurnBins / 4].s = 1.0;
+    tab[kTurnBins / 2].c = tab[3 * kTurnBins / 4].s = -1.0;
+}
+
+MC_HD void sincos_turn_tab(double u, const TurnEntry *tab, double *sn, double *cs) {
+    const double q = std::rint(u * (double)kTurnBins);
+    const double t = std::fma(q, -1.0 / kTurnBins, u);
+    const double two_pi_hi = 6.283185307179586;       // 2 pi rounded to double
+    const double two_pi_lo = 2.4492935982947064e-16;  // 2 pi - two_pi_hi
+    const double d = std::fma(t, two_pi_hi, t * two_pi_lo);
+    const double z = d * d;
+    double ps = -1.0 / 5040.0;
+    ps = std::fma(ps, z, 1.0 / 120.0);
+    ps = std::fma(ps, z, -1.0 / 6.0);
+    const double sd = std::fma(d * z, ps, d);
+    double pc = -1.0 / 720.0;
+    pc = std::fma(pc, z, 1.0 / 24.0);
+    pc = std::fma(pc, z, -0.5);
+    const double cm1 = z * pc;  // cos d - 1
+    const TurnEntry en = tab[(int)q & (kTurnBins - 1)];
+    // the node's value plus the small corrections, added last
+    *sn = en.s + std::fma(en.s, cm1, en.c * sd);
+    *cs = en.c + std::fma(en.c, cm1, -(en.s * sd));
+}
+
+MC_HD double cos_turn_tab(double u, const TurnEntry *tab) {
+    double s, c;
+    sincos_turn_tab(u, tab, &s, &c);
+    return c;
+}
+
+// Both tables of the FP64 step (8 KB), filled on the host.
+struct StepTables {
+    LnEntry ln[kLnBins];
+    TurnEntry turn[kTurnBins];
+};
+
+MC_H void step_tables_fill(StepTables *t) {
+    ln_table_fill(t->ln);
+    turn_table_fill(t->turn);
 }
 
 }  // namespace mc

@@ -50,7 +50,7 @@ struct mc_ctx {
     double dr = 0, dz = 0, inv_dr = 0, inv_dz = 0, R = 0;
 
     double2 *e_dc = nullptr, *e_off = nullptr, *e_rf = nullptr, *e_sc = nullptr;
-    LnEntry *ln_tab = nullptr;  // the FP64 step's logarithm table
+    StepTables *tables = nullptr;  // the FP64 step's logarithm and turn tables
     double *phi_sc = nullptr;
     void *etab = nullptr, *gtab = nullptr;
     float esc[4] = {1, 1, 1, 1}, gsc[4] = {1, 1, 1, 1};
@@ -306,7 +306,7 @@ static StepArgs<P, Tab> step_args(mc_ctx *ctx, PackPtrs<typename P::T> p, double
     a.hit = ctx->hit;
     a.sp = ctx->sp_dev;
     a.t = tally_ptrs(ctx);
-    a.ln_tab = ctx->ln_tab;
+    a.tables = ctx->tables;
     a.n_slots = ctx->n_slots;
     a.step = ctx->step;
     const mc_operating &op = ctx->op;
@@ -660,13 +660,13 @@ int32_t mc_create(const mc_options *o, mc_ctx **out) {
     if (!rc) rc = dalloc_t(ctx, &ctx->sample_count, 1);
     if (!rc && hipMemsetAsync(ctx->sample_count, 0, sizeof(unsigned long long), ctx->stream) != hipSuccess)
         rc = fail(ctx, MC_EDEVICE, "clearing the sample counter");
-    if (!rc) rc = dalloc_t(ctx, &ctx->ln_tab, kLnBins);
+    if (!rc) rc = dalloc_t(ctx, &ctx->tables, 1);
     if (!rc) {
-        LnEntry host[kLnBins];
-        ln_table_fill(host);
-        if (hipMemcpyAsync(ctx->ln_tab, host, sizeof(host), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        StepTables host;
+        step_tables_fill(&host);
+        if (hipMemcpyAsync(ctx->tables, &host, sizeof(host), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
             hipStreamSynchronize(ctx->stream) != hipSuccess)
-            rc = fail(ctx, MC_EDEVICE, "uploading the logarithm table");
+            rc = fail(ctx, MC_EDEVICE, "uploading the step tables");
     }
     if (rc) {
         std::string msg = ctx->err;

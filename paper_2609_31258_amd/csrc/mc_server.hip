@@ -82,7 +82,7 @@ struct mc_server {
     void *gtab = nullptr;
     float gsc[4] = {1, 1, 1, 1}, esc[4] = {1, 1, 1, 1};
     uint8_t *hit = nullptr;
-    LnEntry *ln_tab = nullptr;  // the FP64 step's logarithm table
+    StepTables *tables = nullptr;  // the FP64 step's logarithm and turn tables
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
     Bluestein blu;
     PoissonGrid pg;
@@ -401,7 +401,7 @@ static StepArgs<P, Tab> query_step_args(mc_server *S, Query &Q, double t0, doubl
     a.hit = S->hit;
     a.sp = Q.sp_dev;
     a.t = Q.tp;
-    a.ln_tab = S->ln_tab;
+    a.tables = S->tables;
     a.n_slots = Q.n_slots;
     a.step = Q.step;
     const mc_operating &op = Q.q.op;
@@ -840,7 +840,7 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
     if (!rc) rc = salloc_t(S, &S->tcp, (int64_t)nu * m);
     if (!rc) rc = salloc_t(S, &S->tinv, (int64_t)nu * m);
     if (!rc) rc = salloc_t(S, &tmp, 4 * nn);
-    if (!rc) rc = salloc_t(S, &S->ln_tab, kLnBins);
+    if (!rc) rc = salloc_t(S, &S->tables, 1);
     if (rc) return bail(rc);
     for (auto &a : S->allocs) S->shared_bytes += (int64_t)a.second;
 #define SC2(expr) do { if ((expr) != hipSuccess) return bail(sfail(S, MC_EDEVICE, #expr)); } while (0)
@@ -872,9 +872,9 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
         k_gas<float4><<<blocks_for(nn), kBlk, 0, S->stream>>>((float4 *)S->gtab, tmp, tmp + nn, tmp + 2 * nn,
                                                                tmp + 3 * nn, nn, 1, 1, 1, 1);
     if (!S->bf16()) std::fill(S->gsc, S->gsc + 4, 1.0f);
-    LnEntry ln_host[kLnBins];
-    ln_table_fill(ln_host);
-    SC2(hipMemcpyAsync(S->ln_tab, ln_host, sizeof(ln_host), hipMemcpyHostToDevice, S->stream));
+    StepTables tables_host;
+    step_tables_fill(&tables_host);
+    SC2(hipMemcpyAsync(S->tables, &tables_host, sizeof(tables_host), hipMemcpyHostToDevice, S->stream));
     if (t->mask) SC2(hipMemcpyAsync(mask, t->mask, nn, hipMemcpyHostToDevice, S->stream));
     else SC2(hipMemsetAsync(mask, 0, nn, S->stream));
     const double reach = o->d_hit + 0.5 * std::min(g->dr, g->dz);

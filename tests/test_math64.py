@@ -1,7 +1,7 @@
 """The restricted FP64 elementary functions of the step kernel
 (mc_math64.hpp), compiled on the host with g++ and checked against
-extended-precision (x87 long double) references: each within 2 ulp over the
-arguments the step takes -- uniform variates (w + 1/2) 2^-32 and their
+extended-precision (x87 long double) references: each within 2 ulp (the
+table-driven sine and cosine 2.5) over the arguments the step takes -- uniform variates (w + 1/2) 2^-32 and their
 products for the logarithms (series and table-driven, the latter also at both
 ends and the centre of every bin), positive ratios over the whole double
 range for log1p, uniform turns for the sine and cosine -- and at the ends of
@@ -25,8 +25,10 @@ static long double two_pi_l() { return 2.0L * 3.14159265358979323846264338327950
 int main() {
     mc::LnEntry tab[mc::kLnBins];
     mc::ln_table_fill(tab);
+    mc::TurnEntry ttab[mc::kTurnBins];
+    mc::turn_table_fill(ttab);
     std::mt19937_64 rng(3);
-    double w_ln = 0, w_lnt = 0, w_ln1p = 0, w_sin = 0, w_cos = 0, w_sin2 = 0, w_cos2 = 0;
+    double w_ln = 0, w_lnt = 0, w_ln1p = 0, w_sin = 0, w_cos = 0, w_sin2 = 0, w_cos2 = 0, w_st = 0, w_ct = 0;
     for (long k = 0; k < 2000000; ++k) {
         const double u = ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
         const double v = ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
@@ -61,6 +63,11 @@ int main() {
         const long double rc = kq == 0 ? ct : kq == 1 ? -st : kq == 2 ? -ct : st;
         w_sin = std::fmax(w_sin, ulps(s, rs));
         w_cos = std::fmax(w_cos, ulps(c, rc));
+        double st2, ct2;
+        mc::sincos_turn_tab(u, ttab, &st2, &ct2);
+        w_st = std::fmax(w_st, ulps(st2, rs));
+        w_ct = std::fmax(w_ct, ulps(ct2, rc));
+        if (mc::cos_turn_tab(u, ttab) != ct2) { std::puts("FAIL cos_turn_tab differs from sincos_turn_tab"); return 1; }
         if (mc::cos_turn(u) != c) { std::puts("FAIL cos_turn differs from sincos_turn"); return 1; }
         const long double ds = sinl(two_pi_l() * u), dc = cosl(two_pi_l() * u);
         if (fabsl(ds) > 0.01L) w_sin2 = std::fmax(w_sin2, ulps(s, ds));
@@ -89,11 +96,17 @@ int main() {
         double s, c;
         mc::sincos_turn(turns[i], &s, &c);
         if (s != want_s[i] || c != want_c[i]) { std::printf("FAIL turn %g: %g %g\n", turns[i], s, c); return 1; }
+        mc::sincos_turn_tab(turns[i], ttab, &s, &c);
+        if (s != want_s[i] || c != want_c[i]) { std::printf("FAIL table turn %g: %g %g\n", turns[i], s, c); return 1; }
     }
+    // bounds: 2 ulp, and 2.5 for the table sine and cosine (the node's own
+    // rounding shows where the result is smaller than the node's value)
     const bool ok = std::fmax(std::fmax(w_ln, w_lnt), w_ln1p) <= 2.0 &&
-                    std::fmax(std::fmax(w_sin, w_cos), std::fmax(w_sin2, w_cos2)) <= 2.0;
-    std::printf("%s ln %.3f ln(table) %.3f ln1p(table) %.3f sin %.3f cos %.3f sin(unreduced) %.3f cos(unreduced) %.3f\n",
-                ok ? "OK" : "FAIL", w_ln, w_lnt, w_ln1p, w_sin, w_cos, w_sin2, w_cos2);
+                    std::fmax(std::fmax(w_sin, w_cos), std::fmax(w_sin2, w_cos2)) <= 2.0 &&
+                    std::fmax(w_st, w_ct) <= 2.5;
+    std::printf("%s ln %.3f ln(table) %.3f ln1p(table) %.3f sin %.3f cos %.3f sin(unreduced) %.3f cos(unreduced) %.3f "
+                "sin(table) %.3f cos(table) %.3f\n",
+                ok ? "OK" : "FAIL", w_ln, w_lnt, w_ln1p, w_sin, w_cos, w_sin2, w_cos2, w_st, w_ct);
     return 0;
 }
 '''
