@@ -97,21 +97,9 @@ struct P64 {
     static __device__ __forceinline__ double ln(double x) { return ln_pos(x); }
     // the same from the block's table (step kernels, after prepare_ln)
     static __device__ __forceinline__ double ln_fast(double x) { return ln_tab(x, g_tables.ln); }
-    // x >= 0 and zero or normal at every call site: the reciprocal square
-    // root seed refined by two coupled Newton (Goldschmidt) iterations for
-    // y = sqrt(x), h = 1/(2 sqrt(x)), then one residual correction
-    static __device__ __forceinline__ double sqrt_(double x) {
-        const double r = __builtin_amdgcn_rsq(x);
-        double y = x * r, h = 0.5 * r;
-        double e = fma(-y, h, 0.5);
-        y = fma(y, e, y);
-        h = fma(h, e, h);
-        e = fma(-y, h, 0.5);
-        y = fma(y, e, y);
-        h = fma(h, e, h);
-        y = fma(fma(-y, y, x), h, y);
-        return x > 0.0 ? y : 0.0;
-    }
+    // x >= 0 and zero or normal at every call site: the hardware reciprocal
+    // square root estimate (within 2^-23) refined by sqrt_seeded
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt_seeded(x, __builtin_amdgcn_rsq(x)); }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
     // every call site passes a positive ratio (the Einstein-model inverse,

@@ -12,6 +12,7 @@
 // a fifth to a half of the instructions.
 //
 //   div_mid(n, d)        n / d for d in [1, 4), |n| < 1 (its quotient step)
+//   sqrt_seeded(x, r)    sqrt x from a reciprocal-square-root estimate r
 //   ln_pos(x)            natural logarithm, x > 0 normal and finite (series)
 //   ln_tab(x, tab)       the same from a 256-bin table (ln_table_fill)
 //   ln1p_tab(x, tab)     ln(1 + x), x >= 0 (+inf gives +inf), from the table
@@ -53,6 +54,20 @@ MC_HD double div_mid(double num, double den) {
 #else
     return num / den;
 #endif
+}
+
+// sqrt x for x >= 0 (zero or normal) from an estimate r of 1/sqrt(x) with
+// relative error below 2^-20 (the hardware estimate is within 2^-23): one
+// coupled Newton step for y = sqrt(x) and h = 1/(2 sqrt(x)) (error about
+// 1.5 times the square of the estimate's), then one residual correction,
+// y + (x - y^2) h, which squares the error again below the final rounding.
+MC_HD double sqrt_seeded(double x, double r) {
+    double y = x * r, h = 0.5 * r;
+    const double e = std::fma(-y, h, 0.5);
+    y = std::fma(y, e, y);
+    h = std::fma(h, e, h);
+    y = std::fma(std::fma(-y, y, x), h, y);
+    return x > 0.0 ? y : 0.0;
 }
 
 // 2 atanh f = 2 (f + f^3/3 + f^5/5 + ...) for f = num / den, |f| <= 0.1716

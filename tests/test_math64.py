@@ -5,7 +5,8 @@ table-driven sine and cosine 2.5) over the arguments the step takes -- uniform v
 products for the logarithms (series and table-driven, the latter also at both
 ends and the centre of every bin), positive ratios over the whole double
 range for log1p, uniform turns for the sine and cosine -- and at the ends of
-each domain."""
+each domain; the seeded square root is correctly rounded from estimates eight
+times worse than the hardware's."""
 import os
 import subprocess
 
@@ -99,6 +100,16 @@ int main() {
         mc::sincos_turn_tab(turns[i], ttab, &s, &c);
         if (s != want_s[i] || c != want_c[i]) { std::printf("FAIL table turn %g: %g %g\n", turns[i], s, c); return 1; }
     }
+    // the seeded square root from estimates perturbed by up to 2^-20 (the
+    // hardware estimate is within 2^-23): correctly rounded
+    std::uniform_real_distribution<double> pert(-1.0, 1.0);
+    for (long k = 0; k < 1000000; ++k) {
+        const double m = 1.0 + ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
+        const double x = std::ldexp(m, (int)(rng() % 2000) - 1000);
+        const double r = (double)(1.0L / sqrtl((long double)x)) * (1.0 + pert(rng) * 0x1p-20);
+        if (mc::sqrt_seeded(x, r) != std::sqrt(x)) { std::printf("FAIL sqrt %.17g\n", x); return 1; }
+    }
+    if (mc::sqrt_seeded(0.0, INFINITY) != 0.0) { std::puts("FAIL sqrt 0"); return 1; }
     // bounds: 2 ulp, and 2.5 for the table sine and cosine (the node's own
     // rounding shows where the result is smaller than the node's value)
     const bool ok = std::fmax(std::fmax(w_ln, w_lnt), w_ln1p) <= 2.0 &&
