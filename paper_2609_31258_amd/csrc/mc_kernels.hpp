@@ -667,27 +667,35 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(cons
 template <class T>
 struct DepositArgs {
     PackPtrs<T> p;
-    unsigned long long *q;
-    int64_t n_slots;
+    unsigned long long *q;     // the grid (when qrep is null: the blocks' sums go here)
+    unsigned long long *qrep;  // nrep zeroed copies of the grid, or null
+    int32_t *range;            // lowest and highest node written (with qrep)
+    int64_t n_slots, nn;
     double inv_dr, inv_dz;
-    int32_t nr, nz;
+    int32_t nr, nz, nrep;
 };
 
 // Block-local aggregation: each block sums its packs' node contributions in
-// an LDS hash table (open addressing) and flushes one global atomic per
-// distinct node.  Packs concentrate in a few cells near the source, so this
-// removes almost all contention on the global grid; integer sums make the
-// result independent of the order.
+// an LDS hash table (open addressing) and flushes one device atomic per
+// distinct node.  Packs concentrate in a few cells near the source, so the
+// flush still meets the other blocks' flushes on the same few hundred
+// addresses: each block therefore flushes into one of nrep zeroed copies of
+// the grid (block b into copy b mod nrep), which cuts those same-address
+// chains nrep-fold, and k_deposit_sum adds the copies over the node range
+// the blocks wrote into the grid (and clears them for the next update).
+// Integer sums make the result independent of the order.
 constexpr int kDepHash = 2048;
-// Grid of the deposit: one block of 16 wavefronts per CU.  Every block
-// flushes one device atomic per distinct node it saw, and the packs of a step
-// crowd into a few hundred nodes, so the flush is bound by same-address
-// atomics: more blocks only add flushes, while more wavefronts per block hide
-// the latency of the pack loads and LDS atomics (measured on the 256x1024
-// workload at 1e6 packs: 0.052 ms with 256-thread blocks, 0.039 ms with
-// 1024, 0.065 ms with twice the blocks).
+// Grid of the deposit: one block of 16 wavefronts per CU, each thread
+// reading two packs per pass with their loads issued together (four spill).
 constexpr int64_t kDepositBlocks = 256;
-constexpr int kDepositThreads = 1024;
+constexpr int kDepositThreads = 1024, kDepositUnroll = 2;
+// Copies of the grid for the flush: 16, fewer on grids where 16 copies would
+// pass 64 MiB.
+constexpr int64_t kDepositRepBytes = 64ll << 20;
+inline int32_t deposit_copies(int64_t nn) {
+    const int64_t r = kDepositRepBytes / (8 * nn);
+    return (int32_t)(r >= 16 ? 16 : r < 1 ? 1 : r);
+}
 
 __device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
                                            int32_t node, int64_t v) {
@@ -701,52 +709,128 @@ __device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *va
         }
         h = (h + 1) & (kDepHash - 1);
     }
-    atom_add(&grid[node], v);  // table crowded: go straight to the grid
+    atom_add(&grid[node], v);  // table crowded: go straight to the grid (or its copy)
+}
+
+// One pack's four CIC quanta into the block's table; lo/hi track the nodes.
+template <class P>
+__device__ __forceinline__ void dep_pack(const DepositArgs<typename P::T> &a, int32_t *keys, unsigned long long *vals,
+                                         unsigned long long *dst, double X, double Y, double Z, int64_t Q, int32_t &lo,
+                                         int32_t &hi) {
+#pragma clang fp contract(off)
+    if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) return;
+    const double r = sqrt(X * X + Y * Y);
+    const double ur = r * a.inv_dr, uz = Z * a.inv_dz;
+    double fi = floor(ur), fj = floor(uz);
+    if (fi > (double)(a.nr - 2)) fi = (double)(a.nr - 2);
+    if (fj > (double)(a.nz - 2)) fj = (double)(a.nz - 2);
+    if (fj < 0.0) fj = 0.0;
+    double f = ur - fi, g = uz - fj;
+    if (f > 1.0) f = 1.0;
+    if (g > 1.0) g = 1.0;
+    if (g < 0.0) g = 0.0;
+    const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
+    const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
+    const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
+    const int32_t k = (int32_t)fj * a.nr + (int32_t)fi;
+    dep_insert(keys, vals, dst, k, a0);
+    dep_insert(keys, vals, dst, k + a.nr, a1);
+    dep_insert(keys, vals, dst, k + 1, b0);
+    dep_insert(keys, vals, dst, k + a.nr + 1, b1);
+    lo = min(lo, k);
+    hi = max(hi, k + a.nr + 1);
 }
 
 template <class P>
 __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typename P::T> a) {
+    using T = typename P::T;
     __shared__ int32_t keys[kDepHash];
     __shared__ unsigned long long vals[kDepHash];
+    __shared__ int32_t blo, bhi;
     for (int k = threadIdx.x; k < kDepHash; k += blockDim.x) {
         keys[k] = -1;
         vals[k] = 0ull;
     }
+    if (threadIdx.x == 0) {
+        blo = INT32_MAX;
+        bhi = -1;
+    }
     __syncthreads();
+    unsigned long long *dst = a.qrep ? a.qrep + (int64_t)(blockIdx.x % (unsigned)a.nrep) * a.nn : a.q;
+    int32_t lo = INT32_MAX, hi = -1;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < a.n_slots; s += stride) {
-#pragma clang fp contract(off)
-        if (a.p.status[s] != ST_ACTIVE) continue;
-        double X = a.p.x[s], Y = a.p.y[s], Z = a.p.z[s];
-        if constexpr (P::kTwo) {
-            X += (double)a.p.xl[s];
-            Y += (double)a.p.yl[s];
-            Z += (double)a.p.zl[s];
+    for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s0 < a.n_slots; s0 += kDepositUnroll * stride) {
+        // the pass's reads first (a slot past the end reads nothing), then its packs
+        int32_t st[kDepositUnroll];
+        T x[kDepositUnroll], y[kDepositUnroll], z[kDepositUnroll], xl[kDepositUnroll], yl[kDepositUnroll],
+            zl[kDepositUnroll];
+        int64_t q[kDepositUnroll];
+#pragma unroll
+        for (int u = 0; u < kDepositUnroll; ++u) {
+            const int64_t s = s0 + u * stride;
+            st[u] = -1;
+            x[u] = y[u] = z[u] = xl[u] = yl[u] = zl[u] = (T)0;
+            q[u] = 0;
+            if (s < a.n_slots) {
+                st[u] = a.p.status[s];
+                x[u] = a.p.x[s];
+                y[u] = a.p.y[s];
+                z[u] = a.p.z[s];
+                if constexpr (P::kTwo) {
+                    xl[u] = a.p.xl[s];
+                    yl[u] = a.p.yl[s];
+                    zl[u] = a.p.zl[s];
+                }
+                q[u] = a.p.q[s];
+            }
         }
-        if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) continue;
-        const double r = sqrt(X * X + Y * Y);
-        const double ur = r * a.inv_dr, uz = Z * a.inv_dz;
-        double fi = floor(ur), fj = floor(uz);
-        if (fi > (double)(a.nr - 2)) fi = (double)(a.nr - 2);
-        if (fj > (double)(a.nz - 2)) fj = (double)(a.nz - 2);
-        if (fj < 0.0) fj = 0.0;
-        double f = ur - fi, g = uz - fj;
-        if (f > 1.0) f = 1.0;
-        if (g > 1.0) g = 1.0;
-        if (g < 0.0) g = 0.0;
-        const int64_t Q = a.p.q[s];
-        const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
-        const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
-        const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
-        const int32_t k = (int32_t)fj * a.nr + (int32_t)fi;
-        dep_insert(keys, vals, a.q, k, a0);
-        dep_insert(keys, vals, a.q, k + a.nr, a1);
-        dep_insert(keys, vals, a.q, k + 1, b0);
-        dep_insert(keys, vals, a.q, k + a.nr + 1, b1);
+#pragma unroll
+        for (int u = 0; u < kDepositUnroll; ++u) {
+            if (st[u] != ST_ACTIVE) continue;
+            double X = x[u], Y = y[u], Z = z[u];
+            if constexpr (P::kTwo) {
+                X += (double)xl[u];
+                Y += (double)yl[u];
+                Z += (double)zl[u];
+            }
+            dep_pack<P>(a, keys, vals, dst, X, Y, Z, q[u], lo, hi);
+        }
+    }
+    if (a.range && hi >= 0) {
+        atomicMin(&blo, lo);
+        atomicMax(&bhi, hi);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kDepHash; k += blockDim.x)
-        if (keys[k] >= 0 && vals[k] != 0ull) atomicAdd(&a.q[keys[k]], vals[k]);
+        if (keys[k] >= 0 && vals[k] != 0ull) atomicAdd(&dst[keys[k]], vals[k]);
+    if (a.range && threadIdx.x == 0 && bhi >= 0) {
+        atomicMin(&a.range[0], blo);
+        atomicMax(&a.range[1], bhi);
+    }
+}
+
+// The grid from the copies: q[n] = sum of the copies' values at n for n in
+// the range the deposit wrote (the copies are cleared there), 0 elsewhere;
+// node 0's thread also resets the other range slot, next_range, for the
+// next update (range and next_range alternate between updates).
+static __global__ __launch_bounds__(256) void k_deposit_sum(unsigned long long *q, unsigned long long *qrep,
+                                                            int32_t nrep, int64_t nn, const int32_t *range,
+                                                            int32_t *next_range) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn) return;
+    unsigned long long v = 0ull;
+    if (n >= range[0] && n <= range[1]) {
+        for (int32_t c = 0; c < nrep; ++c) {
+            unsigned long long *cell = qrep + (int64_t)c * nn + n;
+            v += *cell;
+            *cell = 0ull;
+        }
+    }
+    q[n] = v;
+    if (n == 0) {
+        next_range[0] = INT32_MAX;
+        next_range[1] = -1;
+    }
 }
 
 // E = -grad(phi) on nodes: central differences, one-sided at the outer

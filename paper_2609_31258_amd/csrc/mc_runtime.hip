@@ -57,6 +57,9 @@ struct mc_ctx {
     uint8_t *mask = nullptr, *hit = nullptr;
 
     unsigned long long *qgrid = nullptr;
+    unsigned long long *qrep = nullptr;  // the deposit's copies of the grid (nrep of them, kept zeroed)
+    int32_t nrep = 1, dep_parity = 0;
+    int32_t *dep_range = nullptr;        // two (lowest, highest) node slots, alternating by update
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
     void *bh = nullptr;
     Bluestein blu;
@@ -447,22 +450,29 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     const int64_t nn = (int64_t)ctx->nr * ctx->nz;
     {
         Timer t(ctx, MC_K_DEPOSIT);
-        k_zero_u64<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->qgrid, nn);
-        LAUNCHCHK();
+        int32_t *range = ctx->dep_range + 2 * ctx->dep_parity, *next = ctx->dep_range + 2 * (1 - ctx->dep_parity);
         if (ctx->n_slots > 0) {
             DepositArgs<typename P::T> a{};
             a.p = p;
             a.q = ctx->qgrid;
+            a.qrep = ctx->qrep;
+            a.range = range;
             a.n_slots = ctx->n_slots;
+            a.nn = nn;
             a.inv_dr = ctx->inv_dr;
             a.inv_dz = ctx->inv_dz;
             a.nr = ctx->nr;
             a.nz = ctx->nz;
+            a.nrep = ctx->nrep;
             const unsigned nb = (unsigned)std::min<int64_t>((ctx->n_slots + kDepositThreads - 1) / kDepositThreads,
                                                             kDepositBlocks);
             k_deposit<P><<<nb, kDepositThreads, 0, ctx->stream>>>(a);
             LAUNCHCHK();
         }
+        // the grid from the copies (every node written: no separate clear)
+        k_deposit_sum<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->qgrid, ctx->qrep, ctx->nrep, nn, range, next);
+        LAUNCHCHK();
+        ctx->dep_parity = 1 - ctx->dep_parity;
     }
     if (ctx->op.sc_mask && !ctx->mcap.ready) {
         const int32_t rc = mask_setup(ctx);
@@ -727,6 +737,9 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     if (!rc) rc = dalloc_t(ctx, &ctx->mask, nn);
     if (!rc) rc = dalloc_t(ctx, &ctx->hit, nn);
     if (!rc) rc = dalloc_t(ctx, &ctx->qgrid, nn);
+    ctx->nrep = deposit_copies(nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->qrep, (size_t)ctx->nrep * nn);
+    if (!rc) rc = dalloc_t(ctx, &ctx->dep_range, 4);
     if (!rc) rc = dalloc_t(ctx, &ctx->sine, 2 * (int64_t)(g->nz - 1));
     if (!rc) rc = dalloc_t(ctx, &ctx->tcp, (int64_t)nu * m);
     if (!rc) rc = dalloc_t(ctx, &ctx->tinv, (int64_t)nu * m);
@@ -742,6 +755,12 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     HIPCHK(hipMemsetAsync(ctx->e_off, 0, nn * sizeof(double2), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->e_rf, 0, nn * sizeof(double2), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->qgrid, 0, nn * sizeof(unsigned long long), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->qrep, 0, (size_t)ctx->nrep * nn * sizeof(unsigned long long), ctx->stream));
+    {
+        static const int32_t empty[4] = {INT32_MAX, -1, INT32_MAX, -1};
+        HIPCHK(hipMemcpyAsync(ctx->dep_range, empty, sizeof(empty), hipMemcpyHostToDevice, ctx->stream));
+        ctx->dep_parity = 0;
+    }
     // bake E = -grad(phi) for the three potentials
     const double *phis[3] = {t->phi_dc, t->phi_off, t->phi_rf};
     double2 *outs[3] = {ctx->e_dc, ctx->e_off, ctx->e_rf};
