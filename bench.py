@@ -63,8 +63,9 @@ OPS_EXCHANGE = 18         # internal-energy exchange (taken with probability alp
 BYTES_STEP = {"fp64": 144, "fp32": 112}
 # Deposit: status, position (FP64, or the FP32 form's hi+lo pairs) and the
 # int64 charge of every active pack (the LDS-aggregated grid atomics are
-# counted as L2 traffic, not HBM).
+# counted as L2 traffic, not HBM), plus one write of the int64 grid.
 BYTES_DEPOSIT = {"fp64": 36, "fp32": 36}
+GRID_BYTES = 256 * 1024 * 8
 HBM_PEAK = 8.0e12
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_c2_traffic.txt")
@@ -210,11 +211,11 @@ def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
         idle = max(r["slots"] * r["steps"] - r["pack_steps"], 0)
         nbytes = (r["pack_steps"] * BYTES_STEP[precision] + 4 * idle) / launches
     else:
-        nbytes = r["active"] * BYTES_DEPOSIT[precision]  # population is nearly constant in the window
+        nbytes = r["active"] * BYTES_DEPOSIT[precision] + GRID_BYTES  # population nearly constant in the window
     achieved = nbytes / avg_s if avg_s > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "kernel": kernel, "avg_launch_ms": avg_s * 1e3,
+            "kernel": "deposit (k_deposit + k_deposit_sum)" if kernel == "deposit" else kernel, "avg_launch_ms": avg_s * 1e3,
             "launches": launches, "bytes_per_launch": nbytes,
             "issue": measured_issue(traffic_key) if kernel == "step" and traffic_key else None}
 
