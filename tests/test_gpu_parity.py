@@ -187,6 +187,19 @@ def test_pic_update_bit_exact_deposit_and_poisson():
     assert np.abs(pa - pb).max() <= 1e-10 * scale
     es = max(np.abs(erb).max(), np.abs(ezb).max())
     assert np.abs(era - erb).max() <= 1e-8 * es and np.abs(eza - ezb).max() <= 1e-8 * es
+    # two more updates with the packs elsewhere: each grid is the new packs'
+    # charge alone (nothing of an earlier update is left behind)
+    for seed, z_lo, z_hi in ((22, 0.5, 0.8), (23, 0.0, 0.1)):
+        snap2 = synth.pack_snapshot(n, f, seed=seed, z_lo=f.grid.L * z_lo, z_hi=f.grid.L * z_hi, r_hi=1.5e-3,
+                                    weight=0.012483)
+        snap2 = {k: np.concatenate([snap2[k], edge[k]]) for k in snap2}
+        g.write_packs(snap2)
+        o.write_packs(snap2)
+        g.pic_update()
+        o.pic_update()
+        qa, qb = g.read_charge(), o.read_charge()
+        assert np.array_equal(qa, qb), seed
+        assert qa.sum() == by_id(o.read_packs())["q"].sum()
     g.close()
 
 
