@@ -1,5 +1,6 @@
 // mc_math64.hpp -- double-precision elementary functions for the arguments
-// the FP64 step takes, written from their series.
+// the FP64 step takes, written from their series, with and without small
+// tables (the step keeps its tables in LDS).
 //
 // The general library functions handle every input (denormals, infinities,
 // NaN, arguments of any size) and cost about 100 (logarithm), 130 (log1p) and
