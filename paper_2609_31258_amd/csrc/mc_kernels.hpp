@@ -675,11 +675,13 @@ struct DepositArgs {
     int32_t nr, nz, nrep;
 };
 
-// Block-local aggregation: each block sums its packs' node contributions in
-// an LDS hash table (open addressing) and flushes one device atomic per
-// distinct node.  Packs concentrate in a few cells near the source, so the
-// flush still meets the other blocks' flushes on the same few hundred
-// addresses: each block therefore flushes into one of nrep zeroed copies of
+// Block-local aggregation: each block sums its packs' contributions in an
+// LDS hash table (open addressing) keyed by the CIC cell, i.e. the cell's
+// lower-left node: one compare-and-swap per pack, its four quanta added to
+// the entry's four slots (lower-left, upper-left, lower-right, upper-right),
+// and one device atomic per nonzero slot at the flush.  Packs concentrate in
+// a few cells near the source, so the flush still meets the other blocks'
+// flushes on the same few hundred addresses: each block therefore flushes into one of nrep zeroed copies of
 // the grid (block b into copy b mod nrep), which cuts those same-address
 // chains nrep-fold, and k_deposit_sum adds the copies over the node range
 // the blocks wrote into the grid (and clears them for the next update).
@@ -692,24 +694,32 @@ constexpr int kDepositThreads = 1024, kDepositUnroll = 2;
 // Copies of the grid for the flush: 16, fewer on grids where 16 copies would
 // pass 64 MiB.
 constexpr int64_t kDepositRepBytes = 64ll << 20;
+constexpr int32_t kDepositMaxCopies = 16;
 inline int32_t deposit_copies(int64_t nn) {
     const int64_t r = kDepositRepBytes / (8 * nn);
-    return (int32_t)(r >= 16 ? 16 : r < 1 ? 1 : r);
+    return (int32_t)(r >= kDepositMaxCopies ? kDepositMaxCopies : r < 1 ? 1 : r);
 }
 
-__device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
-                                           int32_t node, int64_t v) {
-    if (v == 0) return;
-    uint32_t h = ((uint32_t)node * 2654435761u) >> (32 - 11);
+__device__ __forceinline__ void dep_cell(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
+                                         int32_t k, int32_t nr, int64_t a0, int64_t a1, int64_t b0, int64_t b1) {
+    uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - 11);
     for (int probe = 0; probe < 8; ++probe) {
-        const int32_t old = atomicCAS(&keys[h], -1, node);
-        if (old == -1 || old == node) {
-            atomicAdd(&vals[h], (unsigned long long)v);
+        const int32_t old = atomicCAS(&keys[h], -1, k);
+        if (old == -1 || old == k) {
+            unsigned long long *v = vals + 4 * h;
+            if (a0) atomicAdd(&v[0], (unsigned long long)a0);
+            if (a1) atomicAdd(&v[1], (unsigned long long)a1);
+            if (b0) atomicAdd(&v[2], (unsigned long long)b0);
+            if (b1) atomicAdd(&v[3], (unsigned long long)b1);
             return;
         }
         h = (h + 1) & (kDepHash - 1);
     }
-    atom_add(&grid[node], v);  // table crowded: go straight to the grid (or its copy)
+    // table crowded: go straight to the grid (or its copy)
+    if (a0) atom_add(&grid[k], a0);
+    if (a1) atom_add(&grid[k + nr], a1);
+    if (b0) atom_add(&grid[k + 1], b0);
+    if (b1) atom_add(&grid[k + nr + 1], b1);
 }
 
 // One pack's four CIC quanta into the block's table; lo/hi track the nodes.
@@ -733,10 +743,7 @@ __device__ __forceinline__ void dep_pack(const DepositArgs<typename P::T> &a, in
     const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
     const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
     const int32_t k = (int32_t)fj * a.nr + (int32_t)fi;
-    dep_insert(keys, vals, dst, k, a0);
-    dep_insert(keys, vals, dst, k + a.nr, a1);
-    dep_insert(keys, vals, dst, k + 1, b0);
-    dep_insert(keys, vals, dst, k + a.nr + 1, b1);
+    dep_cell(keys, vals, dst, k, a.nr, a0, a1, b0, b1);
     lo = min(lo, k);
     hi = max(hi, k + a.nr + 1);
 }
@@ -745,11 +752,11 @@ template <class P>
 __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typename P::T> a) {
     using T = typename P::T;
     __shared__ int32_t keys[kDepHash];
-    __shared__ unsigned long long vals[kDepHash];
+    __shared__ unsigned long long vals[4 * kDepHash];
     __shared__ int32_t blo, bhi;
     for (int k = threadIdx.x; k < kDepHash; k += blockDim.x) {
         keys[k] = -1;
-        vals[k] = 0ull;
+        vals[4 * k] = vals[4 * k + 1] = vals[4 * k + 2] = vals[4 * k + 3] = 0ull;
     }
     if (threadIdx.x == 0) {
         blo = INT32_MAX;
@@ -802,7 +809,12 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kDepHash; k += blockDim.x)
-        if (keys[k] >= 0 && vals[k] != 0ull) atomicAdd(&dst[keys[k]], vals[k]);
+        if (keys[k] >= 0) {
+            const int64_t c = keys[k], off[4] = {0, a.nr, 1, a.nr + 1};
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (vals[4 * k + j] != 0ull) atomicAdd(&dst[c + off[j]], vals[4 * k + j]);
+        }
     if (a.range && threadIdx.x == 0 && bhi >= 0) {
         atomicMin(&a.range[0], blo);
         atomicMax(&a.range[1], bhi);
@@ -810,7 +822,8 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
 }
 
 // The grid from the copies: q[n] = sum of the copies' values at n for n in
-// the range the deposit wrote (the copies are cleared there), 0 elsewhere;
+// the range the deposit wrote (the copies are cleared there, after all of
+// the thread's loads have been issued; nrep <= kDepositMaxCopies), 0 elsewhere;
 // node 0's thread also resets the other range slot, next_range, for the
 // next update (range and next_range alternate between updates).
 static __global__ __launch_bounds__(256) void k_deposit_sum(unsigned long long *q, unsigned long long *qrep,
@@ -820,11 +833,14 @@ static __global__ __launch_bounds__(256) void k_deposit_sum(unsigned long long *
     if (n >= nn) return;
     unsigned long long v = 0ull;
     if (n >= range[0] && n <= range[1]) {
-        for (int32_t c = 0; c < nrep; ++c) {
-            unsigned long long *cell = qrep + (int64_t)c * nn + n;
-            v += *cell;
-            *cell = 0ull;
-        }
+        unsigned long long w[kDepositMaxCopies];
+#pragma unroll
+        for (int32_t c = 0; c < kDepositMaxCopies; ++c) w[c] = c < nrep ? qrep[(int64_t)c * nn + n] : 0ull;
+#pragma unroll
+        for (int32_t c = 0; c < kDepositMaxCopies; ++c) v += w[c];
+#pragma unroll
+        for (int32_t c = 0; c < kDepositMaxCopies; ++c)
+            if (c < nrep) qrep[(int64_t)c * nn + n] = 0ull;
     }
     q[n] = v;
     if (n == 0) {
