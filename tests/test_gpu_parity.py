@@ -252,6 +252,36 @@ def test_poisson_transforms_match_oracle(precision, nr, nz):
     g.close()
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,nr", [(0, 96), (1, 128), (0, 512)])
+def test_deposit_with_fewer_grid_copies(precision, nr):
+    """Grids of 0.79M, 1.05M and 4.19M nodes, on which the deposit flushes
+    into 10, 8 and 2 copies of the grid instead of 16 (the copies are capped
+    at 64 MiB): two updates over the same packs, the second on copies the
+    first cleared, each charge grid bit-exact against the oracle's deposit."""
+    n = 100_000
+    f = synth.uniform_fields(nr, 8192, 5e-5)
+    _, ions, _, op, _ = _c2_like()
+    op = synth.Operating(**{**op.__dict__, "z_det": f.grid.L, "r_det": f.grid.R, "sc_on": 1})
+    snap = synth.pack_snapshot(n, f, seed=24, z_lo=0.1 * f.grid.L, z_hi=0.7 * f.grid.L, r_hi=0.6 * f.grid.R,
+                               weight=0.01)
+    if precision == 1:
+        for k in ("x", "y", "z"):  # positions the FP32 form's float pair holds exactly
+            hi = snap[k].astype(np.float32)
+            snap[k] = hi.astype(np.float64) + (snap[k] - hi.astype(np.float64)).astype(np.float32).astype(np.float64)
+    _say("deposit with fewer grid copies", precision, f.grid.nr, f.grid.nz)
+    g, o = make_pair(f, ions, [], op, cap=n, precision=precision)
+    g.write_packs(snap)
+    o.write_packs(snap)
+    o.deposit()
+    want = o.read_charge()
+    assert want.sum() > 0
+    for _ in range(2):
+        g.pic_update()
+        assert np.array_equal(g.read_charge(), want)
+    g.close()
+
+
 def test_pic_update_empty_population():
     _say("pic update, no packs")
     f, ions, _, op, _ = _c2_like()
