@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 3
+#define MC_ABI_VERSION 4
 
 enum {
     MC_OK = 0,
@@ -104,11 +104,13 @@ typedef struct mc_field_tables {
     const uint8_t *mask;
 } mc_field_tables;
 
-/* Ion template ("An ion template specifies mass, charge state, collision
- * cross section, atom count, heat capacity profile, and optional
- * activation parameters").  Heat capacity: Einstein model, s = 3N-6
- * oscillators at theta_e.  alpha < 0 selects the default internal-exchange
- * probability 4 mg ma / (mg + ma)^2, ma = m / n_atoms. */
+/* Ion template ("Simulation scope and modular architecture": the ion is
+ * described by its mass, charge, collision cross section, atom count, heat
+ * capacity and, optionally, its activation parameters).  Heat capacity:
+ * Einstein model, s = 3N-6 oscillators at theta_e.  alpha < 0 selects the
+ * default internal-exchange probability 4 mg ma / (mg + ma)^2, ma = m /
+ * n_atoms (the head-on elastic transfer share; "Particle transport,
+ * collisions, and effective internal temperature"). */
 typedef struct mc_ion {
     double mass_da;
     int32_t charge_z;        /* non-zero */
@@ -121,8 +123,9 @@ typedef struct mc_ion {
     double act_p1, act_p2;
 } mc_ion;
 
-/* Source definition ("A separate source definition specifies current,
- * spatial profile, injection plane, and initial velocity distribution").
+/* Source definition ("Simulation scope and modular architecture" and
+ * "Continuous current Gaussian source": current, transverse profile,
+ * injection plane and initial velocities are given apart from the ion).
  * kind 0: burst, packs only via mc_inject, weight = weight;
  * kind 1: packs_per_step packs every step from step_start, weight
  *         I dt / (z e packs_per_step) so the packs carry the current;
@@ -170,8 +173,8 @@ typedef struct mc_source {
  * n % sample_every == 0 (before the space-charge update and emission), each
  * active pack whose id is a multiple of sample_stride is recorded
  * (mc_sample_rec) into the buffer sized by mc_options.sample_capacity.
- * 0 turns sampling off; both must be >= 0.  Single contexts only: the
- * serving runtime returns tallies and ignores these two fields.
+ * 0 turns sampling off; both must be >= 0.  The serving runtime takes them
+ * per query as well (see mc_query).
  *
  * adaptive: the global step of Eq. 1, dt_n = min(0.05 t_RF, 0.1 tau_coll,
  * dt_acc, dt_CFL, dt_L, dt_rem), evaluated on the device at the start of
@@ -184,7 +187,8 @@ typedef struct mc_source {
  * of simulated time, sources emit per step with that step's dt (Eq. 5), and
  * the Langevin switch always compares with dt.  The step's length costs one
  * small device-to-host read per step.  A step that collapses below 1e-9 dt
- * fails with MC_ENUMERIC.  Single contexts only (the server rejects it). */
+ * fails with MC_ENUMERIC.  The serving runtime runs it per query (see
+ * mc_query). */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
     int32_t collisions_on, sc_on, sc_every;
@@ -221,12 +225,13 @@ typedef struct mc_packs {
  * n_cand/n_coll: collision candidates and accepted collisions; n_cap: pack
  * steps that hit the candidate cap; n_clamp: internal-energy clamps;
  * pack_steps: sum over steps of the active packs advanced; n_langevin:
- * pack steps taken by the hybrid Langevin branch.
+ * pack steps taken by the hybrid Langevin branch; n_exchange: accepted
+ * collisions that exchanged energy with the internal modes.
  * sum_w_*: FP64 sums, reduced in a fixed order (run-to-run identical). */
 typedef struct mc_tallies {
     int64_t emitted_n, emitted_w;
     int64_t class_n[MC_NCLASS], class_w[MC_NCLASS];
-    int64_t n_cand, n_coll, n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, n_langevin;
+    int64_t n_cand, n_coll, n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, n_langevin, n_exchange;
     double sum_w_ke_active, sum_w_eint_active, sum_w_dissoc_terminal;
     int64_t *exit_bins, *loss_map, *hist_ke, *hist_teff, *hist_r, *act_hist_ke, *act_hist_teff;
 } mc_tallies;
@@ -263,47 +268,118 @@ typedef struct mc_timing {
 
 typedef struct mc_ctx mc_ctx;
 
+/* Buffer layout of the tallies ("Terminal events, snapshots, and reported
+ * observables"; Eq. 8 for the exit-current bins).  Filled by
+ * mc_get_tally_layout from the context's grid and operating point, so a
+ * caller can size the arrays of mc_tallies and the record buffers before
+ * reading.  Every histogram has an underflow entry (index 0) and an
+ * overflow entry (last); bin k (1 <= k <= bins) covers
+ * [lo + (k-1) w, lo + k w) with w = (hi - lo) / bins, in log10(KE / eV) for
+ * the kinetic-energy histogram and linearly for the others. */
+typedef struct mc_tally_layout {
+    int32_t n_classes;       /* MC_NCLASS: entries of class_n / class_w */
+    int32_t n_exit_bins;     /* entries of exit_bins (Eq. 8) */
+    double exit_bin_dt;      /* width of an exit-current bin [s]; bin b covers [b, b+1) exit_bin_dt */
+    int32_t nr, nz;          /* loss_map holds nz*nr int64, row-major [nz][nr] */
+    int64_t loss_map_len;
+    int32_t hist_ke_len;     /* MC_HIST_KE entries: ke_bins + 2 */
+    int32_t ke_bins;
+    double ke_log10_lo, ke_log10_hi; /* log10 of the KE range in eV */
+    int32_t hist_teff_len;   /* MC_HIST_TEFF entries: teff_bins + 2 */
+    int32_t teff_bins;
+    double teff_lo, teff_hi; /* [K] */
+    int32_t hist_r_len;      /* MC_HIST_R entries: r_bins + 2 */
+    int32_t r_bins;
+    double r_lo, r_hi;       /* exit radius range [m]: 0 .. r_det */
+    int64_t exit_capacity;   /* exit records kept (mc_read_exits) */
+    int64_t sample_capacity; /* trajectory samples kept (mc_read_samples) */
+    int64_t charge_grid_len; /* int64 entries of mc_read_charge: nz*nr */
+} mc_tally_layout;
+
+/* ABI version of the library (MC_ABI_VERSION of the header it was built from). */
 int32_t mc_abi_version(void);
 
-/* Create a context on options->device.  *out receives the handle.
+/* Create a context on options->device: the simulation of the paper's
+ * "Simulation scope and modular architecture" (one run = fields, ion
+ * templates, sources, operating point).  *out receives the handle.
  * Errors: MC_EINVAL (bad options), MC_EDEVICE. */
 int32_t mc_create(const mc_options *options, mc_ctx **out);
 /* Release all device memory and the ctx-owned stream.  NULL is a no-op. */
 void mc_destroy(mc_ctx *ctx);
+/* Message of the last failed call on ctx (ctx-owned; valid until the next call). */
 const char *mc_last_error(const mc_ctx *ctx);
 
-/* Load and bake the field tables (coordinate-system and gas sections).  May
- * be called once per ctx.  Errors: MC_EINVAL (also for a non-finite table
- * value or a negative gas pressure or temperature), MC_ESTATE, MC_ENOMEM,
- * MC_EBUDGET. */
+/* Load and bake the field tables ("Coordinate system, static fields, and RF
+ * convention", Eqs. 2-4: E = -grad(phi) on the nodes; "Gas field and
+ * electrode mask coupling": gas velocity, pressure, temperature and the
+ * electrode mask).  May be called once per ctx.  The host arrays are copied.
+ * Errors: MC_EINVAL (also for a non-finite table value or a negative gas
+ * pressure or temperature; the ctx then keeps no fields), MC_ESTATE,
+ * MC_ENOMEM, MC_EBUDGET. */
 int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *grid, const mc_field_tables *tables);
-/* Define an ion template; *ion_id receives its index (species tag of packs). */
+/* Define an ion template ("Simulation scope and modular architecture"; heat
+ * capacity and activation as in "Particle transport, collisions, and
+ * effective internal temperature" and Eq. 7); *ion_id receives its index
+ * (the species tag of its packs).  Errors: MC_EINVAL (n_atoms < 3, charge 0,
+ * mass <= 0), MC_ENOMEM (more than 64 templates). */
 int32_t mc_define_ion(mc_ctx *ctx, const mc_ion *ion, int32_t *ion_id);
-/* Set the operating point; requires fields.  Rebuilds the electrode hit table
- * and the folded static field.  Must precede mc_define_source. */
+/* Set the operating point (time step, Eq. 1 when adaptive; RF of Eq. 4;
+ * collision, Langevin and space-charge switches; detector and hit distance
+ * of "Terminal events, snapshots, and reported observables"); requires
+ * fields.  Rebuilds the electrode hit table and the folded static field.
+ * Must precede mc_define_source.  Errors: MC_EINVAL, MC_ESTATE. */
 int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op);
-/* Define a source; *src_id receives its index.  Pack ids of source s are
- * (s << 32) | k for its k-th pack; they key the random streams. */
+/* Define a source ("Continuous current Gaussian source", Eq. 5); *src_id
+ * receives its index.  Pack ids of source s are (s << 32) | k for its k-th
+ * pack; they key the random streams.  Errors: MC_EINVAL, MC_ESTATE. */
 int32_t mc_define_source(mc_ctx *ctx, const mc_source *src, int32_t *src_id);
-/* Emit n packs from source src_id now, at the current step (burst). */
+/* Emit n packs from source src_id now, at the current step (a burst; the
+ * source's transverse profile and velocities of "Continuous current
+ * Gaussian source").  Asynchronous.  Errors: MC_EINVAL, MC_ESTATE, MC_ENOMEM
+ * (pack capacity exceeded). */
 int32_t mc_inject(mc_ctx *ctx, int32_t src_id, int64_t n);
-/* Advance n_steps steps.  Each step: space-charge update when sc_on and
- * step % sc_every == 0; emission of due packs; then for every active pack
- * RK4 push, classification, collisions, dissociation. Asynchronous. */
+/* Advance n_steps steps of the operator-split cycle of "Simulation scope and
+ * modular architecture".  Each step: space-charge update when sc_on and it
+ * is due ("Axisymmetric PIC space charge update"); emission of due packs
+ * (Eq. 5); then for every active pack the RK4 push in the field of Eqs. 3-4,
+ * terminal classification ("Terminal events, snapshots, and reported
+ * observables"), collisions (Eq. 6 and the internal-energy exchange) or the
+ * hybrid Langevin relaxation, and the dissociation hazard (Eq. 7).
+ * Asynchronous with a fixed step; with the adaptive step (Eq. 1) the
+ * step lengths are found on the device and the call reads them back once,
+ * at its end.  Errors: MC_ESTATE, MC_ENOMEM (capacity), MC_ENUMERIC
+ * (adaptive step collapsed), MC_EDEVICE. */
 int32_t mc_step(mc_ctx *ctx, int64_t n_steps);
-/* Space-charge update now (deposit, Poisson, field) from the current packs. */
+/* Space-charge update now ("Axisymmetric PIC space charge update": CIC
+ * deposit, cylindrical Poisson solve, E = -grad(Phi) folded into the static
+ * field) from the current packs.  Asynchronous. */
 int32_t mc_pic_update(mc_ctx *ctx);
+/* Wait for the ctx stream. */
 int32_t mc_synchronize(mc_ctx *ctx);
+/* Step counter, simulated time, last step length, capacities and sizes. */
 int32_t mc_get_info(const mc_ctx *ctx, mc_info *info);
+/* Layout of the tally arrays and record buffers (see mc_tally_layout);
+ * requires an operating point (MC_ESTATE otherwise). */
+int32_t mc_get_tally_layout(const mc_ctx *ctx, mc_tally_layout *out);
 
+/* Reported observables ("Terminal events, snapshots, and reported
+ * observables"; exit current of Eq. 8; survival yield of Eq. 7): class
+ * counts and weights, exit-current bins, loss map, histograms, FP64 energy
+ * and survival sums; array sizes from mc_get_tally_layout.  Synchronises. */
 int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out);
-/* Copy up to cap exit records (sorted by pack id) into buf; *n receives the
- * total number recorded (may exceed cap). */
+/* Terminal events ("Terminal events, snapshots, and reported observables"):
+ * copy up to cap exit records (sorted by pack id) into buf; *n receives the
+ * total number recorded (may exceed cap).  Synchronises. */
 int32_t mc_read_exits(mc_ctx *ctx, mc_exit_rec *buf, int64_t cap, int64_t *n);
-/* Copy up to cap trajectory samples, sorted by (step, id), into buf; *n
+/* Trajectory snapshots ("Terminal events, snapshots, and reported
+ * observables"): copy up to cap samples, sorted by (step, id), into buf; *n
  * receives the number taken (may exceed the buffer: the rest were dropped). */
 int32_t mc_read_samples(mc_ctx *ctx, mc_sample_rec *buf, int64_t cap, int64_t *n);
+/* Pack population ("Simulation scope and modular architecture": the packs'
+ * state) into host arrays (see mc_packs).  Synchronises. */
 int32_t mc_read_packs(mc_ctx *ctx, mc_packs *out);
+/* Replace the pack population by n active packs (snapshot restart; see
+ * mc_packs).  Errors: MC_EINVAL (non-finite values, unknown tag), MC_ENOMEM. */
 int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in);
 /* Checkpoint and resume.  mc_save_state writes the context's dynamic state
  * (pack slots, tallies, exit records and samples taken, space-charge field,
@@ -315,12 +391,16 @@ int32_t mc_write_packs(mc_ctx *ctx, const mc_packs *in);
  * Both synchronise the stream. */
 int32_t mc_save_state(mc_ctx *ctx, const char *path);
 int32_t mc_load_state(mc_ctx *ctx, const char *path);
-/* int64 charge grid of the last deposit, nz*nr, units of 2^-32 e. */
+/* int64 charge grid of the last CIC deposit ("Axisymmetric PIC space charge
+ * update"), nz*nr, units of 2^-32 e. */
 int32_t mc_read_charge(mc_ctx *ctx, int64_t *q);
-/* Space-charge potential and field of the last update (nz*nr each; nullable). */
+/* Space-charge potential and field of the last update ("Axisymmetric PIC
+ * space charge update"; nz*nr each; each pointer nullable). */
 int32_t mc_read_sc(mc_ctx *ctx, double *phi, double *er, double *ez);
-/* Electrode hit table (nz*nr bytes). */
+/* Electrode hit table ("Gas field and electrode mask coupling": a node is a
+ * hit node when metal lies within the hit distance; nz*nr bytes). */
 int32_t mc_read_hit(mc_ctx *ctx, uint8_t *hit);
+/* Per-kernel HIP-event times (mc_options.timing) and their reset. */
 int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out);
 int32_t mc_reset_timing(mc_ctx *ctx);
 
@@ -405,19 +485,31 @@ typedef struct mc_server_stats {
 
 typedef struct mc_server mc_server;
 
+/* Create a server over one field set, baked as in mc_load_fields
+ * ("Coordinate system, static fields, and RF convention"; "Gas field and
+ * electrode mask coupling").  Each query it runs is one simulation of the
+ * method with its own operating conditions, ion and current -- the paper's
+ * simulation-guided design use ("Simulation scope and modular
+ * architecture").  Errors: MC_EINVAL, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE. */
 int32_t mc_server_create(const mc_server_options *options, const mc_grid *grid, const mc_field_tables *tables,
                          mc_server **out);
 /* Stop the worker (resident and pending queries are abandoned) and free everything. */
 void mc_server_destroy(mc_server *server);
+/* Message of the server's last failed call (server-owned). */
 const char *mc_server_last_error(const mc_server *server);
-/* Queue a query; *qid receives its id.  MC_EBUDGET if its memory exceeds the pool. */
+/* Queue a query (one run of the step of mc_step with the query's own ion,
+ * source and operating point); *qid receives its id.  Thread-safe.
+ * Errors: MC_EINVAL (invalid query), MC_EBUDGET (its memory exceeds the pool). */
 int32_t mc_server_submit(mc_server *server, const mc_query *query, uint64_t *qid);
-/* Copy the query's state and, once done, its result.  MC_EINVAL for an unknown id. */
+/* Copy the query's state and, once done, its result (the observables of
+ * mc_read_tallies plus its exit records and samples).  Thread-safe.
+ * MC_EINVAL for an unknown id. */
 int32_t mc_server_poll(mc_server *server, uint64_t qid, mc_query_result *out);
 /* Block until the query is done (or failed) or timeout_s passes, then poll. */
 int32_t mc_server_wait(mc_server *server, uint64_t qid, double timeout_s, mc_query_result *out);
 /* Forget a finished query's host result. */
 int32_t mc_server_release(mc_server *server, uint64_t qid);
+/* Admission, pool and throughput counters of the server. */
 int32_t mc_server_get_stats(mc_server *server, mc_server_stats *out);
 
 #ifdef __cplusplus

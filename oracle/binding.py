@@ -46,7 +46,7 @@ class Packs(C.Structure):
 class Tallies(C.Structure):
     _fields_ = [("emitted_n", I64), ("emitted_w", I64), ("class_n", I64 * NCLASS), ("class_w", I64 * NCLASS),
                 ("n_cand", I64), ("n_coll", I64), ("n_cap", I64), ("n_clamp", I64), ("exit_overflow", I64), ("n_langevin", I64),
-                ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
+                ("n_exchange", I64), ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
                 ("exit_bins", PI64), ("loss_map", PI64), ("hist_ke", PI64), ("hist_teff", PI64), ("hist_r", PI64),
                 ("act_hist_ke", PI64), ("act_hist_teff", PI64)]
 
@@ -85,7 +85,7 @@ def lib():
         "orc_poisson_residual": (F64, [I32, I32, F64, F64, PD, PD]),
         "orc_poisson_masked": (I32, [I32, I32, F64, F64, PD, PU8, F64, I32, PD]),
         "orc_rho_from_charge": (None, [I32, I32, F64, F64, PI64, PD]),
-        "orc_iict_update": (None, [F64, F64, PD, PD, F64, F64, F64, PD, PD, PD, PD, PI32]),
+        "orc_iict_update": (None, [F64, F64, PD, PD, F64, F64, F64, PD, PD, PD, PD, PI32, PI32]),
         "orc_collision_probe": (I32, [F64, F64, F64, F64, F64, PD, PD, F64, I64, U64, C.POINTER(Probe)]),
         "orc_create": (C.c_void_p, [U64]),
         "orc_destroy": (None, [C.c_void_p]),
@@ -212,10 +212,10 @@ def rho_from_charge(q: np.ndarray, dr: float, dz: float) -> np.ndarray:
 def iict_update(m, mg, v, vgas, e_int, t_eff, alpha, uniforms):
     v, vg = _f64(v), _f64(vgas)
     w = _f64(uniforms).copy()
-    vo, vgo, eo, cl = np.zeros(3), np.zeros(3), np.zeros(1), np.zeros(1, dtype=np.int32)
+    vo, vgo, eo, cl = np.zeros(3), np.zeros(3), np.zeros(1), np.zeros(2, dtype=np.int32)
     lib().orc_iict_update(m, mg, _p(v, F64), _p(vg, F64), e_int, t_eff, alpha, _p(w, F64), _p(vo, F64),
-                          _p(vgo, F64), _p(eo, F64), _p(cl, I32))
-    return vo, vgo, float(eo[0]), int(cl[0])
+                          _p(vgo, F64), _p(eo, F64), _p(cl[:1], I32), _p(cl[1:], I32))
+    return vo, vgo, float(eo[0]), int(cl[0]), int(cl[1])
 
 
 def langevin_gamma(m: float, mg: float, n_sigma: float, t_gas: float) -> float:
@@ -358,7 +358,7 @@ class OracleSim:
         self._chk(lib().orc_read_tallies(self._h, C.byref(T)), "read_tallies")
         out = dict(bufs)
         for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "exit_overflow", "n_langevin",
-                  "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
+                  "n_exchange", "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
             out[k] = getattr(T, k)
         out["class_n"] = np.array(list(T.class_n), np.int64)
         out["class_w"] = np.array(list(T.class_w), np.int64)

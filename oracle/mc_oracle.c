@@ -199,18 +199,26 @@ void orc_dst1(const double *in, int32_t m, double *out) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Charge density from the int64 deposit grid ("deposited charge is          */
-/* normalized by the corresponding annular control volume").  The grid     */
-/* holds charge in units of e 2^-32.  Reading: the control volume of node i  */
-/* is the volume the bilinear (CIC) weight of that node covers,              */
-/*   V_0 = pi dr^2 dz / 3,   V_i = 2 pi r_i dr dz (i >= 1),                  */
-/* so a uniform density deposits to itself at every node, the axis included. */
-/* Pinned: uniform-density packs give rho = Q/V at all nodes (statistics).   */
+/* Charge density from the int64 deposit grid ("Axisymmetric PIC space      */
+/* charge update": the deposited charge of a node is divided by its annular  */
+/* control volume).  The grid holds charge in units of e 2^-32.  Reading:   */
+/* the control volume is the finite-volume cell of the radial operator      */
+/* below -- the disk of radius dr/2 on the axis, the annulus of width dr    */
+/* about r_i elsewhere:                                                     */
+/*   V_0 = pi (dr/2)^2 dz,   V_i = 2 pi r_i dr dz (i >= 1),                 */
+/* so the solve carries exactly the deposited charge (sum rho_i V_i = sum Q)  */
+/* and the discrete Gauss flux through every face equals the deposited     */
+/* charge inside it.  (At i >= 1 this volume is also the volume the CIC      */
+/* weight of the node covers; on the axis the CIC weight covers             */
+/* pi dr^2 dz / 3, so a uniform density reads 4/3 of itself on that node.)  */
+/* Pinned: packs deposited on a long grid, solved, give a Gauss flux through */
+/* each of the first faces equal to the deposited charge within; uniform    */
+/* density reads back at the off-axis nodes.                               */
 /* ------------------------------------------------------------------------ */
 void orc_rho_from_charge(int32_t nr, int32_t nz, double dr, double dz, const int64_t *q, double *rho) {
     for (int32_t j = 0; j < nz; ++j)
         for (int32_t i = 0; i < nr; ++i) {
-            double v = (i == 0) ? PI * dr * dr * dz / 3.0 : 2.0 * PI * (i * dr) * dr * dz;
+            double v = (i == 0) ? PI * (0.5 * dr) * (0.5 * dr) * dz : 2.0 * PI * (i * dr) * dr * dz;
             rho[(int64_t)j * nr + i] = (double)q[(int64_t)j * nr + i] * QE * 0x1p-32 / v;
         }
 }
@@ -428,14 +436,20 @@ double orc_poisson_residual(int32_t nr, int32_t nz, double dr, double dz, const 
 /*    otherwise Et' = Et (elastic);                                           */
 /*  - isotropic scattering of the relative velocity, |g'| = sqrt(2 Et'/mu).   */
 /* Uniforms: u[0] cos(chi), u[1] azimuth, u[2] exchange select, u[3], u[4]   */
-/* the Gamma(2) draw.                                                       */
-/* Pinned: momentum and total (kinetic + internal) energy conservation, and  */
-/* thermalisation of T_eff to the gas temperature; the partition against the */
-/* paper's own adapter is parity unpinned.                                   */
+/* the Gamma(2) draw.  *exchanged is set when the relative energy was       */
+/* redrawn from the bath.                                                   */
+/* Pinned: momentum and total (kinetic + internal) energy conservation; the */
+/* exchange fraction per accepted collision equals alpha (binomial bound);   */
+/* the default alpha equals the head-on elastic transfer fraction derived   */
+/* from momentum and energy conservation; the initial relaxation rate of    */
+/* E_int in a gas at T, alpha nu 2 kB (T - T_eff), with nu = n sigma <g>;    */
+/* the stationary spread sd(T_eff) = sqrt(kB T^2 / C) of a canonical bath.  */
+/* The partition against the paper's own adapter (its equations are cited,  */
+/* not printed) is parity unpinned.                                         */
 /* ------------------------------------------------------------------------ */
 void orc_iict_update(double m, double mg, const double v[3], const double vgas[3], double e_int, double t_eff,
                      double alpha, const double u[5], double v_out[3], double vgas_out[3], double *e_int_out,
-                     int32_t *clamped) {
+                     int32_t *clamped, int32_t *exchanged) {
     double M = m + mg, mu = m * mg / M;
     double vcm[3], g[3];
     for (int a = 0; a < 3; ++a) {
@@ -445,7 +459,9 @@ void orc_iict_update(double m, double mg, const double v[3], const double vgas[3
     double g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
     double et = 0.5 * mu * g2, etp = et;
     *clamped = 0;
+    *exchanged = 0;
     if (u[2] < alpha) {
+        *exchanged = 1;
         etp = -KB * t_eff * log(u[3] * u[4]);
         double e_new = e_int + et - etp;
         if (e_new < 0.0) {
@@ -499,7 +515,7 @@ typedef struct {
 } coll_env_t;
 
 typedef struct {
-    int64_t n_cand, n_acc, n_cap, n_clamp, n_lang;
+    int64_t n_cand, n_acc, n_cap, n_clamp, n_lang, n_exch;
     double sum_g, sum_g2;
 } coll_count_t;
 
@@ -547,11 +563,12 @@ static void collide(const coll_env_t *E, const uint32_t key[2], int64_t id, int6
         double t_eff = orc_einstein_t(*e_int, E->n_atoms, E->theta);
         double ui[5] = {u01(wc[0]), u01(wc[1]), uacc * (s + wn) / gn, u01(wc[2]), u01(wc[3])};
         double vo[3], vgo[3], eo;
-        int32_t clamped;
-        orc_iict_update(E->m, E->mg, v, vgas, *e_int, t_eff, E->alpha, ui, vo, vgo, &eo, &clamped);
+        int32_t clamped, exchanged;
+        orc_iict_update(E->m, E->mg, v, vgas, *e_int, t_eff, E->alpha, ui, vo, vgo, &eo, &clamped, &exchanged);
         v[0] = vo[0]; v[1] = vo[1]; v[2] = vo[2];
         *e_int = eo;
         cnt->n_clamp += clamped;
+        cnt->n_exch += exchanged;
     }
 }
 
@@ -632,7 +649,7 @@ struct orc_sim {
     int32_t *ex_i, *ex_j;
     double *ex_t, *ex_r;
     /* per-step counters */
-    int64_t n_cand, n_coll, n_cap, n_clamp, n_lang;
+    int64_t n_cand, n_coll, n_cap, n_clamp, n_lang, n_exch;
     int64_t emitted_n, emitted_w;
     /* adaptive step (Eq. 1): time, next space-charge time, last step */
     double t, t_next_pic, last_dt;
@@ -1232,8 +1249,8 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
         double cst[3] = {s->op.v_rf * cos(w2 * t0 + s->op.phase_rf),
                          s->op.v_rf * cos(w2 * (t0 + 0.5 * dt) + s->op.phase_rf),
                          s->op.v_rf * cos(w2 * (t0 + dt) + s->op.phase_rf)};
-        int64_t nc = 0, na = 0, ncap = 0, ncl = 0, nlv = 0;
-#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nc, na, ncap, ncl, nlv)
+        int64_t nc = 0, na = 0, ncap = 0, ncl = 0, nlv = 0, nex = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : nc, na, ncap, ncl, nlv, nex)
         for (int64_t k = 0; k < s->n; ++k) {
             if (s->status[k] != ORC_ACTIVE) continue;
             coll_count_t cnt;
@@ -1244,12 +1261,14 @@ int32_t orc_step(orc_sim *s, int64_t n_steps) {
             ncap += cnt.n_cap;
             ncl += cnt.n_clamp;
             nlv += cnt.n_lang;
+            nex += cnt.n_exch;
         }
         s->n_cand += nc;
         s->n_coll += na;
         s->n_cap += ncap;
         s->n_clamp += ncl;
         s->n_lang += nlv;
+        s->n_exch += nex;
         s->last_dt = dt;
         s->t = s->op.adaptive ? t0 + dt : (double)(step + 1) * s->op.dt;
         s->step++;
@@ -1371,6 +1390,7 @@ int32_t orc_read_tallies(const orc_sim *s, orc_tallies *t) {
     t->n_cap = s->n_cap;
     t->n_clamp = s->n_clamp;
     t->n_langevin = s->n_lang;
+    t->n_exchange = s->n_exch;
     return 0;
 }
 

@@ -83,6 +83,7 @@ typedef struct orc_tallies {
     int64_t emitted_n, emitted_w;
     int64_t class_n[ORC_NCLASS], class_w[ORC_NCLASS];
     int64_t n_cand, n_coll, n_cap, n_clamp, exit_overflow, n_langevin;
+    int64_t n_exchange; /* accepted collisions that exchanged internal energy */
     double sum_w_ke_active, sum_w_eint_active, sum_w_dissoc_terminal;
     int64_t *exit_bins; /* [n_exit_bins] */
     int64_t *loss_map;  /* [nz*nr] */
@@ -127,7 +128,7 @@ double orc_poisson_residual(int32_t nr, int32_t nz, double dr, double dz, const 
 void orc_rho_from_charge(int32_t nr, int32_t nz, double dr, double dz, const int64_t *q, double *rho);
 void orc_iict_update(double m, double mg, const double v[3], const double vgas[3], double e_int, double t_eff,
                      double alpha, const double u[5], double v_out[3], double vgas_out[3], double *e_int_out,
-                     int32_t *clamped);
+                     int32_t *clamped, int32_t *exchanged);
 int32_t orc_collision_probe(double m_da, double ccs, double mg_da, double p, double t_gas, const double u[3],
                             const double v[3], double dt, int64_t n_steps, uint64_t seed, orc_probe *out);
 

@@ -34,15 +34,16 @@ struct PackPtrs {
 };
 
 // int64 tally block.  Layout of cnt: class_n[6], class_w[6], n_cand, n_coll,
-// n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, exit_count.
+// n_cap, n_clamp, pack_steps, exit_overflow, exit_dropped, exit_count,
+// n_langevin, n_exchange.
 enum { TC_CLASS_N = 0, TC_CLASS_W = 6, TC_CAND = 12, TC_COLL = 13, TC_CAP = 14, TC_CLAMP = 15, TC_PACKSTEPS = 16,
-       TC_EXOVER = 17, TC_EXDROP = 18, TC_EXCOUNT = 19, TC_LANG = 20, TC_N = 21 };
+       TC_EXOVER = 17, TC_EXDROP = 18, TC_EXCOUNT = 19, TC_LANG = 20, TC_EXCH = 21, TC_N = 22 };
 
 // Per-step event counters (pack steps, candidates, collisions, caps, clamps,
-// Langevin steps): each block adds its totals to one of kHotRep replicas,
+// Langevin steps, internal-energy exchanges): each block adds its totals to one of kHotRep replicas,
 // one 128-byte line each, so concurrent blocks rarely update the same
 // address; readers add the replicas into the counters (fold_hot).
-enum { HOT_PACKSTEPS = 0, HOT_CAND = 1, HOT_COLL = 2, HOT_CAP = 3, HOT_CLAMP = 4, HOT_LANG = 5, HOT_N = 6 };
+enum { HOT_PACKSTEPS = 0, HOT_CAND = 1, HOT_COLL = 2, HOT_CAP = 3, HOT_CLAMP = 4, HOT_LANG = 5, HOT_EXCH = 6, HOT_N = 7 };
 constexpr int kHotRep = 128, kHotStride = 16;
 constexpr int64_t kHotLen = (int64_t)kHotRep * kHotStride;
 
@@ -51,7 +52,7 @@ constexpr int64_t kHotLen = (int64_t)kHotRep * kHotStride;
 inline int64_t hot_offset(int64_t base) { return (base + kHotStride - 1) / kHotStride * kHotStride; }
 
 inline void fold_hot(const unsigned long long *hot, unsigned long long *cnt) {
-    static const int to[HOT_N] = {TC_PACKSTEPS, TC_CAND, TC_COLL, TC_CAP, TC_CLAMP, TC_LANG};
+    static const int to[HOT_N] = {TC_PACKSTEPS, TC_CAND, TC_COLL, TC_CAP, TC_CLAMP, TC_LANG, TC_EXCH};
     for (int r = 0; r < kHotRep; ++r)
         for (int k = 0; k < HOT_N; ++k) cnt[to[k]] += hot[(int64_t)r * kHotStride + k];
 }
@@ -64,28 +65,32 @@ struct TallyPtrs {
 
 // ---------------------------------------------------------------------------
 // Histogram bins: KE log10 bins over [1e-3, 1e3] eV, T_eff over [0, 5000] K,
-// exit radius over [0, r_det]; bin 0 = underflow, last = overflow.
+// exit radius over [0, r_det]; bin 0 = underflow, last = overflow.  The
+// ranges are published by mc_get_tally_layout.
 // ---------------------------------------------------------------------------
+constexpr double kKeLog10Lo = -3.0, kKeLog10Hi = 3.0, kTeffLo = 0.0, kTeffHi = 5000.0;
+constexpr int kKeBins = MC_HIST_KE - 2, kTeffBins = MC_HIST_TEFF - 2, kRBins = MC_HIST_R - 2;
+
 __device__ __forceinline__ int hbin_ke(double ke_ev) {
 #pragma clang fp contract(off)
     if (!(ke_ev > 0.0)) return 0;
-    const double u = (log10(ke_ev) + 3.0) * (200.0 / 6.0);
+    const double u = (log10(ke_ev) - kKeLog10Lo) * ((double)kKeBins / (kKeLog10Hi - kKeLog10Lo));
     if (!(u >= 0.0)) return 0;
-    if (u >= 200.0) return 201;
+    if (u >= (double)kKeBins) return kKeBins + 1;
     return 1 + (int)floor(u);
 }
 __device__ __forceinline__ int hbin_teff(double t) {
 #pragma clang fp contract(off)
-    const double u = t * (200.0 / 5000.0);
+    const double u = (t - kTeffLo) * ((double)kTeffBins / (kTeffHi - kTeffLo));
     if (!(u >= 0.0)) return 0;
-    if (u >= 200.0) return 201;
+    if (u >= (double)kTeffBins) return kTeffBins + 1;
     return 1 + (int)floor(u);
 }
 __device__ __forceinline__ int hbin_r(double r, double rdet) {
 #pragma clang fp contract(off)
-    const double u = r / rdet * 100.0;
+    const double u = r / rdet * (double)kRBins;
     if (!(u >= 0.0)) return 0;
-    if (u >= 100.0) return 101;
+    if (u >= (double)kRBins) return kRBins + 1;
     return 1 + (int)floor(u);
 }
 
@@ -264,14 +269,14 @@ __device__ __forceinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s
 }
 
 struct StepCount {
-    uint64_t cand, acc, cap, clamp, act, lang;
+    uint64_t cand, acc, cap, clamp, act, lang, exch;
 };
 
 // One pack, one step.
 template <class P, class Tab>
 __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n, uint32_t k0, uint32_t k1) {
     using T = typename P::T;
-    uint32_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0;  // per pack and step: < 2^32
+    uint32_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0, nexch = 0;  // per pack and step: < 2^32
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
         n.act = 1;
         // the species record by reference, so each field is read where it is
@@ -462,6 +467,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     T etp = et;
                     // exchange select: the acceptance residual, uniform given acceptance
                     if (uacc * (sv + wn) < alpha * gn) {  // residual uacc (s + |w|)/|g| < alpha
+                        ++nexch;
                         const T te = einstein_t<P>(e + el, skt, theta);
                         etp = -(T)kB * te * P::ln_fast(P::u01(wc.w2) * P::u01(wc.w3));
                         const T de = et - etp;
@@ -514,6 +520,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
     n.cap = ncap;
     n.clamp = nclamp;
     n.lang = nlang;
+    n.exch = nexch;
 }
 
 // Block-aggregated counters: wavefront sums, then LDS, then one atomic per
@@ -524,7 +531,8 @@ __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount
     if (threadIdx.x < HOT_N) red[threadIdx.x] = 0ull;
     __syncthreads();
     const uint64_t v[HOT_N] = {wave_sum_u64(n.act), wave_sum_u64(n.cand), wave_sum_u64(n.acc),
-                               wave_sum_u64(n.cap), wave_sum_u64(n.clamp), wave_sum_u64(n.lang)};
+                               wave_sum_u64(n.cap),   wave_sum_u64(n.clamp), wave_sum_u64(n.lang),
+                               wave_sum_u64(n.exch)};
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < HOT_N; ++k)
@@ -548,7 +556,7 @@ constexpr int step_waves() {
 template <class P, class Tab>
 __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
     P::prepare_tables(a.tables);
-    StepCount n{0, 0, 0, 0, 0, 0};
+    StepCount n{0, 0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
     flush_counts(a.t, n);
 }
@@ -652,7 +660,7 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(cons
     const int q = block_query(prefix, nq);
     const StepArgs<P, Tab> &a = descs[q];
     P::prepare_tables(a.tables);
-    StepCount n{0, 0, 0, 0, 0, 0};
+    StepCount n{0, 0, 0, 0, 0, 0, 0};
     // the random key is the query's, the same for the whole block: scalar
     step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n,
              __builtin_amdgcn_readfirstlane(a.k0), __builtin_amdgcn_readfirstlane(a.k1));

@@ -34,18 +34,28 @@ static __global__ __launch_bounds__(256) void k_sine_table(double *s, int32_t nz
 
 // ---------------------------------------------------------------------------
 // Poisson: unknowns Phi[i][j], 0 <= i <= nr-2, 1 <= j <= nz-2 (m = nz-2).
-// Right-hand side b = -rho/eps0 with rho = Q e 2^-32 / V_i, V_0 = pi dr^2 dz/3,
-// V_i = 2 pi r_i dr dz.  Forward DST-I per radial row (scaled 2/(m+1)), one
+// Right-hand side b = -rho/eps0 with rho = Q e 2^-32 / V_i over the annular
+// control volume of the finite-volume operator (control_volume).  Forward
+// DST-I per radial row (scaled 2/(m+1)), one
 // tridiagonal system per mode (coefficients precomputed), inverse DST-I.
 // Row-major work arrays bh[i][k], k contiguous.
 // ---------------------------------------------------------------------------
+// Annular control volume of node i (the space-charge section): the cell of
+// the finite-volume radial operator, a disk of radius dr/2 on the axis and an
+// annulus of width dr about r_i elsewhere, so the solve holds exactly the
+// deposited charge and its Gauss flux through every cell face equals the
+// charge inside.
+__device__ __forceinline__ double control_volume(int32_t i, double dr, double dz) {
+    return i == 0 ? kPi * (0.5 * dr) * (0.5 * dr) * dz : 2.0 * kPi * ((double)i * dr) * dr * dz;
+}
+
 template <class D>
 __global__ __launch_bounds__(256) void k_dst_rows(const unsigned long long *q, const double *rhs, const double *sine,
                                                   D *bh, int32_t nr, int32_t nz, double dr, double dz) {
     extern __shared__ unsigned char smem_raw[];
     D *row = reinterpret_cast<D *>(smem_raw);
     const int32_t i = blockIdx.x, m = nz - 2, n2 = 2 * (nz - 1);
-    const double vol = (i == 0) ? kPi * dr * dr * dz / 3.0 : 2.0 * kPi * ((double)i * dr) * dr * dz;
+    const double vol = control_volume(i, dr, dz);
     const double scale = -kQe * 0x1p-32 / (vol * kEps0);
     for (int32_t j = threadIdx.x; j < m; j += blockDim.x) {
         const int64_t o = (int64_t)(j + 1) * nr + i;
@@ -300,7 +310,7 @@ __global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long
     extern __shared__ unsigned char smem_raw[];
     Cx<D> *a = reinterpret_cast<Cx<D> *>(smem_raw);
     const int32_t i = blockIdx.x, m = nz - 2;
-    const double vol = (i == 0) ? kPi * dr * dr * dz / 3.0 : 2.0 * kPi * ((double)i * dr) * dr * dz;
+    const double vol = control_volume(i, dr, dz);
     const double scale = -kQe * 0x1p-32 / (vol * kEps0);
     for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
         Cx<D> v{(D)0, (D)0};

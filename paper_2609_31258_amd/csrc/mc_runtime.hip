@@ -1008,6 +1008,35 @@ int32_t mc_get_info(const mc_ctx *ctx, mc_info *info) {
     return MC_OK;
 }
 
+int32_t mc_get_tally_layout(const mc_ctx *ctx, mc_tally_layout *out) {
+    if (!ctx || !out) return MC_EINVAL;
+    if (!ctx->has_op) return MC_ESTATE;
+    mc_tally_layout L{};
+    L.n_classes = MC_NCLASS;
+    L.n_exit_bins = ctx->op.n_exit_bins;
+    L.exit_bin_dt = ctx->op.exit_bin_dt;
+    L.nr = ctx->nr;
+    L.nz = ctx->nz;
+    L.loss_map_len = (int64_t)ctx->nr * ctx->nz;
+    L.hist_ke_len = MC_HIST_KE;
+    L.ke_bins = kKeBins;
+    L.ke_log10_lo = kKeLog10Lo;
+    L.ke_log10_hi = kKeLog10Hi;
+    L.hist_teff_len = MC_HIST_TEFF;
+    L.teff_bins = kTeffBins;
+    L.teff_lo = kTeffLo;
+    L.teff_hi = kTeffHi;
+    L.hist_r_len = MC_HIST_R;
+    L.r_bins = kRBins;
+    L.r_lo = 0.0;
+    L.r_hi = ctx->op.r_det;
+    L.exit_capacity = ctx->tp.exit_cap;
+    L.sample_capacity = ctx->sample_cap;
+    L.charge_grid_len = (int64_t)ctx->nr * ctx->nz;
+    *out = L;
+    return MC_OK;
+}
+
 int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out) {
     if (!ctx || !out) return MC_EINVAL;
     if (!ctx->has_op) return fail(ctx, MC_ESTATE, "no operating point");
@@ -1038,6 +1067,7 @@ int32_t mc_read_tallies(mc_ctx *ctx, mc_tallies *out) {
     out->exit_overflow = (int64_t)cnt[TC_EXOVER];
     out->exit_dropped = (int64_t)cnt[TC_EXDROP];
     out->n_langevin = (int64_t)cnt[TC_LANG];
+    out->n_exchange = (int64_t)cnt[TC_EXCH];
     out->sum_w_ke_active = sums[0];
     out->sum_w_eint_active = sums[1];
     out->sum_w_dissoc_terminal = sums[2];

@@ -646,6 +646,7 @@ static int32_t retire_query(mc_server *S, Query &Q, PackPtrs<T> p) {
     r.exit_overflow = (int64_t)tal[TC_EXOVER];
     r.exit_dropped = (int64_t)tal[TC_EXDROP];
     r.n_langevin = (int64_t)tal[TC_LANG];
+    r.n_exchange = (int64_t)tal[TC_EXCH];
     r.sum_w_ke_active = sums[0];
     r.sum_w_eint_active = sums[1];
     r.sum_w_dissoc_terminal = sums[2];

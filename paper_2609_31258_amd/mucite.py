@@ -23,7 +23,7 @@ PD, PI64, PI32, PU8 = C.POINTER(F64), C.POINTER(I64), C.POINTER(I32), C.POINTER(
 
 MC_OK, MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE, MC_ENUMERIC, MC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PREC_FP64, PREC_FP32 = 0, 1
-ABI_VERSION = 3
+ABI_VERSION = 4
 NCLASS = 6
 HIST_KE, HIST_TEFF, HIST_R = 202, 202, 102
 K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY = range(6)
@@ -74,10 +74,18 @@ class Packs(C.Structure):
 class Tallies(C.Structure):
     _fields_ = [("emitted_n", I64), ("emitted_w", I64), ("class_n", I64 * NCLASS), ("class_w", I64 * NCLASS),
                 ("n_cand", I64), ("n_coll", I64), ("n_cap", I64), ("n_clamp", I64), ("pack_steps", I64),
-                ("exit_overflow", I64), ("exit_dropped", I64), ("n_langevin", I64),
+                ("exit_overflow", I64), ("exit_dropped", I64), ("n_langevin", I64), ("n_exchange", I64),
                 ("sum_w_ke_active", F64), ("sum_w_eint_active", F64), ("sum_w_dissoc_terminal", F64),
                 ("exit_bins", PI64), ("loss_map", PI64), ("hist_ke", PI64), ("hist_teff", PI64), ("hist_r", PI64),
                 ("act_hist_ke", PI64), ("act_hist_teff", PI64)]
+
+
+class TallyLayout(C.Structure):
+    _fields_ = [("n_classes", I32), ("n_exit_bins", I32), ("exit_bin_dt", F64), ("nr", I32), ("nz", I32),
+                ("loss_map_len", I64), ("hist_ke_len", I32), ("ke_bins", I32), ("ke_log10_lo", F64),
+                ("ke_log10_hi", F64), ("hist_teff_len", I32), ("teff_bins", I32), ("teff_lo", F64),
+                ("teff_hi", F64), ("hist_r_len", I32), ("r_bins", I32), ("r_lo", F64), ("r_hi", F64),
+                ("exit_capacity", I64), ("sample_capacity", I64), ("charge_grid_len", I64)]
 
 
 class ExitRec(C.Structure):
@@ -148,6 +156,7 @@ _SIGS = {
     "mc_pic_update": (I32, [C.c_void_p]),
     "mc_synchronize": (I32, [C.c_void_p]),
     "mc_get_info": (I32, [C.c_void_p, C.POINTER(Info)]),
+    "mc_get_tally_layout": (I32, [C.c_void_p, C.POINTER(TallyLayout)]),
     "mc_read_tallies": (I32, [C.c_void_p, C.POINTER(Tallies)]),
     "mc_read_exits": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
     "mc_read_samples": (I32, [C.c_void_p, C.c_void_p, I64, PI64]),
@@ -370,18 +379,25 @@ class Sim:
             setattr(P, k, _p(a, {np.float64: F64, np.int64: I64, np.int32: I32}[a.dtype.type]))
         self._chk(self.L.mc_write_packs(self._h, C.byref(P)), "mc_write_packs")
 
+    def tally_layout(self) -> Dict[str, object]:
+        L = TallyLayout()
+        self._chk(self.L.mc_get_tally_layout(self._h, C.byref(L)), "mc_get_tally_layout")
+        return {f: getattr(L, f) for f, _ in TallyLayout._fields_}
+
     def read_tallies(self) -> Dict[str, object]:
         T = Tallies()
-        bufs = dict(exit_bins=np.zeros(self.n_exit_bins, np.int64), loss_map=np.zeros((self.nz, self.nr), np.int64),
-                    hist_ke=np.zeros(HIST_KE, np.int64), hist_teff=np.zeros(HIST_TEFF, np.int64),
-                    hist_r=np.zeros(HIST_R, np.int64), act_hist_ke=np.zeros(HIST_KE, np.int64),
-                    act_hist_teff=np.zeros(HIST_TEFF, np.int64))
+        L = self.tally_layout()  # buffer sizes from the library's own layout
+        bufs = dict(exit_bins=np.zeros(L["n_exit_bins"], np.int64),
+                    loss_map=np.zeros(L["loss_map_len"], np.int64).reshape(L["nz"], L["nr"]),
+                    hist_ke=np.zeros(L["hist_ke_len"], np.int64), hist_teff=np.zeros(L["hist_teff_len"], np.int64),
+                    hist_r=np.zeros(L["hist_r_len"], np.int64), act_hist_ke=np.zeros(L["hist_ke_len"], np.int64),
+                    act_hist_teff=np.zeros(L["hist_teff_len"], np.int64))
         for k, a in bufs.items():
             setattr(T, k, _p(a, I64))
         self._chk(self.L.mc_read_tallies(self._h, C.byref(T)), "mc_read_tallies")
         out = dict(bufs)
         for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "pack_steps", "exit_overflow",
-                  "exit_dropped", "n_langevin", "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
+                  "exit_dropped", "n_langevin", "n_exchange", "sum_w_ke_active", "sum_w_eint_active", "sum_w_dissoc_terminal"):
             out[k] = getattr(T, k)
         out["class_n"] = np.array(list(T.class_n), np.int64)
         out["class_w"] = np.array(list(T.class_w), np.int64)
@@ -530,7 +546,7 @@ class Server:
             T = r.tallies
             tal = dict(bufs)
             for k in ("emitted_n", "emitted_w", "n_cand", "n_coll", "n_cap", "n_clamp", "pack_steps",
-                      "exit_overflow", "exit_dropped", "n_langevin", "sum_w_ke_active", "sum_w_eint_active",
+                      "exit_overflow", "exit_dropped", "n_langevin", "n_exchange", "sum_w_ke_active", "sum_w_eint_active",
                       "sum_w_dissoc_terminal"):
                 tal[k] = getattr(T, k)
             tal["class_n"] = np.array(list(T.class_n), np.int64)

@@ -84,7 +84,7 @@ def _poisson_residual(q, phi, dr, dz):
     finite-volume cylindrical operator (axis row: 4 (phi_1 - phi_0)/dr^2)."""
     nz, nr = q.shape
     i = np.arange(nr, dtype=np.float64)
-    vol = np.where(i == 0, np.pi * dr * dr * dz / 3.0, 2.0 * np.pi * i * dr * dr * dz)
+    vol = np.where(i == 0, np.pi * (0.5 * dr) ** 2 * dz, 2.0 * np.pi * i * dr * dr * dz)  # annular control volumes
     b = -(q.astype(np.float64) * QE * 2.0 ** -32 / vol[None, :]) / EPS0
     p = phi
     ar = np.empty((nz - 2, nr - 1))

@@ -277,7 +277,8 @@ def test_iict_update_conserves_momentum_and_energy():
             vg = rng.normal(0, 300, 3)
             e_int = rng.uniform(1e-20, 1e-18)
             uni = rng.uniform(0, 1, 5)
-            vo, vgo, eo, cl = O.iict_update(m, mg, v, vg, e_int, 450.0, alpha, uni)
+            vo, vgo, eo, cl, ex = O.iict_update(m, mg, v, vg, e_int, 450.0, alpha, uni)
+            assert ex == (1 if alpha == 1.0 else 0)
             assert np.allclose(m * vo + mg * vgo, m * v + mg * vg, rtol=1e-12, atol=1e-30)
             ke0 = 0.5 * m * v @ v + 0.5 * mg * vg @ vg + e_int
             ke1 = 0.5 * m * vo @ vo + 0.5 * mg * vgo @ vgo + eo
@@ -292,7 +293,18 @@ def _gas_box(p, tg, ez=0.0, nr=16, nz=128):
     return synth.uniform_fields(nr, nz, 5e-5, ez=ez, p=p, t_gas=tg)
 
 
+def _einstein_heat_capacity(t, n_atoms, theta=1100.0):
+    """Textbook heat capacity of s = 3N - 6 Einstein oscillators,
+    C = s kB x^2 e^x / (e^x - 1)^2 with x = theta / T."""
+    x = theta / t
+    return (3 * n_atoms - 6) * KB * x * x * math.exp(x) / math.expm1(x) ** 2
+
+
 def test_thermalisation_to_gas_temperature():
+    """Uniform gas at 500 K, packs starting at T_eff = 300 K: the translational
+    energy goes to (3/2) kB T, the mean T_eff to T, and the spread of T_eff
+    about it to that of a canonical bath, sqrt(kB T^2 / C) (C the heat
+    capacity of the internal modes at T)."""
     tg = 500.0
     f = _gas_box(1e5, tg)
     ion = synth.Ion(500.0, 1, 2e-18, 150)
@@ -301,16 +313,97 @@ def test_thermalisation_to_gas_temperature():
     n = 2000
     s.write_packs(_snap(n, 0.0, 0.0, 3e-3, 0.0, 0.0, 0.0, e_int=O.einstein_u(300.0, 150)))
     s.step(120)
-    ke, te = [], []
+    ke, te, var = [], [], []
     m = 500 * DA
     for _ in range(40):
         s.step(2)
         p = s.read_packs()
         assert np.all(p["status"] == 0)
         ke.append(0.5 * m * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2).mean())
-        te.append(np.mean([O.einstein_t(e, 150) for e in p["e_int"]]))
+        t = np.array([O.einstein_t(e, 150) for e in p["e_int"]])
+        te.append(t.mean())
+        var.append(t.var())
     assert np.mean(ke) == pytest.approx(1.5 * KB * tg, rel=0.015)
     assert np.mean(te) == pytest.approx(tg, rel=0.01)
+    sd_canonical = math.sqrt(KB * tg * tg / _einstein_heat_capacity(tg, 150))
+    assert sd_canonical == pytest.approx(28.8, abs=0.1)
+    assert math.sqrt(np.mean(var)) == pytest.approx(sd_canonical, rel=0.05)
+
+
+def _head_on_transfer(m1, m2):
+    """Share of the kinetic energy that a head-on elastic collision passes
+    from a moving m1 to m2 at rest: the non-trivial root a = v1'/v1 of
+    momentum and energy conservation, m1 = m1 a + m2 b and
+    m1 = m1 a^2 + m2 b^2 (v1 = 1), solved numerically; the share is 1 - a^2."""
+    k = m1 * m1 / m2
+    roots = np.roots([m1 + k, -2 * k, k - m1]).real
+    a = roots[np.argmax(np.abs(roots - 1.0))]
+    return 1.0 - a * a
+
+
+def _exchange_counts(alpha, m_da=500.0, n_atoms=150, n=4000, steps=20):
+    f = _gas_box(1e5, 300.0)
+    ion = synth.Ion(m_da, 1, 2e-18, n_atoms, alpha=alpha)
+    op = synth.Operating(dt=1e-9, z_det=f.grid.L, r_det=f.grid.R, collisions_on=1)
+    s = _sim(f, ion, op)
+    s.write_packs(_snap(n, 0.0, 0.0, 3e-3, 0.0, 0.0, 0.0, e_int=O.einstein_u(300.0, n_atoms)))
+    s.step(steps)
+    t = s.read_tallies()
+    return t["n_exchange"], t["n_coll"]
+
+
+@pytest.mark.parametrize("alpha,m_da,n_atoms", [(0.0, 500.0, 150), (0.2, 500.0, 150), (1.0, 500.0, 150),
+                                                 (-1.0, 500.0, 150), (-1.0, 10 * 28.0134, 10)])
+def test_exchange_fraction_per_accepted_collision(alpha, m_da, n_atoms):
+    """The internal-energy exchange happens on a fraction alpha of the
+    accepted collisions (binomial, 5 sigma).  alpha < 0 selects the default:
+    the head-on elastic transfer share between a gas molecule and one atom
+    of the ion (mass m/N), 0.3801 for the 500 Da, 150-atom ion and exactly 1
+    when an atom weighs as much as the gas molecule."""
+    ex, acc = _exchange_counts(alpha, m_da, n_atoms)
+    assert acc > 500_000
+    want = alpha if alpha >= 0.0 else _head_on_transfer(28.0134, m_da / n_atoms)
+    if alpha < 0.0 and n_atoms == 150:
+        assert want == pytest.approx(0.3801, abs=1e-4)
+    if want in (0.0, 1.0):
+        assert ex == round(want * acc)
+    else:
+        assert abs(ex / acc - want) < 5 * math.sqrt(want * (1 - want) / acc), (ex / acc, want)
+
+
+def test_internal_energy_relaxation_rate():
+    """Initial heating of the internal modes by the gas: ion translation at
+    the gas temperature T, internal modes at T0.  Accepted collisions come
+    at nu = n sigma <|g|>, <|g|> = sqrt(8 kB T / (pi mu)); their relative
+    energy is Gamma(2, kB T) (mean 2 kB T) and a fraction alpha of them
+    redraw it from the bath, Gamma(2, kB T_eff) (mean 2 kB T_eff), the
+    difference going to E_int:
+        d<E_int>/dt = alpha nu 2 kB (T - T_eff),
+    with T_eff relaxing at kappa = 2 kB alpha nu / C(T_eff), so over a short
+    window t, <E_int(t)> - E0 = alpha nu 2 kB (T - T0) t (1 - kappa t / 2)
+    to first order.  alpha is the default (head-on transfer) share."""
+    tg, t0, p, n_atoms, m_da, ccs = 500.0, 300.0, 1e5, 150, 500.0, 2e-18
+    dt, steps, n = 1e-10, 2, 100_000
+    f = _gas_box(p, tg)
+    ion = synth.Ion(m_da, 1, ccs, n_atoms)
+    op = synth.Operating(dt=dt, z_det=f.grid.L, r_det=f.grid.R, collisions_on=1)
+    s = _sim(f, ion, op)
+    m = m_da * DA
+    rng = np.random.default_rng(21)
+    e0 = O.einstein_u(t0, n_atoms)
+    snap = _snap(n, 0.0, 0.0, 3e-3, 0.0, 0.0, 0.0, e_int=e0)
+    snap["vx"], snap["vy"], snap["vz"] = rng.normal(0.0, math.sqrt(KB * tg / m), (3, n))
+    s.write_packs(snap)
+    s.step(steps)
+    de = s.read_packs()["e_int"] - e0
+    t = steps * dt
+    mu = m * MG / (m + MG)
+    nu = p / (KB * tg) * ccs * math.sqrt(8 * KB * tg / (math.pi * mu))
+    alpha = _head_on_transfer(28.0134, m_da / n_atoms)
+    kappa = 2 * KB * alpha * nu / _einstein_heat_capacity(t0, n_atoms)
+    want = alpha * nu * 2 * KB * (tg - t0) * t * (1 - 0.5 * kappa * t)
+    sem = de.std() / math.sqrt(n)
+    assert abs(de.mean() - want) < 5 * sem + 0.005 * want, (de.mean() / want, sem / want)
 
 
 def _mason_schamp(m_da, ccs, p, tg, charge=1):

@@ -286,11 +286,12 @@ def test_deposit_pack_on_node():
     assert np.count_nonzero(q) == 2
 
 
-def test_rho_from_uniform_density_including_axis():
-    """Packs uniform in a cylinder volume: the CIC charge over each node's
-    weight volume is the true density, the axis node included (the axis
-    weight volume pi dr^2 dz / 3 differs from the disk pi (dr/2)^2 dz by a
-    factor 4/3, which this resolves)."""
+def test_rho_from_uniform_density():
+    """Packs uniform in a cylinder volume: the CIC charge of each off-axis
+    node over its annular control volume 2 pi r_i dr dz (which is also the
+    volume its CIC weight covers) is the true density.  On the axis the
+    control volume is the disk pi (dr/2)^2 dz while the CIC weight covers
+    pi dr^2 dz / 3, so that node reads 4/3 of the density."""
     h = 5e-5
     nr, nz = 24, 40
     rng = np.random.default_rng(4)
@@ -307,4 +308,33 @@ def test_rho_from_uniform_density_including_axis():
     vhat = np.array([math.pi * h ** 3 / 3] + [2 * math.pi * i * h ** 3 for i in range(1, imax)])
     per_node = n * vhat / (math.pi * rmax ** 2 * (z1 - z0)) * (j1 - j0)
     sd = 1.0 / np.sqrt(per_node)
-    assert np.all(np.abs(est - 1.0) < 5 * sd + 1e-3), (est, sd)
+    expect = np.ones(imax)
+    expect[0] = 4.0 / 3.0
+    assert np.all(np.abs(est - expect) < 5 * sd * expect + 1e-3), (est, sd)
+
+
+def test_deposited_charge_gauss_flux_through_first_faces():
+    """Deposit, solve and field as one chain: packs on every interior row of a
+    long grid (L/R ~ 16, end effects ~exp(-2.4 * 8)) at r = 0.3 dr and 2.6 dr,
+    CIC-deposited, divided by the control volumes and solved.  In the middle
+    row the potential no longer varies along z, so the discrete Gauss law
+    holds face by face: the flux 2 pi r_{i+1/2} dz (Phi_i - Phi_{i+1}) / dr
+    through the cylinder face r_{i+1/2} equals the deposited charge of the
+    row's nodes 0..i over eps0 -- the axis node's charge in full."""
+    nr, nz, h = 48, 768, 5e-5
+    rows = np.arange(1, nz - 1, dtype=float)
+    rad = np.concatenate([np.full(rows.size, 0.3 * h), np.full(rows.size, 2.6 * h)])
+    zz = np.concatenate([rows, rows]) * h
+    ph = np.linspace(0.0, 2 * math.pi, rad.size, endpoint=False)
+    s, f = _charge_sim(_snap(rad * np.cos(ph), rad * np.sin(ph), zz, np.full(rad.size, 1000.0)), nr=nr, nz=nz,
+                       charge=1)
+    q = s.read_charge()
+    phi, _, _ = s.read_sc()
+    jm = nz // 2
+    assert q[jm, 0] > 0 and q[jm, 1] > 0 and q[jm, 2] > 0 and q[jm, 3] > 0 and np.all(q[jm, 4:] == 0)
+    qenc = np.cumsum(q[jm].astype(float)) * QE * 2.0 ** -32
+    for i in range(0, 8):
+        flux = 2 * math.pi * (i + 0.5) * h * h * (phi[jm, i] - phi[jm, i + 1]) / h
+        assert flux == pytest.approx(qenc[i] / EPS0, rel=1e-7), i
+
+

@@ -105,6 +105,5 @@ def test_simulation_pic_update_uses_the_mask():
     g = f.grid
     q = s.read_charge()
     i = np.arange(g.nr)
-    vol = np.where(i == 0, np.pi * g.dr * g.dr * g.dz / 3.0, 2.0 * np.pi * i * g.dr * g.dr * g.dz)
-    rho = q * 1.602176634e-19 * 2.0 ** -32 / vol[None, :]
+    rho = O.rho_from_charge(q, g.dr, g.dz)
     assert _masked_residual(rho, phi, f.mask, g.dr, g.dz) <= 1e-9
