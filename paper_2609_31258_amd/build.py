@@ -6,9 +6,7 @@ compiles csrc/mc_runtime.hip (single simulations) and csrc/mc_server.hip (servin
 which include the kernels, with hipcc into
 paper_2609_31258_amd/libmucite.so.  Flags: -O3, FMA contraction on (the
 kernels turn it off locally where results must be bit-reproducible), packed
-FP32 instructions disabled.  Also builds paper_2609_31258_amd/issue_probe, a
-standalone program that measures the vector issue rate of the instruction
-classes of the step kernel (csrc/issue_probe.hip).
+FP32 instructions disabled.
 """
 import os
 import subprocess
@@ -17,7 +15,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmucite.so")
-PROBE = os.path.join(HERE, "issue_probe")
 SOURCES = [os.path.join(HERE, "csrc", "mc_runtime.hip"), os.path.join(HERE, "csrc", "mc_server.hip")]
 ARCH = os.environ.get("MUCITE_ARCH", "gfx950")
 
@@ -38,21 +35,7 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
-    build_probe(verbose)
     return LIB
-
-
-def build_probe(verbose: bool = False) -> str:
-    """The vector issue-rate probe (csrc/issue_probe.hip), a standalone program
-    built with the library's code-generation flags."""
-    tmp = PROBE + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
-           "-packed-fp32-ops", "-Wall", "-o", tmp, os.path.join(HERE, "csrc", "issue_probe.hip")]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, PROBE)
-    return PROBE
 
 
 if __name__ == "__main__":
