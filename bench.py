@@ -6,19 +6,24 @@ weighted to a 10 nA current, ion m = 5000 Da, z = +5, CCS 1500 A^2, N2 gas at
 1e5 -> 200 Pa, collisions on, CIC deposit + Poisson every 10 steps,
 dt = 0.5 ns.  A step is one pass of the whole path (emission, RK4 push,
 classification, collisions, dissociation, tallies, and the space-charge
-update every 10th step).  `warmup` steps run untimed first (the default
-fills the population to 1e6 packs); then exactly `steps` steps are timed
-with the device synchronised on both sides.  value = active pack-steps
-advanced in the timed window / wall seconds, FP64 path; the FP32 form
-(FP32 math, BF16 tables, two-float positions) is timed the same way and
-reported beside it, and so is the hybrid form (the FP32 form with the
+update every 10th step).
+
+The run first advances the workload through its emission ramp (steps
+0..1999, untimed set-up that does not depend on --warmup), so the population
+is the full 1e6 packs; then `warmup` untimed steps; then exactly `steps`
+steps timed with the device synchronised on both sides.  value = active
+pack-steps advanced in the timed window / wall seconds, FP64 path; the FP32
+form (FP32 math, BF16 tables, two-float positions) is timed the same way
+and reported beside it, and so is the hybrid form (the FP32 form with the
 Langevin branch taking the dense first millimetre).
 
 Also reported: the dominant kernel's roofline (HIP events around every
-launch of the fused step kernel), windows of the masked Poisson solve, the
-snapshots and the adaptive step on the full-occupancy state (`next_rows`),
-the serving leg, and the CPU oracle's rate on a bounded sample of the same
-workload on this host's cores.
+launch of the fused step kernel), the deposit's, windows of the masked
+Poisson solve, the snapshots and the adaptive step (`next_rows`), the large
+1024 x 8192 configuration, the plain 128 x 512 configuration over its whole
+horizon with the oracle timed beside it, serving latency under overload and
+at a sustainable load, and the CPU oracle's rate on a bounded sample of the
+same workload on this host's cores.
 """
 from __future__ import annotations
 
@@ -34,16 +39,18 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "ion-pack steps/s (push+collision+PIC) FP32 vs FP64 GPU; serving p50/p99 latency"
-WORKLOAD = ("256x1024 ring-electrode grid (0.05 mm), 1e6 packs injected at 500/step weighted to 10 nA, "
-            "m=5000 Da z=+5 CCS 1500 A^2 N2, CIC+Poisson every 10 steps, dt=0.5 ns; timed window at full occupancy")
+WORKLOAD = ("256x1024 ring-electrode grid (0.05 mm), 1e6 packs injected at 500/step over steps 0-1999 weighted "
+            "to 10 nA, m=5000 Da z=+5 CCS 1500 A^2 N2 1e5->200 Pa, CIC+Poisson every 10 steps, dt=0.5 ns; "
+            "timed window after the emission ramp and the warmup steps (full 1e6-pack population)")
 
-# Peak vector rate of MI355X for the arithmetic this kernel issues: 256 CUs x
-# 64 lanes x 2.4 GHz, an FMA counted as two operations (the FP64 vector peak,
-# 78.6 TFLOP/s; unpacked FP32 issues at the same rate -- packed FP32 is not
-# used).  The issue_probe program beside the library measures it: one wave64
-# instruction per SIMD about every 4.1 clocks for v_fma_f32, v_mad_u64_u32 and
-# v_bitop3_b32 and 4.3 for v_fma_f64.
-PEAK_OPS = 256 * 64 * 2 * 2.4e9
+# Published MI355X vector peaks: FP64 78.6 TFLOP/s, FP32 157.3 TFLOP/s (256
+# CUs x 2.4 GHz; an FMA counts as two operations).  The fused step is bound
+# by vector-ALU issue; each form is priced against the peak of its own
+# arithmetic type.  (Measured issue rates: unpacked FP32, 64-bit integer
+# products and three-input XORs issue at the FP64 rate, so the FP32 form's
+# ceiling in practice is the FP64 figure; the published FP32 figure counts
+# packed instructions, which the build disables.)
+PEAK_OPS = {"fp64": 78.6e12, "fp32": 157.3e12}
 
 # Algorithmic operation counts of the fused step kernel: each add, multiply,
 # compare/select, integer xor/add/multiply half, conversion and elementary
@@ -139,48 +146,55 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed steps after the 2000-step emission ramp (the ramp always runs)")
     ap.add_argument("--forms", default="fp64,fp32,hybrid",
                     help="comma list of the forms to time: fp64 (plain FP64 path), fp32 (FP32 math, BF16 tables, "
                          "two-float positions), hybrid (FP32 form with the Langevin branch in 0-1 mm)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-packs", type=int, default=400_000)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=300,
+                    help="steps of the workload's emission ramp the oracle runs for the CPU baseline")
     ap.add_argument("--serving-queries", type=int, default=256)
     ap.add_argument("--serving-rate", type=float, default=20.0)
     ap.add_argument("--serving-steps", type=int, default=2000)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--sustained-queries", type=int, default=48,
+                    help="queries of the serving run at a load the GPU sustains")
+    ap.add_argument("--sustained-rate", type=float, default=4.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-next-rows", action="store_true",
                     help="skip the windows of the masked Poisson solve, the snapshots and the adaptive step")
-    ap.add_argument("--large", action="store_true",
-                    help="also time a window of the large configuration (1024x8192 grid, 1.6e7 packs of ten "
-                         "species, FP32 form) at full occupancy")
-    ap.add_argument("--large-fill-steps", type=int, default=10_000,
-                    help="steps over which the large configuration emits its packs before the timed window")
-    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the window of the large configuration (1024x8192 grid, 1.6e7 packs of ten species)")
+    ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--large-fill", action="store_true",
+                    help="large configuration: run its 1e4-step emission ramp instead of starting from a snapshot")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 128x512 full-horizon run and its oracle timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
 
 
-def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False):
-    import torch
-    from paper_2609_31258_amd import mucite, synth
-    f, ions, srcs, op, _ = synth.config_c2()
-    if langevin:  # hybrid form: aggregated relaxation in the dense first millimetre
-        op.langevin_on, op.lv_z_lo, op.lv_z_hi, op.lv_switch = 1, 0.0, 1e-3, 0.05
-    sim = mucite.Sim(seed=synth.SEED, pack_capacity=srcs[0].n_total, precision=precision, timing=True)
-    sim.setup(f, ions, srcs, op)
+def _say(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _fill(sim, n_steps: int, label: str) -> None:
+    """Untimed stepping in chunks, one progress line per chunk."""
     t0 = time.time()
     done = 0
-    while done < warmup:  # progress lines come from the work itself
-        k = min(500, warmup - done)
+    while done < n_steps:
+        k = min(500, n_steps - done)
         sim.step(k)
         sim.synchronize()
         done += k
-        print(f"[bench] {'fp64' if precision == 0 else 'fp32'}{' hybrid' if langevin else ''} warmup {done}/{warmup} "
-              f"({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
+        _say(f"{label} {done}/{n_steps} ({time.time() - t0:.1f} s)")
+
+
+def _timed(sim, steps: int):
+    """Exactly `steps` steps between two device synchronisations; the
+    tallies and kernel times of the window."""
+    import torch
     sim.reset_timing()
     before = sim.read_tallies()
     torch.cuda.synchronize()
@@ -192,14 +206,32 @@ def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False):
     after = sim.read_tallies()
     tim = sim.read_timing()
     info = sim.info()
+    d = lambda k: after[k] - before[k]
+    return dict(wall=t2 - t1, pack_steps=d("pack_steps"), cand=d("n_cand"), coll=d("n_coll"), exch=d("n_exchange"),
+                langevin=d("n_langevin"), timing=tim, slots=info["n_slots"], active=int(after["class_n"][0]),
+                classes=after["class_n"].tolist(), tallies=after, steps=steps, start_step=info["step"] - steps)
+
+
+def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False):
+    """The workload from step 0: its emission ramp (2000 steps, 500 packs per
+    step), `warmup` more steps, then the timed window on the full population."""
+    from paper_2609_31258_amd import mucite, synth
+    f, ions, srcs, op, _ = synth.config_c2()
+    if langevin:  # hybrid form: aggregated relaxation in the dense first millimetre
+        op.langevin_on, op.lv_z_lo, op.lv_z_hi, op.lv_switch = 1, 0.0, 1e-3, 0.05
+    ramp = srcs[0].n_total // srcs[0].packs_per_step
+    name = ("fp64" if precision == 0 else "fp32") + (" hybrid" if langevin else "")
+    sim = mucite.Sim(seed=synth.SEED, pack_capacity=srcs[0].n_total, precision=precision, timing=True)
+    sim.setup(f, ions, srcs, op)
+    _fill(sim, ramp, f"{name} emission ramp")
+    if warmup:
+        _fill(sim, warmup, f"{name} warmup")
+    r = _timed(sim, steps)
+    r["ramp_steps"] = ramp
     sim.close()
-    wall = t2 - t1
-    ps = after["pack_steps"] - before["pack_steps"]
-    cand = after["n_cand"] - before["n_cand"]
-    coll = after["n_coll"] - before["n_coll"]
-    return dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim, slots=info["n_slots"],
-                active=int(after["class_n"][0]), classes=after["class_n"].tolist(), tallies=after,
-                langevin=after["n_langevin"] - before["n_langevin"], steps=steps)
+    _say(f"{name}: {r['pack_steps'] / r['wall']:.3e} pack-steps/s, {r['wall'] * 1e3 / steps:.3f} ms/step, "
+         f"{r['active']} active")
+    return r
 
 
 def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
@@ -215,66 +247,36 @@ def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
     achieved = nbytes / avg_s if avg_s > 0 else 0.0
     return {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": achieved / HBM_PEAK, "traffic": measured_traffic(traffic_key) if traffic_key else None,
-            "kernel": "deposit (k_deposit + k_deposit_sum)" if kernel == "deposit" else kernel, "avg_launch_ms": avg_s * 1e3,
+            "kernel": "deposit (k_deposit)" if kernel == "deposit" else "k_step", "avg_launch_ms": avg_s * 1e3,
             "launches": launches, "bytes_per_launch": nbytes,
             "issue": measured_issue(traffic_key) if kernel == "step" and traffic_key else None}
 
 
-def run_large(fill_steps: int, steps: int, n_packs: int = 16_000_000):
-    """The large configuration in the FP32 form: emission of all packs over
-    fill_steps steps (untimed), then a timed window of `steps` steps at full
-    occupancy with space charge every 5 steps."""
-    import torch
-    from paper_2609_31258_amd import mucite, synth
-    f, ions, srcs, op, meta = synth.config_c5(n_packs=n_packs, emit_steps=fill_steps)
-    sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=1, timing=True)
-    sim.setup(f, ions, srcs, op)
-    t0 = time.time()
-    done = 0
-    while done < fill_steps:
-        k = min(500, fill_steps - done)
-        sim.step(k)
-        sim.synchronize()
-        done += k
-        print(f"[bench] large fill {done}/{fill_steps} ({time.time() - t0:.1f} s)", file=sys.stderr, flush=True)
-    sim.reset_timing()
-    before = sim.read_tallies()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
-    t2 = time.perf_counter()
-    after = sim.read_tallies()
-    tim = sim.read_timing()
-    sim.close()
-    wall = t2 - t1
-    ps = after["pack_steps"] - before["pack_steps"]
-    coll = after["n_coll"] - before["n_coll"]
-    cand = after["n_cand"] - before["n_cand"]
-    alpha = sum(4 * synth.M_N2_DA * (i.mass_da / i.n_atoms) / (synth.M_N2_DA + i.mass_da / i.n_atoms) ** 2
-                for i in ions) / len(ions)
-    r = dict(wall=wall, pack_steps=ps, cand=cand, coll=coll, timing=tim)
-    return {"workload": "1024x8192 grid, 1.6e7 packs of ten species (200-5e4 Da, Arrhenius), 50 nA, "
-                        "SC every 5 steps, dt=0.25 ns, FP32 form (BF16 tables)",
-            "fill_steps": fill_steps, "steps": steps, "value": ps / wall, "unit": "pack-steps/s",
-            "ms_per_step": wall * 1e3 / steps, "active": int(after["class_n"][0]),
-            "classes": after["class_n"].tolist(), "collisions_per_s": coll / wall,
-            "candidates_per_pack_step": cand / max(ps, 1), "kernel_ms": tim["ms"],
-            "roofline": roofline(r, "none", alpha)}
-
-
 def roofline(r, precision: str, alpha: float):
+    """Vector-ALU roofline of the fused step: algorithmic operations per
+    launch over the launch's average HIP-event duration, against the
+    published vector peak of the form's arithmetic type."""
     ms = r["timing"]["ms"]["step"]
     launches = max(r["timing"]["launches"]["step"], 1)
     avg_s = ms / 1e3 / launches
     ops = (r["pack_steps"] * OPS_PACK_STEP + r["cand"] * OPS_CANDIDATE +
-           r["coll"] * (OPS_ACCEPTED + alpha * OPS_EXCHANGE))
+           r["coll"] * OPS_ACCEPTED + r.get("exch", alpha * r["coll"]) * OPS_EXCHANGE)
     ops_per_launch = ops / launches
     achieved = ops_per_launch / avg_s
-    return {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12, "unit": "Top/s",
-            "frac": achieved / PEAK_OPS, "traffic": measured_traffic(precision),
+    peak = PEAK_OPS[precision if precision in PEAK_OPS else "fp32"]
+    return {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": measured_traffic(precision),
             "kernel": "k_step (fused push/classify/collide)", "avg_launch_ms": avg_s * 1e3, "launches": launches,
             "ops_per_launch": ops_per_launch, "issue": measured_issue(precision)}
+
+
+def default_alpha() -> float:
+    """Internal-exchange probability of the workload's ion (default rule
+    4 mg ma / (mg + ma)^2, ma = m / n_atoms)."""
+    from paper_2609_31258_amd import synth
+    _, ions, _, _, _ = synth.config_c2()
+    mg, ma = synth.M_N2_DA, ions[0].mass_da / ions[0].n_atoms
+    return 4 * mg * ma / (mg + ma) ** 2
 
 
 def precision_report(t64, t32):
@@ -299,35 +301,143 @@ def precision_report(t64, t32):
     return out
 
 
-def default_alpha() -> float:
-    """Internal-exchange probability of the workload's ion (default rule
-    4 mg ma / (mg + ma)^2, ma = m / n_atoms)."""
-    from paper_2609_31258_amd import synth
-    _, ions, _, _, _ = synth.config_c2()
-    mg, ma = synth.M_N2_DA, ions[0].mass_da / ions[0].n_atoms
-    return 4 * mg * ma / (mg + ma) ** 2
-
-
-def cpu_baseline(n_packs: int, n_steps: int):
-    """The oracle as it stands, on this host's cores, on a bounded sample:
-    n_packs packs in the full-occupancy state of the same workload (packs
-    within 0.3 mm of the injection plane, thermal about the gas flow),
-    n_steps steps including the space-charge updates."""
+def cpu_baseline(n_steps: int):
+    """The oracle as it stands, on this host's cores, on a bounded sample of
+    the same workload: its first n_steps steps from step 0 (emission at 500
+    packs per step, the space-charge update every 10 steps), all of it timed."""
     from oracle.binding import OracleSim, num_threads
     from paper_2609_31258_amd import synth
-    f, ions, op, snap = full_occupancy_snapshot(n_packs)
+    f, ions, srcs, op, _ = synth.config_c2()
     o = OracleSim(synth.SEED)
-    o.setup(f, ions, [], op)
-    o.write_packs(snap)
+    o.setup(f, ions, srcs, op)
     t0 = time.perf_counter()
-    o.step(n_steps)
+    done = 0
+    while done < n_steps:
+        k = min(50, n_steps - done)
+        o.step(k)
+        done += k
+        _say(f"oracle (cpu baseline) {done}/{n_steps} steps ({time.perf_counter() - t0:.1f} s)")
     wall = time.perf_counter() - t0
     T = o.read_tallies()
-    cores = num_threads()
-    return {"value": n_packs * n_steps / wall, "unit": "pack-steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_packs} packs at full-occupancy state of the same workload, {n_steps} steps "
-                      f"({(n_steps + 9) // 10} space-charge updates), {wall:.1f} s",
-            "collisions_per_s": T["n_coll"] / wall}
+    o.close()
+    ps = sum(min(n, srcs[0].n_total // srcs[0].packs_per_step) * srcs[0].packs_per_step for n in range(1, n_steps + 1))
+    return {"value": ps / wall, "unit": "pack-steps/s", "cores": num_threads(), "kind": "oracle",
+            "sample": f"the workload's first {n_steps} steps from step 0 (emission ramp to "
+                      f"{n_steps * srcs[0].packs_per_step} packs, {(n_steps + 9) // 10} space-charge updates), "
+                      f"{ps:.3e} pack-steps in {wall:.1f} s",
+            "collisions_per_s": T["n_coll"] / wall, "wall_s": wall}
+
+
+def run_c1_full():
+    """The plain 128x512 configuration over its whole horizon (1e4 packs,
+    2000 steps of 1 ns, collisions on, no space charge) on the GPU (FP64) and
+    in the oracle on this host's cores; whole-run wall times."""
+    import torch
+    from oracle.binding import OracleSim, num_threads
+    from paper_2609_31258_amd import mucite, synth
+    f, ions, srcs, op, meta = synth.config_c1()
+    n, steps = meta["burst"], meta["steps"]
+    g = mucite.Sim(seed=synth.SEED, pack_capacity=n, precision=0, timing=True)
+    g.setup(f, ions, srcs, op)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.inject(0, n)
+    g.step(steps)
+    g.synchronize()
+    wall_g = time.perf_counter() - t0
+    tg = g.read_tallies()
+    g.close()
+    _say(f"128x512 full run on the GPU: {wall_g:.3f} s")
+    o = OracleSim(synth.SEED)
+    o.setup(f, ions, srcs, op)
+    t0 = time.perf_counter()
+    o.inject(0, n)
+    for k in range(0, steps, 500):
+        o.step(500)
+        _say(f"128x512 full run, oracle {k + 500}/{steps} ({time.perf_counter() - t0:.1f} s)")
+    wall_o = time.perf_counter() - t0
+    to = o.read_tallies()
+    o.close()
+    ps = n * steps
+    return {"workload": "128x512 grid, 1e4 packs of 500 Da z=+1 at step 0, 2000 x 1 ns, collisions on, "
+                        "no space charge, FP64",
+            "gpu": {"wall_s": wall_g, "value": tg["pack_steps"] / wall_g, "unit": "pack-steps/s",
+                    "collisions": int(tg["n_coll"]), "classes": tg["class_n"].tolist()},
+            "oracle": {"wall_s": wall_o, "value": ps / wall_o, "unit": "pack-steps/s", "cores": num_threads(),
+                       "collisions": int(to["n_coll"]), "classes": to["class_n"].tolist()},
+            "speedup": wall_o / wall_g}
+
+
+def c5_snapshot(f, ions, n: int, seed: int, weights):
+    """The large configuration's packs after its emission ramp, as a seeded
+    snapshot: the ten species in equal shares (round robin), positions within
+    3 mm of the injection plane and 0.3 mm of the axis, velocities thermal
+    about the gas flow, internal energies of an Einstein solid at 300-1500 K."""
+    import numpy as np
+    from paper_2609_31258_amd import synth
+    snap = synth.pack_snapshot(n, f, seed=seed, z_hi=3e-3, r_hi=3e-4, v_sigma=50.0, v_drift=300.0)
+    tag = (np.arange(n) % len(ions)).astype(np.int32)
+    snap["tag"] = tag
+    snap["w"] = np.asarray(weights, dtype=np.float64)[tag]
+    dof = np.array([3 * i.n_atoms - 6 for i in ions], dtype=np.float64)[tag]
+    snap["e_int"] = dof * 1.380649e-23 * 300.0 * np.random.default_rng(seed + 1).uniform(0.3, 1.5, n)
+    return snap
+
+
+def run_large(steps: int, fill: bool, n_packs: int = 16_000_000):
+    """The large configuration in the FP32 form (1024x8192 grid, 1.6e7 packs
+    of ten species, space charge every 5 steps): a timed window of `steps`
+    steps on the full population, started from a seeded snapshot of the
+    post-ramp state (or after the 1e4-step emission ramp with --large-fill);
+    and the oracle's rate on a 1e5-pack slice of the same snapshot (push,
+    collisions and dissociation; the oracle's direct O(nz^2) sine sums take
+    minutes per space-charge update on this grid, so the slice runs without
+    them)."""
+    from oracle.binding import OracleSim, num_threads
+    from paper_2609_31258_amd import mucite, synth
+    f, ions, srcs, op, meta = synth.config_c5(n_packs=n_packs)
+    # each species' pack weight: its share of the current over its packs per step
+    w = [src.current_a * op.dt / (ion.charge_z * 1.602176634e-19) / src.packs_per_step for src, ion in zip(srcs, ions)]
+    sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=1, timing=True)
+    if fill:
+        sim.setup(f, ions, srcs, op)
+        _fill(sim, meta["emit_steps"], "large emission ramp")
+        start = "after its 1e4-step emission ramp"
+    else:
+        sim.setup(f, ions, [], op)
+        snap = c5_snapshot(f, ions, n_packs, synth.SEED, w)
+        sim.write_packs(snap)
+        del snap
+        _fill(sim, 5, "large warmup")
+        start = "from a seeded snapshot of the post-ramp state (3 mm x 0.3 mm, ten species)"
+    r = _timed(sim, steps)
+    sim.close()
+    ps = r["pack_steps"]
+    alpha = sum(4 * synth.M_N2_DA * (i.mass_da / i.n_atoms) / (synth.M_N2_DA + i.mass_da / i.n_atoms) ** 2
+                for i in ions) / len(ions)
+    _say(f"large: {ps / r['wall']:.3e} pack-steps/s, {r['wall'] * 1e3 / steps:.3f} ms/step")
+    # oracle slice
+    n_cpu, cpu_steps = 100_000, 10
+    o = OracleSim(synth.SEED)
+    op.sc_on = 0
+    o.setup(f, ions, [], op)
+    o.write_packs(c5_snapshot(f, ions, n_cpu, synth.SEED + 3, w))
+    t0 = time.perf_counter()
+    o.step(cpu_steps)
+    wall_o = time.perf_counter() - t0
+    to = o.read_tallies()
+    o.close()
+    _say(f"large: oracle slice {n_cpu * cpu_steps / wall_o:.3e} pack-steps/s ({wall_o:.1f} s)")
+    return {"workload": "1024x8192 grid, 1.6e7 packs of ten species (200-5e4 Da, Arrhenius), 50 nA, "
+                        "SC every 5 steps, dt=0.25 ns, FP32 form (BF16 tables); window " + start,
+            "steps": steps, "value": ps / r["wall"], "unit": "pack-steps/s",
+            "ms_per_step": r["wall"] * 1e3 / steps, "active": r["active"], "classes": r["classes"],
+            "collisions_per_s": r["coll"] / r["wall"], "candidates_per_pack_step": r["cand"] / max(ps, 1),
+            "kernel_ms": r["timing"]["ms"], "roofline": roofline(r, "fp32", alpha),
+            "cpu_slice": {"value": n_cpu * cpu_steps / wall_o, "unit": "pack-steps/s", "cores": num_threads(),
+                          "kind": "oracle", "sample": f"{n_cpu} packs of the same snapshot, {cpu_steps} steps, "
+                                                      f"no space-charge update, {wall_o:.1f} s",
+                          "collisions_per_s": to["n_coll"] / wall_o}}
 
 
 def serving_query(f, q, steps: int):
@@ -347,7 +457,7 @@ def serving_query(f, q, steps: int):
 def full_occupancy_snapshot(n_packs: int):
     """The workload's full-occupancy state as a pack snapshot: n_packs packs
     within 0.3 mm of the injection plane, thermal about the gas flow, at the
-    source's pack weight (the state the emission ramp reaches)."""
+    source's pack weight."""
     from paper_2609_31258_amd import synth
     f, ions, srcs, op, _ = synth.config_c2()
     snap = synth.pack_snapshot(n_packs, f, seed=synth.SEED, z_hi=3e-4, r_hi=3e-4, v_sigma=22.0, v_drift=300.0,
@@ -356,7 +466,7 @@ def full_occupancy_snapshot(n_packs: int):
 
 
 def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_capacity: int = 0, **op_changes):
-    """One timed window of the full-occupancy state with some operating
+    """One timed window of a full-population snapshot with some operating
     fields changed (the next rows: masked Poisson, snapshots, adaptive step).
     The first step (and with it the first space-charge update, where the
     capacitance matrix of the masked solve is built) is timed on its own."""
@@ -376,41 +486,32 @@ def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_
     first = time.perf_counter() - t0
     sim.step(9)
     sim.synchronize()
-    sim.reset_timing()
-    before, t_sim0 = sim.read_tallies(), sim.info()["time"]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sim.step(steps)
-    sim.synchronize()
-    t2 = time.perf_counter()
-    after, info = sim.read_tallies(), sim.info()
-    tim = sim.read_timing()
+    t_sim0 = sim.info()["time"]
+    r = _timed(sim, steps)
+    sim_time = sim.info()["time"] - t_sim0
     n_samples = len(sim.read_samples()) if sample_capacity else 0
     sim.close()
-    wall = t2 - t1
-    ps = after["pack_steps"] - before["pack_steps"]
-    sim_time = info["time"] - t_sim0
+    tim = r["timing"]
+    wall = r["wall"]
     updates = max(tim["launches"]["poisson"], 1)
-    print(f"[bench] {name}: {ps / wall:.3e} pack-steps/s, {wall * 1e3 / steps:.3f} ms per step", file=sys.stderr,
-          flush=True)
-    return {"value": ps / wall, "unit": "pack-steps/s", "ms_per_step": wall * 1e3 / steps, "steps": steps,
-            "first_step_s": first, "mean_dt_s": sim_time / steps, "simulated_s_per_wall_s": sim_time / wall,
-            "space_charge_updates": tim["launches"]["poisson"],
+    _say(f"{name}: {r['pack_steps'] / wall:.3e} pack-steps/s, {wall * 1e3 / steps:.3f} ms per step")
+    return {"value": r["pack_steps"] / wall, "unit": "pack-steps/s", "ms_per_step": wall * 1e3 / steps,
+            "steps": steps, "first_step_s": first, "mean_dt_s": sim_time / steps,
+            "simulated_s_per_wall_s": sim_time / wall, "space_charge_updates": tim["launches"]["poisson"],
             "update_ms": (tim["ms"]["deposit"] + tim["ms"]["poisson"] + tim["ms"]["field"]) / updates,
             "samples": n_samples, "kernel_ms": tim["ms"]}
 
 
 def run_next_rows(steps: int, n_packs: int = 1_000_000):
-    """The next rows on the full-occupancy state of the workload, FP32 form:
+    """The next rows on a full-population snapshot of the workload, FP32 form:
     a plain window, the masked Poisson solve (potential zero on the ring
     electrodes' mask nodes), full-population snapshots every 20 steps, and
     the adaptive step of Eq. 1 with explicit collisions and on the hybrid
     branch (largest step 2 ns, the Langevin cap)."""
-    from paper_2609_31258_amd import synth
     f, _, _, _ = full_occupancy_snapshot(1)
     g = f.grid
     mask = f.mask.reshape(g.nz, g.nr)
-    out = {"state": f"{n_packs} packs at the full-occupancy state of the workload (FP32 form, BF16 tables)"}
+    out = {"state": f"{n_packs} packs, seeded snapshot of the full population (FP32 form, BF16 tables)"}
     out["plain"] = run_variant("plain", steps, n_packs)
     out["masked_poisson"] = run_variant("masked poisson", steps, n_packs, sc_mask=1)
     out["masked_poisson"]["mask_nodes"] = int(mask[1:-1, :-1].sum())
@@ -424,7 +525,8 @@ def run_next_rows(steps: int, n_packs: int = 1_000_000):
     return out
 
 
-def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budget_gib: float, max_resident: int):
+def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budget_gib: float, max_resident: int,
+                label: str = "serving"):
     """Poisson arrivals of design queries into one server (shared 256x1024 field
     set, FP32 form); latency = completion - submission on the server clock."""
     from paper_2609_31258_amd import mucite, synth
@@ -440,14 +542,13 @@ def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budg
             time.sleep(delay)
         ion, src, op = serving_query(f, q, steps)
         ids.append(srv.submit(ion, src, op, n_steps=steps, seed=q["seed"]))
-        if (k + 1) % 64 == 0:
-            print(f"[bench] serving submitted {k + 1}/{n_queries}", file=sys.stderr, flush=True)
+        if (k + 1) % 16 == 0:
+            _say(f"{label} submitted {k + 1}/{n_queries}")
     res = []
     for k, i in enumerate(ids):
         res.append(srv.wait(i, 3600.0))
-        if (k + 1) % 64 == 0:
-            print(f"[bench] serving completed {k + 1}/{n_queries} ({time.perf_counter() - t0:.1f} s)",
-                  file=sys.stderr, flush=True)
+        if (k + 1) % 16 == 0:
+            _say(f"{label} completed {k + 1}/{n_queries} ({time.perf_counter() - t0:.1f} s)")
     st = srv.stats()
     srv.close()
     lat = [r["t_done"] - r["t_submit"] for r in res if r["state"] == mucite.Q_DONE]
@@ -455,10 +556,14 @@ def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budg
     pct = lambda p: lat[min(len(lat) - 1, int(math.ceil(p * len(lat))) - 1)] if lat else None
     span = max(r["t_done"] for r in res) - min(r["t_submit"] for r in res)
     ps = sum(r["tallies"]["pack_steps"] for r in res if r["state"] == mucite.Q_DONE)
+    # offered load: the work that arrived per second of arrivals, over the
+    # rate at which the GPU served it while busy
+    service_rate = ps / st["busy_s"] if st["busy_s"] > 0 else None
+    arrival_span = qs[-1]["arrival_s"] if len(qs) > 1 else None
     return {"queries": n_queries, "completed": len(lat), "arrival_rate_hz": rate_hz, "steps_per_query": steps,
             "p50_latency_s": pct(0.50), "p99_latency_s": pct(0.99), "mean_latency_s": sum(lat) / len(lat),
             "throughput_pack_steps_per_s": ps / span, "pack_steps": ps, "span_s": span,
-            "offered_load": (ps / (ps / st["busy_s"])) / (qs[-1]["arrival_s"] + 1e-9) if st["busy_s"] > 0 else None,
+            "offered_load": (ps / arrival_span) / service_rate if service_rate and arrival_span else None,
             "max_resident_seen": st["max_resident_seen"], "pool_peak_bytes": st["pool_peak"],
             "dtype": "f32 (BF16 tables)" if precision == 1 else "f64"}
 
@@ -470,13 +575,13 @@ def copy_calibration():
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(f"[bench] copy calibration: {n} bytes read, {n} bytes written", file=sys.stderr, flush=True)
+    _say(f"copy calibration: {n} bytes read, {n} bytes written")
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "the path runs on one GPU: multi-GPU runs are not implemented"}))
+        print(json.dumps({"error": "this build runs on one GPU: --gpus above 1 is not supported (no multi-GPU path)"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -502,38 +607,44 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if main_key == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "grid": [256, 1024], "packs": r["slots"], "active": r["active"],
-                   "sc_every": 10, "dt_s": 0.5e-9, "precision": main_key},
+                   "ramp_steps": r["ramp_steps"], "first_timed_step": r["start_step"], "sc_every": 10,
+                   "dt_s": 0.5e-9, "precision": main_key},
         "roofline": hbm_roofline(r, "fp32", "step", "hybrid") if main_key == "hybrid" else roofline(r, main_key, default_alpha()),
         "collisions_per_s": r["coll"] / r["wall"],
         "candidates_per_pack_step": r["cand"] / max(r["pack_steps"], 1),
         "kernel_ms": r["timing"]["ms"],
     }
+    if main_key != "hybrid":
+        out["deposit_roofline"] = hbm_roofline(r, main_key, "deposit", "deposit_" + main_key)
     if "fp32" in res and main_key == "fp64":
         q = res["fp32"]
         out["fp32_form"] = {"value": q["pack_steps"] / q["wall"], "unit": "pack-steps/s",
                             "ms_per_step": q["wall"] * 1e3 / args.steps, "dtype": "f32 (BF16 tables)",
-                            "speedup_vs_fp64": (q["pack_steps"] / q["wall"]) / value,
+                            "active": q["active"], "speedup_vs_fp64": (q["pack_steps"] / q["wall"]) / value,
                             "roofline": roofline(q, "fp32", default_alpha()), "collisions_per_s": q["coll"] / q["wall"],
-                            "error_vs_fp64": precision_report(r["tallies"], q["tallies"])}
-    if "fp32" in res:
-        out["deposit_roofline_fp32"] = hbm_roofline(res["fp32"], "fp32", "deposit", "deposit_fp32")
+                            "deposit_roofline": hbm_roofline(q, "fp32", "deposit", "deposit_fp32"),
+                            "kernel_ms": q["timing"]["ms"], "error_vs_fp64": precision_report(r["tallies"], q["tallies"])}
     if "hybrid" in res and main_key != "hybrid":
         h = res["hybrid"]
         ref = res.get("fp32")
         out["hybrid_form"] = {"value": h["pack_steps"] / h["wall"], "unit": "pack-steps/s",
                               "ms_per_step": h["wall"] * 1e3 / args.steps, "dtype": "f32 (BF16 tables)",
-                              "langevin_fraction": h["langevin"] / max(h["pack_steps"], 1),
+                              "active": h["active"], "langevin_fraction": h["langevin"] / max(h["pack_steps"], 1),
                               "speedup_vs_explicit_fp32": (h["pack_steps"] / h["wall"]) / (ref["pack_steps"] / ref["wall"])
                               if ref else None,
                               "roofline": hbm_roofline(h, "fp32", "step", "hybrid"), "kernel_ms": h["timing"]["ms"]}
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
+    if not args.no_c1:
+        out["c1_full"] = run_c1_full()
+    if not args.no_large:
+        out["large"] = run_large(args.large_steps, args.large_fill)
     if not args.no_next_rows:
         out["next_rows"] = run_next_rows(args.steps)
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)
-    if args.large:
-        out["large"] = run_large(args.large_fill_steps, args.large_steps)
-    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_packs, args.cpu_steps)
+        out["serving_sustained"] = run_serving(args.sustained_queries, args.sustained_rate, args.serving_steps, 1,
+                                               args.serving_budget_gib, 64, label="serving (sustained)")
     print(json.dumps(out), flush=True)
 
 
