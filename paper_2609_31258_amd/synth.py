@@ -212,6 +212,26 @@ def config_c1t(n_packs: int = 10_000):
     return f, [ion], [src], op, {"steps": 100_000, "burst": n_packs}
 
 
+def config_c1x(n_transmit: int = 16_000, n_ring: int = 8_000):
+    """Terminal-event variant of the low-pressure fields (1000 -> 20 Pa, ring
+    inner radius 0.25 mm) on a narrow 20 x 512 grid (R = 0.95 mm), built so
+    that every terminal class occurs within about 1000 steps: a burst
+    source 1.5 mm before the detector plane (packs cross it within the
+    detector radius of 0.3 mm -> transmitted, outside it -> axial, or leave
+    through r = R -> radial) and a burst source between the last two rings
+    (electrode hits on the last ring).  Ion: 500 Da, z = +1, 200 A^2,
+    150 atoms, Arrhenius dissociation with A = 1e12 1/s and Ea = 0.42 eV
+    (about 1e5 1/s at 300 K, so survival yields are well inside (0, 1));
+    RF 100 V at 1 MHz; dt = 5 ns (lambda dt <= 0.05)."""
+    f = ring_fields(20, 512, p0=1000.0, p1=20.0, r_in=2.5e-4)
+    ion = Ion(500.0, 1, 200e-20, 150, act_kind=2, act_p1=1e12, act_p2=0.42)
+    srcs = [Source(kind=0, ion=0, weight=1.0, n_total=n_transmit, sigma_r=3e-4, r_trunc=9e-4, z_inj=24.0e-3),
+            Source(kind=0, ion=0, weight=0.5, n_total=n_ring, sigma_r=3e-4, r_trunc=9e-4, z_inj=21.3e-3)]
+    op = Operating(dt=5e-9, v_rf=100.0, f_rf=1e6, z_det=f.grid.L, r_det=3e-4, sc_on=0,
+                   exit_bin_dt=1e-7, n_exit_bins=100)
+    return f, [ion], srcs, op, {"steps": 1200, "bursts": [n_transmit, n_ring]}
+
+
 def config_c2(n_packs: int = 1_000_000, packs_per_step: int = 500, current_a: float = 10e-9):
     """256x1024 grid with space charge: packs injected continuously at
     packs_per_step, weighted to a 10 nA current; m = 5000 Da, z = +5,

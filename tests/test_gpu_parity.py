@@ -115,9 +115,9 @@ def test_single_step_fp64_within_1e6(cfg):
     o.step(1)
     r = step_errors(g.read_packs(), o.read_packs(), f.grid.dr, thermal_speed(), snap["h"])
     _say(f"  max dx {r['max_dx']:.2e} dv {r['max_dv']:.2e} de {r['max_de']:.2e} dh {r['max_dh']:.2e} "
-         f"status flips {int((~r['same_status']).sum())}")
+         f"status flips {int((~r['same_status']).sum())}, packs outside 1e-6: {int((~r['ok']).sum())}")
     assert r["same_status"].all()
-    assert r["ok"].sum() >= n - max(1, n // 10_000)
+    assert r["ok"].all()  # every pack, as the single-step bar asks
     ta, tb = g.read_tallies(), o.read_tallies()
     assert np.array_equal(ta["class_n"], tb["class_n"])
     assert np.array_equal(ta["class_w"], tb["class_w"])
