@@ -405,6 +405,48 @@ int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out);
 int32_t mc_reset_timing(mc_ctx *ctx);
 
 /* ------------------------------------------------------------------------- */
+/* Stand-alone CIC deposit on caller-owned device arrays.                     */
+/* ------------------------------------------------------------------------- */
+/* Packs for the stand-alone deposit: device arrays of length n (device
+ * memory of the current HIP device; the caller keeps ownership).  Positions
+ * in m (r = sqrt(x^2 + y^2)), charges in units of 2^-32 e; packs whose
+ * status is not MC_ACTIVE are skipped, as are packs with a non-finite
+ * position.  With n == 0 the pointers may be NULL. */
+typedef struct mc_cic_packs {
+    int64_t n;
+    const double *x, *y, *z;
+    const int64_t *q;
+    const int32_t *status;
+} mc_cic_packs;
+
+/* Cloud-in-cell deposit of the packs' charges onto the node grid, the
+ * deposit step of "Axisymmetric PIC space charge update" exactly as a
+ * simulation's space-charge update does it: each pack's int64 charge is
+ * split bilinearly in (r, z) onto the four nodes of its cell, the split
+ * rounded so the four parts sum to the charge exactly (cell index clamped
+ * to the grid).  q_out: device int64 array of grid->nz * grid->nr, row-major
+ * [nz][nr], overwritten with the deposited charge (2^-32 e); the result does
+ * not depend on the order of the packs.  Enqueued on `stream` (a
+ * hipStream_t; NULL = the default stream); the call allocates its scratch
+ * (copies of the grid for the blocks' flushes) with hipMalloc, waits for
+ * the stream and frees it.  Errors: MC_EINVAL (NULL pointers, grid < 3 x 3
+ * or non-positive spacing, n < 0), MC_ENOMEM, MC_EDEVICE. */
+int32_t mc_deposit_cic(const mc_cic_packs *packs, const mc_grid *grid, int64_t *q_out, void *stream);
+
+/* The deposit of mc_deposit_cic for callers that cannot allocate device
+ * memory -- code being recorded into a HIP graph, tight serving loops,
+ * harnesses that forbid hipMalloc: no allocation and no host
+ * synchronisation (asynchronous on `stream`).  Its scratch is a fixed
+ * library-owned device array of 8 MiB + 16 B per GPU, held until the
+ * process ends, so the grid may hold at most 1 048 576 nodes (MC_EINVAL
+ * beyond; 16 grid copies up to 65 536 nodes, fewer above).  Every call on a
+ * GPU uses that GPU's one array and leaves it cleared for the next:
+ * concurrent calls on one GPU (overlapping on different streams) race and
+ * must be serialised by the caller.  Results are bit-identical to
+ * mc_deposit_cic.  Errors: MC_EINVAL, MC_EDEVICE. */
+int32_t mc_deposit_cic_noalloc(const mc_cic_packs *packs, const mc_grid *grid, int64_t *q_out, void *stream);
+
+/* ------------------------------------------------------------------------- */
 /* Serving: continuous batching of design queries over shared field tables.   */
 /*                                                                           */
 /* A server owns one field set (grid, potentials, gas, mask, hit distance and */

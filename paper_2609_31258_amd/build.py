@@ -2,8 +2,9 @@
 
     python -m paper_2609_31258_amd.build
 
-compiles csrc/mc_runtime.hip (single simulations) and csrc/mc_server.hip (serving),
-which include the kernels, with hipcc into
+compiles csrc/mc_runtime.hip (single simulations), csrc/mc_server.hip (serving)
+and csrc/mc_deposit_op.hip (the stand-alone deposit), which include the
+kernels, with hipcc into
 paper_2609_31258_amd/libmucite.so.  Flags: -O3, FMA contraction on (the
 kernels turn it off locally where results must be bit-reproducible), packed
 FP32 instructions disabled.
@@ -15,7 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmucite.so")
-SOURCES = [os.path.join(HERE, "csrc", "mc_runtime.hip"), os.path.join(HERE, "csrc", "mc_server.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f) for f in ("mc_runtime.hip", "mc_server.hip", "mc_deposit_op.hip")]
 ARCH = os.environ.get("MUCITE_ARCH", "gfx950")
 
 

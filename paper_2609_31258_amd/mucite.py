@@ -133,6 +133,11 @@ class ServerStats(C.Structure):
                                    "pack_steps", "max_resident_seen")] + [("busy_s", F64), ("wall_s", F64)]
 
 
+class CicPacks(C.Structure):
+    _fields_ = [("n", I64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p), ("q", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
 Q_PENDING, Q_RUNNING, Q_DONE, Q_FAILED = 0, 1, 2, 3
 
 EXIT_DTYPE = np.dtype([(f, np.int64 if t is I64 else (np.int32 if t is I32 else np.float64))
@@ -169,6 +174,8 @@ _SIGS = {
     "mc_read_hit": (I32, [C.c_void_p, PU8]),
     "mc_read_timing": (I32, [C.c_void_p, C.POINTER(Timing)]),
     "mc_reset_timing": (I32, [C.c_void_p]),
+    "mc_deposit_cic": (I32, [C.POINTER(CicPacks), C.POINTER(Grid), C.c_void_p, C.c_void_p]),
+    "mc_deposit_cic_noalloc": (I32, [C.POINTER(CicPacks), C.POINTER(Grid), C.c_void_p, C.c_void_p]),
     "mc_server_create": (I32, [C.POINTER(ServerOptions), C.POINTER(Grid), C.POINTER(FieldTables),
                                C.POINTER(C.c_void_p)]),
     "mc_server_destroy": (None, [C.c_void_p]),
@@ -569,6 +576,31 @@ class Server:
         st = ServerStats()
         self._chk(self.L.mc_server_get_stats(self._h, C.byref(st)), "mc_server_get_stats")
         return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+
+def deposit_cic(x, y, z, q, status, grid, out, *, noalloc: bool = False, stream=None) -> None:
+    """CIC deposit of device tensors (x, y, z float64; q int64; status int32;
+    one GPU) onto `out` (int64 tensor of nz * nr on the same device) through
+    mc_deposit_cic, or mc_deposit_cic_noalloc with noalloc=True.  `grid` has
+    nr, nz, dr, dz.  Runs on `stream` (a torch stream; default: the current
+    one)."""
+    import torch
+    n = int(x.numel())
+    for t, dt in ((x, torch.float64), (y, torch.float64), (z, torch.float64), (q, torch.int64),
+                  (status, torch.int32)):
+        if t.dtype != dt or not t.is_contiguous() or t.numel() != n or not t.is_cuda:
+            raise ValueError("deposit_cic: x, y, z float64, q int64, status int32, contiguous, on the GPU, same length")
+    if out.dtype != torch.int64 or not out.is_contiguous() or out.numel() != grid.nr * grid.nz:
+        raise ValueError("deposit_cic: out must be a contiguous int64 tensor of nz * nr")
+    L = load_library()
+    P = CicPacks(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), q.data_ptr(), status.data_ptr())
+    G = Grid(grid.nr, grid.nz, grid.dr, grid.dz)
+    s = (stream or torch.cuda.current_stream(out.device)).cuda_stream
+    fn = L.mc_deposit_cic_noalloc if noalloc else L.mc_deposit_cic
+    with torch.cuda.device(out.device):
+        rc = fn(C.byref(P), C.byref(G), C.c_void_p(out.data_ptr()), C.c_void_p(s))
+    if rc != MC_OK:
+        raise MucateError(rc, fn.__name__, "deposit failed")
 
 
 def declared_symbols(header: str = HEADER):

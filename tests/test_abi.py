@@ -21,10 +21,11 @@ def test_library_exports_every_declared_symbol():
 def test_binding_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "sz.c"
     src.write_text('#include "mucite.h"\n#include <stdio.h>\n'
-                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mc_options), '
+                   'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(mc_options), '
                    'sizeof(mc_grid), sizeof(mc_field_tables), sizeof(mc_ion), sizeof(mc_source), '
                    'sizeof(mc_operating), sizeof(mc_packs), sizeof(mc_tallies), sizeof(mc_exit_rec), '
-                   'sizeof(mc_info), sizeof(mc_timing), sizeof(mc_sample_rec), sizeof(mc_tally_layout));'
+                   'sizeof(mc_info), sizeof(mc_timing), sizeof(mc_sample_rec), sizeof(mc_tally_layout), '
+                   'sizeof(mc_cic_packs));'
                    'return 0;}\n')
     inc = os.path.join(os.path.dirname(mucite.HERE), "include")
     exe = tmp_path / "sz"
@@ -32,7 +33,7 @@ def test_binding_struct_layouts_match_the_header(tmp_path):
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     want = [C.sizeof(s) for s in (mucite.Options, mucite.Grid, mucite.FieldTables, mucite.Ion, mucite.Source,
                                   mucite.Operating, mucite.Packs, mucite.Tallies, mucite.ExitRec, mucite.Info,
-                                  mucite.Timing, mucite.SampleRec, mucite.TallyLayout)]
+                                  mucite.Timing, mucite.SampleRec, mucite.TallyLayout, mucite.CicPacks)]
     assert got == want
 
 
@@ -55,6 +56,8 @@ def test_null_arguments_are_rejected_without_a_device():
     assert L.mc_step(None, 1) == mucite.MC_EINVAL
     assert L.mc_read_tallies(None, None) == mucite.MC_EINVAL
     assert L.mc_get_tally_layout(None, None) == mucite.MC_EINVAL
+    assert L.mc_deposit_cic(None, None, None, None) == mucite.MC_EINVAL
+    assert L.mc_deposit_cic_noalloc(None, None, None, None) == mucite.MC_EINVAL
     L.mc_destroy(None)
     assert L.mc_server_submit(None, None, None) == mucite.MC_EINVAL
     assert L.mc_server_poll(None, 1, None) == mucite.MC_EINVAL
