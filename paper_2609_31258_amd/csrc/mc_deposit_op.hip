@@ -112,8 +112,8 @@ int32_t launch_deposit(const mc_cic_packs *packs, const mc_grid *grid, int64_t *
         k_deposit<P64><<<nb, kDepositThreads, 0, stream>>>(a);
     }
     // every node of the output written: the sums over the range, zero elsewhere
-    k_deposit_sum<<<(unsigned)((nn + 255) / 256), 256, 0, stream>>>(reinterpret_cast<unsigned long long *>(q_out),
-                                                                      copies, ncopies, nn, range, range + 2);
+    k_deposit_sum<<<(unsigned)std::min<int64_t>((nn + 255) / 256, kDepositSumBlocks), 256, 0, stream>>>(
+        reinterpret_cast<unsigned long long *>(q_out), copies, ncopies, nn, range, nullptr, range + 2);
     return hipGetLastError() == hipSuccess ? MC_OK : MC_EDEVICE;
 }
 

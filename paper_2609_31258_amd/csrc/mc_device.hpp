@@ -209,19 +209,34 @@ __device__ __forceinline__ Cell<T> locate(T r, T z, T inv_dr, T inv_dz, int32_t 
     return c;
 }
 
+// The four nodes of one table cell, (i, j), (i+1, j), (i, j+1), (i+1, j+1).
+template <class T>
+struct Nodes4 {
+    Q4<T> t00, t10, t01, t11;
+};
+
 template <class T, class Tab>
-__device__ __forceinline__ Q4<T> gather4(const Tab *tab, const float *sc, const Cell<T> &c, int32_t nr) {
-    const int64_t k = (int64_t)c.j * nr + c.i;
-    const Q4<T> t00 = load4(tab, k, sc), t10 = load4(tab, k + 1, sc);
-    const Q4<T> t01 = load4(tab, k + nr, sc), t11 = load4(tab, k + nr + 1, sc);
+__device__ __forceinline__ Nodes4<T> load_nodes(const Tab *tab, const float *sc, int32_t i, int32_t j, int32_t nr) {
+    const int64_t k = (int64_t)j * nr + i;
+    return Nodes4<T>{load4(tab, k, sc), load4(tab, k + 1, sc), load4(tab, k + nr, sc), load4(tab, k + nr + 1, sc)};
+}
+
+// Bilinear interpolation of a cell's nodes at the cell fractions (f, g).
+template <class T>
+__device__ __forceinline__ Q4<T> interp(const Nodes4<T> &n, const Cell<T> &c) {
     const T w00 = ((T)1 - c.f) * ((T)1 - c.g), w10 = c.f * ((T)1 - c.g);
     const T w01 = ((T)1 - c.f) * c.g, w11 = c.f * c.g;
     Q4<T> o;
-    o.a = w00 * t00.a + w10 * t10.a + w01 * t01.a + w11 * t11.a;
-    o.b = w00 * t00.b + w10 * t10.b + w01 * t01.b + w11 * t11.b;
-    o.c = w00 * t00.c + w10 * t10.c + w01 * t01.c + w11 * t11.c;
-    o.d = w00 * t00.d + w10 * t10.d + w01 * t01.d + w11 * t11.d;
+    o.a = w00 * n.t00.a + w10 * n.t10.a + w01 * n.t01.a + w11 * n.t11.a;
+    o.b = w00 * n.t00.b + w10 * n.t10.b + w01 * n.t01.b + w11 * n.t11.b;
+    o.c = w00 * n.t00.c + w10 * n.t10.c + w01 * n.t01.c + w11 * n.t11.c;
+    o.d = w00 * n.t00.d + w10 * n.t10.d + w01 * n.t01.d + w11 * n.t11.d;
     return o;
+}
+
+template <class T, class Tab>
+__device__ __forceinline__ Q4<T> gather4(const Tab *tab, const float *sc, const Cell<T> &c, int32_t nr) {
+    return interp(load_nodes<T>(tab, sc, c.i, c.j, nr), c);
 }
 
 // Einstein model inverse: T = theta / ln(1 + s kB theta / U).

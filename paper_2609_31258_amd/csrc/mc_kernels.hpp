@@ -272,11 +272,188 @@ struct StepCount {
     uint64_t cand, acc, cap, clamp, act, lang, exch;
 };
 
+// Per pack and step: < 2^32 each.
+struct PackCount {
+    uint32_t cand, acc, cap, clamp, lang, exch;
+};
+
+// Gas at a pack's post-push position ("Gas field and electrode mask
+// coupling"): flow velocity projected by Eq. 3, temperature, and n_gas sigma
+// of the pack's species (zero where there is no gas).
+template <class T>
+struct GasAt {
+    T ux, uy, uz, tg, ngs;
+    bool gas;
+};
+
+template <class P, class Tab>
+__device__ __forceinline__ GasAt<typename P::T> gas_at(const StepArgs<P, Tab> &a, const Species &sp,
+                                                       typename P::T rr, typename P::T x1, typename P::T y1,
+                                                       typename P::T z1) {
+    using T = typename P::T;
+    const T m = (T)sp.m, ccs = (T)sp.ccs;
+    const Cell<T> cl = locate<T>(rr, z1, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
+    const Q4<T> g = gather4<T>(a.gtab, a.gsc, cl, a.nr);
+    const T sr = rr > (T)0 ? P::div(g.a, rr) : (T)0;
+    GasAt<T> o;
+    o.ux = sr * x1;
+    o.uy = sr * y1;
+    o.uz = g.b;
+    o.tg = g.d;
+    // n_gas * sigma.  FP32 form: evaluated on every lane and then
+    // selected, so that all four gas components and the cross-section
+    // are read at once rather than behind a branch on the temperature
+    // (its quotient is one reciprocal); FP64: the division stays behind
+    // the branch, where the compiler keeps it without stack use
+    if constexpr (P::kTwo) {
+        const T ngs_any = P::div(g.c, (T)kB * (o.tg > (T)0 ? o.tg : (T)1)) * ccs;
+        o.ngs = o.tg > (T)0 ? ngs_any : (T)0;
+    } else {
+        o.ngs = o.tg > (T)0 ? P::div(g.c, (T)kB * o.tg) * ccs : (T)0;
+    }
+    // (FP32 form: the mass, positive by definition, enters the test so
+    // that its read is issued with the gas gather instead of after it)
+    o.gas = P::kTwo ? (o.ngs > (T)0) & (bool)isfinite(o.ngs) & (m > (T)0) : o.ngs > (T)0 && isfinite(o.ngs);
+    return o;
+}
+
+// Whether a pack takes the hybrid Langevin branch this step: the branch is
+// on, its post-push z lies in the window (or there is none), and its
+// candidate rate lambda = n sigma (s + abar) reaches the switch
+// (lambda dt_ref >= lv_switch).
+template <class P, class Tab>
+__device__ __forceinline__ bool takes_langevin(const StepArgs<P, Tab> &a, double Z1, typename P::T lam) {
+    using T = typename P::T;
+    return a.langevin_on && (!(a.lv_z_hi > a.lv_z_lo) || (Z1 >= a.lv_z_lo && Z1 < a.lv_z_hi)) &&
+           lam * (T)a.lv_dt_ref >= (T)a.lv_switch;
+}
+
+// Hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward
+// the gas velocity over dt, hard-sphere friction rate, Box-Muller normals
+// from one block.
+template <class P, class Tab>
+__device__ __forceinline__ void langevin_relax(const StepArgs<P, Tab> &a, const Species &sp, int64_t id,
+                                               uint32_t k0, uint32_t k1, const GasAt<typename P::T> &g,
+                                               typename P::T &vx, typename P::T &vy, typename P::T &vz) {
+    using T = typename P::T;
+    const T dt = (T)a.dt, m = (T)sp.m, mg = (T)a.mg;
+    const T fm = P::div(mg, m + mg);
+    const W4 w = draw(id, a.step, kPurposeLangevin, 0u, k0, k1);
+    const T r0 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w0)));
+    const T r1 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w2)));
+    T s0, c0;
+    P::sc2pi_fast(P::u01(w.w1), &s0, &c0);
+    const T c1 = P::cos2pi_fast(P::u01(w.w3));
+    const T ktm = P::div((T)kB * g.tg, m);  // kB T / m (no underflow in FP32)
+    const T gam = (T)(16.0 / 3.0) * g.ngs * P::sqrt_(fm * ktm * (T)0.15915494309189535);
+    const T f = P::exp_(-gam * dt);
+    const T sd = P::sqrt_(ktm * ((T)1 - f * f));
+    vx = g.ux + (vx - g.ux) * f + sd * (r0 * c0);
+    vy = g.uy + (vy - g.uy) * f + sd * (r0 * s0);
+    vz = g.uz + (vz - g.uz) * f + sd * (r1 * c1);
+}
+
+// The explicit collision loop of one pack over one step (Eq. 6 and the
+// collision paragraph): sequential exponential waits at lambda =
+// n sigma (s + abar), partner from the two-branch mixture, acceptance
+// |g|/(s + |w|), impulsive hard-sphere update with the internal-energy
+// exchange.  Entered with s, lambda and v - u of the post-push state.
+template <class P, class Tab>
+__device__ __forceinline__ void collide_explicit(const StepArgs<P, Tab> &a, const Species &sp, int64_t id,
+                                                 uint32_t k0, uint32_t k1, const GasAt<typename P::T> &g,
+                                                 typename P::T ag, typename P::T abar, typename P::T sv,
+                                                 typename P::T lam, typename P::T &vx, typename P::T &vy,
+                                                 typename P::T &vz, typename P::T &e, typename P::T &el,
+                                                 PackCount &pc) {
+    using T = typename P::T;
+    const T dt = (T)a.dt, m = (T)sp.m, mg = (T)a.mg;
+    const T M = m + mg, fm = P::div(mg, M), fi = P::div(m, M), mu = mg * fi;  // no m*mg product (FP32 range)
+    const T two_mu = P::div((T)2, mu);
+    const T alpha = (T)sp.alpha, skt = (T)sp.skt, theta = (T)sp.theta;
+    const T ux = g.ux, uy = g.uy, uz = g.uz, ngs = g.ngs;
+    T rx = vx - ux, ry = vy - uy, rz = vz - uz;
+    // candidate cap; a non-finite rate ends the loop at once
+    const T nexp = lam * dt;
+    const int32_t cap = (nexp < (T)1e6) ? 64 + 8 * (int32_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
+    T tleft = dt;
+    for (int32_t c = 0;; ++c) {
+        if (c == cap) {
+            ++pc.cap;
+            break;
+        }
+        const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), k0, k1);
+        const T tau = -P::div(P::ln_fast(P::u01(wa.w0)), lam);
+        if (!(tau < tleft)) break;
+        tleft -= tau;
+        ++pc.cand;
+        const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), k0, k1);
+        // partner thermal velocity: E = |w|^2/(2 a^2) ~ Gamma(3/2) (Maxwellian branch)
+        // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
+        const bool maxw = P::u01(wa.w1) * (sv + abar) < sv;  // u < s/(s + abar)
+        const T cc = P::cos2pi_fast(P::u01(wb.w0));
+        const T en = -P::ln_fast(P::u01(wa.w2)) - P::ln_fast(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
+        const T wn = ag * P::sqrt_((T)2 * en);
+        const T ct = (T)2 * P::u01(wb.w1) - (T)1;
+        const T st = P::sqrt_(fmax((T)0, (T)1 - ct * ct));
+        T sph, cph;
+        P::sc2pi_fast(P::u01(wb.w2), &sph, &cph);
+        const T wx = wn * st * cph, wy = wn * st * sph, wz = wn * ct;
+        const T gx = rx - wx, gy = ry - wy, gz = rz - wz;
+        const T g2 = gx * gx + gy * gy + gz * gz;
+        const T gn = P::sqrt_(g2);
+        const T uacc = P::u01(wb.w3);
+        if (!(uacc * (sv + wn) < gn)) continue;
+        ++pc.acc;
+        const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), k0, k1);
+        // centre of mass of the ion and the partner (lab velocity u + w)
+        const T vcx = fi * vx + fm * (ux + wx), vcy = fi * vy + fm * (uy + wy), vcz = fi * vz + fm * (uz + wz);
+        const T et = (T)0.5 * mu * g2;
+        T etp = et;
+        // exchange select: the acceptance residual, uniform given acceptance
+        if (uacc * (sv + wn) < alpha * gn) {  // residual uacc (s + |w|)/|g| < alpha
+            ++pc.exch;
+            const T te = einstein_t<P>(e + el, skt, theta);
+            etp = -(T)kB * te * P::ln_fast(P::u01(wc.w2) * P::u01(wc.w3));
+            const T de = et - etp;
+            if (e + el + de < (T)0) {
+                etp = e + el + et;
+                e = 0;
+                el = 0;
+                ++pc.clamp;
+            } else {
+                acc2(e, el, de);
+            }
+        }
+        const T cchi = (T)2 * P::u01(wc.w0) - (T)1;
+        const T schi = P::sqrt_(fmax((T)0, (T)1 - cchi * cchi));
+        T sps, cps;
+        P::sc2pi_fast(P::u01(wc.w1), &sps, &cps);
+        const T f = fm * P::sqrt_(etp * two_mu);
+        vx = vcx + f * schi * cps;
+        vy = vcy + f * schi * sps;
+        vz = vcz + f * cchi;
+        rx = vx - ux;
+        ry = vy - uy;
+        rz = vz - uz;
+        sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
+        lam = ngs * (sv + abar);
+    }
+}
+
+// Eq. 7: hazard with the post-collision effective temperature.
+template <class P, class Tab>
+__device__ __forceinline__ void accumulate_hazard(const StepArgs<P, Tab> &a, const Species &sp, int64_t s,
+                                                  typename P::T e, typename P::T el) {
+    using T = typename P::T;
+    const T te = einstein_t<P>(e + el, (T)sp.skt, (T)sp.theta);
+    a.p.h[s] = a.p.h[s] + rate<P>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * (T)a.dt;
+}
+
 // One pack, one step.
 template <class P, class Tab>
 __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n, uint32_t k0, uint32_t k1) {
     using T = typename P::T;
-    uint32_t ncand = 0, nacc = 0, ncap = 0, nclamp = 0, nlang = 0, nexch = 0;  // per pack and step: < 2^32
+    PackCount pc{0, 0, 0, 0, 0, 0};
     if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
         n.act = 1;
         // the species record by reference, so each field is read where it is
@@ -378,132 +555,29 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         if (cls == ST_ACTIVE && a.collisions_on) {
             // ---- collisions with the gas at the new position ----
             const T rr = (T)r1;
-            const T m = (T)sp.m, mg = (T)a.mg, ccs = (T)sp.ccs;
-            const Cell<T> cl = locate<T>(rr, z1, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
-            const Q4<T> g = gather4<T>(a.gtab, a.gsc, cl, a.nr);
-            const T sr = rr > (T)0 ? P::div(g.a, rr) : (T)0;
-            const T ux = sr * x1, uy = sr * y1, uz = g.b, tg = g.d;
-            // n_gas * sigma.  FP32 form: evaluated on every lane and then
-            // selected, so that all four gas components and the cross-section
-            // are read at once rather than behind a branch on the temperature
-            // (its quotient is one reciprocal); FP64: the division stays behind
-            // the branch, where the compiler keeps it without stack use
-            T ngs;
-            if constexpr (P::kTwo) {
-                const T ngs_any = P::div(g.c, (T)kB * (tg > (T)0 ? tg : (T)1)) * ccs;
-                ngs = tg > (T)0 ? ngs_any : (T)0;
-            } else {
-                ngs = tg > (T)0 ? P::div(g.c, (T)kB * tg) * ccs : (T)0;
-            }
-            // (FP32 form: the mass, positive by definition, enters the test so
-            // that its read is issued with the gas gather instead of after it)
-            const bool gas = P::kTwo ? (ngs > (T)0) & (bool)isfinite(ngs) & (m > (T)0) : ngs > (T)0 && isfinite(ngs);
-            if (gas) {
-                const T ag = P::sqrt_(P::div((T)kB * tg, mg));
+            const GasAt<T> g = gas_at(a, sp, rr, x1, y1, z1);
+            if (g.gas) {
+                const T ag = P::sqrt_(P::div((T)kB * g.tg, (T)a.mg));
                 const T abar = ag * (T)1.5957691216057308;  // sqrt(8/pi)
-                const T M = m + mg, fm = P::div(mg, M), fi = P::div(m, M), mu = mg * fi;  // no m*mg product (FP32 range)
-                const T two_mu = P::div((T)2, mu);
-                const T alpha = (T)sp.alpha, skt = (T)sp.skt, theta = (T)sp.theta;
-                T rx = vx - ux, ry = vy - uy, rz = vz - uz;
-                T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
-                T lam = ngs * (sv + abar);
-                lang = a.langevin_on && (!(a.lv_z_hi > a.lv_z_lo) || (Z1 >= a.lv_z_lo && Z1 < a.lv_z_hi)) &&
-                       lam * (T)a.lv_dt_ref >= (T)a.lv_switch;
-                if (lang) {
-                    // hybrid Langevin branch: exact Ornstein-Uhlenbeck relaxation of v toward the gas
-                    // velocity over dt, hard-sphere friction rate, Box-Muller normals from one block
-                    const W4 w = draw(P::kTwo ? id : a.p.id[s], a.step, kPurposeLangevin, 0u, k0, k1);
-                    const T r0 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w0)));
-                    const T r1 = P::sqrt_((T)-2 * P::ln_fast(P::u01(w.w2)));
-                    T s0, c0;
-                    P::sc2pi_fast(P::u01(w.w1), &s0, &c0);
-                    const T c1 = P::cos2pi_fast(P::u01(w.w3));
-                    const T ktm = P::div((T)kB * tg, m);  // kB T / m (no underflow in FP32)
-                    const T gam = (T)(16.0 / 3.0) * ngs * P::sqrt_(fm * ktm * (T)0.15915494309189535);
-                    const T f = P::exp_(-gam * dt);
-                    const T sd = P::sqrt_(ktm * ((T)1 - f * f));
-                    vx = ux + (vx - ux) * f + sd * (r0 * c0);
-                    vy = uy + (vy - uy) * f + sd * (r0 * s0);
-                    vz = uz + (vz - uz) * f + sd * (r1 * c1);
-                    ++nlang;
+                const T rx = vx - g.ux, ry = vy - g.uy, rz = vz - g.uz;
+                const T sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
+                const T lam = g.ngs * (sv + abar);
+                lang = takes_langevin(a, Z1, lam);
+                if constexpr (!P::kTwo) {
+                    if (!lang) id = a.p.id[s];
                 }
-                // candidate cap; a non-finite rate ends the loop at once
-                const T nexp = lang ? (T)0 : lam * dt;
-                const int32_t cap = (nexp < (T)1e6) ? 64 + 8 * (int32_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
-                T tleft = lang ? (T)0 : dt;
-                if constexpr (!P::kTwo) id = a.p.id[s];
-                for (int32_t c = 0; !lang; ++c) {
-                    if (c == cap) {
-                        ++ncap;
-                        break;
-                    }
-                    const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), k0, k1);
-                    const T tau = -P::div(P::ln_fast(P::u01(wa.w0)), lam);
-                    if (!(tau < tleft)) break;
-                    tleft -= tau;
-                    ++ncand;
-                    const W4 wb = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 1), k0, k1);
-                    // partner thermal velocity: E = |w|^2/(2 a^2) ~ Gamma(3/2) (Maxwellian branch)
-                    // or Gamma(2) (flux-weighted branch), isotropic direction; no divergent branch
-                    const bool maxw = P::u01(wa.w1) * (sv + abar) < sv;  // u < s/(s + abar)
-                    const T cc = P::cos2pi_fast(P::u01(wb.w0));
-                    const T en = -P::ln_fast(P::u01(wa.w2)) - P::ln_fast(P::u01(wa.w3)) * (maxw ? cc * cc : (T)1);
-                    const T wn = ag * P::sqrt_((T)2 * en);
-                    const T ct = (T)2 * P::u01(wb.w1) - (T)1;
-                    const T st = P::sqrt_(fmax((T)0, (T)1 - ct * ct));
-                    T sph, cph;
-                    P::sc2pi_fast(P::u01(wb.w2), &sph, &cph);
-                    const T wx = wn * st * cph, wy = wn * st * sph, wz = wn * ct;
-                    const T gx = rx - wx, gy = ry - wy, gz = rz - wz;
-                    const T g2 = gx * gx + gy * gy + gz * gz;
-                    const T gn = P::sqrt_(g2);
-                    const T uacc = P::u01(wb.w3);
-                    if (!(uacc * (sv + wn) < gn)) continue;
-                    ++nacc;
-                    const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), k0, k1);
-                    // centre of mass of the ion and the partner (lab velocity u + w)
-                    const T vcx = fi * vx + fm * (ux + wx), vcy = fi * vy + fm * (uy + wy), vcz = fi * vz + fm * (uz + wz);
-                    const T et = (T)0.5 * mu * g2;
-                    T etp = et;
-                    // exchange select: the acceptance residual, uniform given acceptance
-                    if (uacc * (sv + wn) < alpha * gn) {  // residual uacc (s + |w|)/|g| < alpha
-                        ++nexch;
-                        const T te = einstein_t<P>(e + el, skt, theta);
-                        etp = -(T)kB * te * P::ln_fast(P::u01(wc.w2) * P::u01(wc.w3));
-                        const T de = et - etp;
-                        if (e + el + de < (T)0) {
-                            etp = e + el + et;
-                            e = 0;
-                            el = 0;
-                            ++nclamp;
-                        } else {
-                            acc2(e, el, de);
-                        }
-                    }
-                    const T cchi = (T)2 * P::u01(wc.w0) - (T)1;
-                    const T schi = P::sqrt_(fmax((T)0, (T)1 - cchi * cchi));
-                    T sps, cps;
-                    P::sc2pi_fast(P::u01(wc.w1), &sps, &cps);
-                    const T f = fm * P::sqrt_(etp * two_mu);
-                    vx = vcx + f * schi * cps;
-                    vy = vcy + f * schi * sps;
-                    vz = vcz + f * cchi;
-                    rx = vx - ux;
-                    ry = vy - uy;
-                    rz = vz - uz;
-                    sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
-                    lam = ngs * (sv + abar);
+                if (lang) {
+                    langevin_relax(a, sp, P::kTwo ? id : a.p.id[s], k0, k1, g, vx, vy, vz);
+                    ++pc.lang;
+                } else {
+                    collide_explicit(a, sp, id, k0, k1, g, ag, abar, sv, lam, vx, vy, vz, e, el, pc);
                 }
             }
         }
-
         if (cls == ST_ACTIVE) {
             // ---- Eq. 7: hazard with the post-collision effective temperature ----
             // (not accumulated in an aggregated Langevin step)
-            if (!lang) {
-                const T te = einstein_t<P>(e + el, (T)sp.skt, (T)sp.theta);
-                a.p.h[s] = a.p.h[s] + rate<P>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * dt;
-            }
+            if (!lang) accumulate_hazard(a, sp, s, e, el);
             a.p.e[s] = e;
             if constexpr (P::kTwo) a.p.el[s] = el;
         } else {
@@ -515,12 +589,12 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         a.p.vy[s] = vy;
         a.p.vz[s] = vz;
     }
-    n.cand = ncand;
-    n.acc = nacc;
-    n.cap = ncap;
-    n.clamp = nclamp;
-    n.lang = nlang;
-    n.exch = nexch;
+    n.cand = pc.cand;
+    n.acc = pc.acc;
+    n.cap = pc.cap;
+    n.clamp = pc.clamp;
+    n.lang = pc.lang;
+    n.exch = pc.exch;
 }
 
 // Block-aggregated counters: wavefront sums, then LDS, then one atomic per
@@ -811,9 +885,18 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
             dep_pack<P>(a, keys, vals, dst, X, Y, Z, q[u], lo, hi);
         }
     }
-    if (a.range && hi >= 0) {
-        atomicMin(&blo, lo);
-        atomicMax(&bhi, hi);
+    if (a.range) {
+        // lowest and highest node over the wavefront first: one LDS atomic per
+        // wavefront instead of one per thread on the same two words
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            lo = min(lo, __shfl_xor(lo, o, 64));
+            hi = max(hi, __shfl_xor(hi, o, 64));
+        }
+        if ((threadIdx.x & 63) == 0 && hi >= 0) {
+            atomicMin(&blo, lo);
+            atomicMax(&bhi, hi);
+        }
     }
     __syncthreads();
     for (int k = threadIdx.x; k < kDepHash; k += blockDim.x)
@@ -829,33 +912,47 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
     }
 }
 
-// The grid from the copies: q[n] = sum of the copies' values at n for n in
-// the range the deposit wrote (the copies are cleared there, after all of
-// the thread's loads have been issued; nrep <= kDepositMaxCopies), 0 elsewhere;
-// node 0's thread also resets the other range slot, next_range, for the
-// next update (range and next_range alternate between updates).
+// The grid from the copies: q[n] = the sum of the copies' values at n for n
+// in the range this deposit wrote (range; the copies are cleared there, after
+// all of the thread's loads have been issued; nrep <= kDepositMaxCopies), 0
+// elsewhere.  Only the nodes in the span of this range and of the previous
+// deposit's (prev) are written -- the grid is zero outside the previous
+// range already -- or every node when prev is null.  Grid-stride; the first
+// thread also resets the range slot `next` for the deposit after this one.
 static __global__ __launch_bounds__(256) void k_deposit_sum(unsigned long long *q, unsigned long long *qrep,
                                                             int32_t nrep, int64_t nn, const int32_t *range,
-                                                            int32_t *next_range) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= nn) return;
-    unsigned long long v = 0ull;
-    if (n >= range[0] && n <= range[1]) {
-        unsigned long long w[kDepositMaxCopies];
-#pragma unroll
-        for (int32_t c = 0; c < kDepositMaxCopies; ++c) w[c] = c < nrep ? qrep[(int64_t)c * nn + n] : 0ull;
-#pragma unroll
-        for (int32_t c = 0; c < kDepositMaxCopies; ++c) v += w[c];
-#pragma unroll
-        for (int32_t c = 0; c < kDepositMaxCopies; ++c)
-            if (c < nrep) qrep[(int64_t)c * nn + n] = 0ull;
+                                                            const int32_t *prev, int32_t *next) {
+    int64_t n0 = 0, n1 = nn - 1;
+    if (prev) {
+        n0 = min((int64_t)range[0], (int64_t)prev[0]);
+        n1 = max((int64_t)range[1], (int64_t)prev[1]);
+        n1 = min(n1, nn - 1);
     }
-    q[n] = v;
-    if (n == 0) {
-        next_range[0] = INT32_MAX;
-        next_range[1] = -1;
+    const int32_t lo = range[0], hi = range[1];
+    for (int64_t n = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n <= n1;
+         n += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long v = 0ull;
+        if (n >= lo && n <= hi) {
+            unsigned long long w[kDepositMaxCopies];
+#pragma unroll
+            for (int32_t c = 0; c < kDepositMaxCopies; ++c) w[c] = c < nrep ? qrep[(int64_t)c * nn + n] : 0ull;
+#pragma unroll
+            for (int32_t c = 0; c < kDepositMaxCopies; ++c) v += w[c];
+#pragma unroll
+            for (int32_t c = 0; c < kDepositMaxCopies; ++c)
+                if (c < nrep) qrep[(int64_t)c * nn + n] = 0ull;
+        }
+        q[n] = v;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        next[0] = INT32_MAX;
+        next[1] = -1;
     }
 }
+
+// Blocks of the sum kernel: enough to cover a 1M-node grid in one sweep of
+// 256-thread blocks, grid-stride beyond.
+constexpr int64_t kDepositSumBlocks = 4096;
 
 // E = -grad(phi) on nodes: central differences, one-sided at the outer
 // edges, E_r = 0 on the axis.

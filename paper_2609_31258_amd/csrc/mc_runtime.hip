@@ -58,8 +58,9 @@ struct mc_ctx {
 
     unsigned long long *qgrid = nullptr;
     unsigned long long *qrep = nullptr;  // the deposit's copies of the grid (nrep of them, kept zeroed)
-    int32_t nrep = 1, dep_parity = 0;
-    int32_t *dep_range = nullptr;        // two (lowest, highest) node slots, alternating by update
+    int32_t nrep = 1, dep_slot = 0;
+    int32_t *dep_range = nullptr;        // three (lowest, highest) node slots, rotating by update
+    bool dep_full = true;                // the next sum writes every node (the grid may hold charge anywhere)
     double *sine = nullptr, *tcp = nullptr, *tinv = nullptr;
     void *bh = nullptr;
     Bluestein blu;
@@ -450,7 +451,9 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     const int64_t nn = (int64_t)ctx->nr * ctx->nz;
     {
         Timer t(ctx, MC_K_DEPOSIT);
-        int32_t *range = ctx->dep_range + 2 * ctx->dep_parity, *next = ctx->dep_range + 2 * (1 - ctx->dep_parity);
+        // slots: this deposit's range, the previous deposit's, and the next one's
+        int32_t *range = ctx->dep_range + 2 * ctx->dep_slot, *prev = ctx->dep_range + 2 * ((ctx->dep_slot + 2) % 3),
+                *next = ctx->dep_range + 2 * ((ctx->dep_slot + 1) % 3);
         if (ctx->n_slots > 0) {
             DepositArgs<typename P::T> a{};
             a.p = p;
@@ -469,10 +472,14 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
             k_deposit<P><<<nb, kDepositThreads, 0, ctx->stream>>>(a);
             LAUNCHCHK();
         }
-        // the grid from the copies (every node written: no separate clear)
-        k_deposit_sum<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->qgrid, ctx->qrep, ctx->nrep, nn, range, next);
+        // the grid from the copies: the nodes of this deposit's range and the
+        // previous one's are written, the rest of the grid is zero already
+        const unsigned sb = (unsigned)std::min<int64_t>(grid_for(nn), kDepositSumBlocks);
+        k_deposit_sum<<<sb, kBlock, 0, ctx->stream>>>(ctx->qgrid, ctx->qrep, ctx->nrep, nn, range,
+                                                      ctx->dep_full ? nullptr : prev, next);
         LAUNCHCHK();
-        ctx->dep_parity = 1 - ctx->dep_parity;
+        ctx->dep_slot = (ctx->dep_slot + 1) % 3;
+        ctx->dep_full = false;
     }
     if (ctx->op.sc_mask && !ctx->mcap.ready) {
         const int32_t rc = mask_setup(ctx);
@@ -739,7 +746,7 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     if (!rc) rc = dalloc_t(ctx, &ctx->qgrid, nn);
     ctx->nrep = deposit_copies(nn);
     if (!rc) rc = dalloc_t(ctx, &ctx->qrep, (size_t)ctx->nrep * nn);
-    if (!rc) rc = dalloc_t(ctx, &ctx->dep_range, 4);
+    if (!rc) rc = dalloc_t(ctx, &ctx->dep_range, 6);
     if (!rc) rc = dalloc_t(ctx, &ctx->sine, 2 * (int64_t)(g->nz - 1));
     if (!rc) rc = dalloc_t(ctx, &ctx->tcp, (int64_t)nu * m);
     if (!rc) rc = dalloc_t(ctx, &ctx->tinv, (int64_t)nu * m);
@@ -757,9 +764,10 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     HIPCHK(hipMemsetAsync(ctx->qgrid, 0, nn * sizeof(unsigned long long), ctx->stream));
     HIPCHK(hipMemsetAsync(ctx->qrep, 0, (size_t)ctx->nrep * nn * sizeof(unsigned long long), ctx->stream));
     {
-        static const int32_t empty[4] = {INT32_MAX, -1, INT32_MAX, -1};
+        static const int32_t empty[6] = {INT32_MAX, -1, INT32_MAX, -1, INT32_MAX, -1};
         HIPCHK(hipMemcpyAsync(ctx->dep_range, empty, sizeof(empty), hipMemcpyHostToDevice, ctx->stream));
-        ctx->dep_parity = 0;
+        ctx->dep_slot = 0;
+        ctx->dep_full = true;
     }
     // bake E = -grad(phi) for the three potentials
     const double *phis[3] = {t->phi_dc, t->phi_off, t->phi_rf};
@@ -1261,6 +1269,7 @@ int32_t mc_load_state(mc_ctx *ctx, const char *path) {
     if (!ctx || !path) return MC_EINVAL;
     if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
     HIPCHK(hipSetDevice(ctx->opt.device));
+    ctx->dep_full = true;  // the restored charge grid may hold charge anywhere
     HIPCHK(hipStreamSynchronize(ctx->stream));
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(ctx, MC_EINVAL, std::string("cannot read ") + path);
