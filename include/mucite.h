@@ -185,9 +185,9 @@ typedef struct mc_source {
  * Langevin branch; dt_rem = time to the next space-charge update).  dt is
  * then the largest step, the space-charge update runs every sc_every * dt
  * of simulated time, sources emit per step with that step's dt (Eq. 5), and
- * the Langevin switch always compares with dt.  The step's length costs one
- * small device-to-host read per step.  A step that collapses below 1e-9 dt
- * fails with MC_ENUMERIC.  The serving runtime runs it per query (see
+ * the Langevin switch always compares with dt.  The lengths stay on the
+ * device (see mc_step).  A step that collapses below 1e-9 dt fails with
+ * MC_ENUMERIC.  The serving runtime runs it per query (see
  * mc_query). */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
@@ -345,10 +345,14 @@ int32_t mc_inject(mc_ctx *ctx, int32_t src_id, int64_t n);
  * terminal classification ("Terminal events, snapshots, and reported
  * observables"), collisions (Eq. 6 and the internal-energy exchange) or the
  * hybrid Langevin relaxation, and the dissociation hazard (Eq. 7).
- * Asynchronous with a fixed step; with the adaptive step (Eq. 1) the
- * step lengths are found on the device and the call reads them back once,
- * at its end.  Errors: MC_ESTATE, MC_ENOMEM (capacity), MC_ENUMERIC
- * (adaptive step collapsed), MC_EDEVICE. */
+ * Asynchronous with a fixed step.  With the adaptive step (Eq. 1) each
+ * step's length is found on the device and the step kernels read it there;
+ * the call reads the step record back once per stretch of steps before a
+ * space-charge update could fall due, and at its end (while a source still
+ * emits, whose Eq. 5 counts need each length on the host, once per step).
+ * Errors: MC_ESTATE, MC_ENOMEM (capacity), MC_ENUMERIC (adaptive step
+ * collapsed; the step counter and time stay at the collapsed step),
+ * MC_EDEVICE. */
 int32_t mc_step(mc_ctx *ctx, int64_t n_steps);
 /* Space-charge update now ("Axisymmetric PIC space charge update": CIC
  * deposit, cylindrical Poisson solve, E = -grad(Phi) folded into the static

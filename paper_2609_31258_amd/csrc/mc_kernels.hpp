@@ -205,6 +205,10 @@ struct StepArgs {
     double lv_z_lo, lv_z_hi, lv_switch, lv_dt_ref;  // switch: lambda lv_dt_ref >= lv_switch
     uint32_t k0, k1;
     const StepTables *tables;  // the FP64 step's logarithm and turn tables (device memory)
+    // adaptive step kept on the device: the step record written by
+    // k_dt_finish -- (t0, dt, c0, ch, c1) of this step, then t0 and c0 of
+    // the next -- read in place of the fields above; null with a fixed step
+    const double *dyn;
 };
 
 // Total field of Eq. 4 at (x, y, z), radial part projected by Eq. 3.
@@ -629,6 +633,17 @@ constexpr int step_waves() {
 
 template <class P, class Tab>
 __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
+    if (a.dyn) {
+        // the step's time, length and RF stage coefficients from the device
+        // record; a zero length marks an adaptive run halted by a collapsed
+        // step (every thread returns: no barrier is left waiting)
+        if (!(a.dyn[1] > 0.0)) return;
+        a.t0 = a.dyn[0];
+        a.dt = a.dyn[1];
+        a.c0 = a.dyn[2];
+        a.ch = a.dyn[3];
+        a.c1 = a.dyn[4];
+    }
     P::prepare_tables(a.tables);
     StepCount n{0, 0, 0, 0, 0, 0, 0};
     step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
@@ -665,7 +680,7 @@ __global__ __launch_bounds__(256) void k_dt_limits(StepArgs<P, Tab> a, unsigned 
         const T vn = P::sqrt_(vx * vx + vy * vy + vz * vz);
         if (vn > (T)0) lim = fmin(lim, (double)((T)0.5 * P::div(h, vn)));
         T ex, ey, ez;
-        efield(a, x, y, z, (T)a.c0, ex, ey, ez);
+        efield(a, x, y, z, (T)(a.dyn ? a.dyn[6] : a.c0), ex, ey, ez);
         const T an = (T)fabs(sp.qm) * P::sqrt_(ex * ex + ey * ey + ez * ez);
         const T rr = P::sqrt_(x * x + y * y);
         const Cell<T> cl = locate<T>(rr, z, (T)a.inv_dr, (T)a.inv_dz, a.nr, a.nz);
@@ -719,6 +734,58 @@ static __global__ __launch_bounds__(kHotRep) void k_dt_reduce(unsigned long long
         out[0] = mn[0];
         out[1] = fl[0];
     }
+}
+
+// The adaptive step on the device (one block of kHotRep threads): the
+// replica lines reduced as in k_dt_reduce, then
+//   dt = min(dt_max, limit, rf_cap, lv_cap if a pack takes the Langevin
+//            branch, t_pic - t0)
+// (the caps are +inf where they do not apply), and the step record: this
+// step's (t0, dt, c0, ch, c1) with c = V_RF cos(w2 t + phase) at t0, t0 +
+// dt/2 and t0 + dt, then the next step's t0 = t0 + dt and c0.  A step below
+// `collapse` halts the run: the record's length becomes zero (the step
+// kernels return at once) and word 7 keeps 1 + the step index, the time
+// staying at the collapsed step's start.
+static __global__ __launch_bounds__(kHotRep) void k_dt_finish(unsigned long long *rep, double *rec, double dt_max,
+                                                              double rf_cap, double lv_cap, double t_pic,
+                                                              double collapse, double v_rf, double w2, double phase,
+                                                              int64_t step) {
+#pragma clang fp contract(off)
+    __shared__ unsigned long long mn[kHotRep], fl[kHotRep];
+    const int k = threadIdx.x;
+    mn[k] = rep[(int64_t)k * kHotStride];
+    fl[k] = rep[(int64_t)k * kHotStride + 1];
+    rep[(int64_t)k * kHotStride] = kInfBits;
+    rep[(int64_t)k * kHotStride + 1] = 0ull;
+    __syncthreads();
+    for (int w = kHotRep / 2; w > 0; w >>= 1) {
+        if (k < w) {
+            mn[k] = mn[k] < mn[k + w] ? mn[k] : mn[k + w];
+            fl[k] |= fl[k + w];
+        }
+        __syncthreads();
+    }
+    if (k != 0) return;
+    unsigned long long *halted = reinterpret_cast<unsigned long long *>(rec + 7);
+    const double t0 = rec[5], c0 = rec[6];
+    double d = fmin(dt_max, __longlong_as_double((long long)mn[0]));
+    d = fmin(d, rf_cap);
+    if (fl[0]) d = fmin(d, lv_cap);
+    d = fmin(d, t_pic - t0);
+    if (*halted || !(d > collapse)) {
+        if (!*halted) *halted = (unsigned long long)step + 1ull;
+        rec[1] = 0.0;
+        return;
+    }
+    const double t1 = t0 + d;
+    const double c1 = v_rf * cos(w2 * t1 + phase);
+    rec[0] = t0;
+    rec[1] = d;
+    rec[2] = c0;
+    rec[3] = v_rf * cos(w2 * (t0 + 0.5 * d) + phase);
+    rec[4] = c1;
+    rec[5] = t1;
+    rec[6] = c1;
 }
 
 static __global__ __launch_bounds__(kHotRep) void k_dt_reset(unsigned long long *rep) {
@@ -1127,8 +1194,12 @@ constexpr int kSampleThreads = 1024;
 template <class T>
 __global__ __launch_bounds__(kSampleThreads) void k_sample(PackPtrs<T> p, const Species *sp, int64_t n_slots,
                                                            int64_t step, int64_t stride, mc_sample_rec *out,
-                                                           unsigned long long *count, int64_t cap) {
+                                                           unsigned long long *count, int64_t cap,
+                                                           const double *dyn = nullptr) {
 #pragma clang fp contract(off)
+    // an adaptive run halted on the device takes no further samples (the
+    // record of the previous step has zero length)
+    if (dyn && !(dyn[1] > 0.0) && reinterpret_cast<const unsigned long long *>(dyn)[7]) return;
     __shared__ unsigned int wave_base[kSampleThreads / 64];
     __shared__ unsigned long long block_base;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -71,6 +71,8 @@ struct mc_ctx {
     double *rhs = nullptr, *phi_tmp = nullptr;
     // adaptive step (Eq. 1)
     unsigned long long *dt_rep = nullptr, *dt_out = nullptr;
+    double *dt_rec = nullptr;   // the step record kept on the device (k_dt_finish)
+    bool dt_rec_valid = false;  // its next-step time matches t
     double t = 0.0, t_next_pic = 0.0, last_dt = 0.0;
     // trajectory samples
     mc_sample_rec *samples = nullptr;
@@ -343,19 +345,20 @@ static StepArgs<P, Tab> step_args(mc_ctx *ctx, PackPtrs<typename P::T> p, double
 }
 
 template <class P, class Tab>
-static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, double dt) {
+static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, double dt, const double *dyn) {
     if (ctx->n_slots == 0) return MC_OK;
-    const StepArgs<P, Tab> a = step_args<P, Tab>(ctx, p, t0, dt);
+    StepArgs<P, Tab> a = step_args<P, Tab>(ctx, p, t0, dt);
+    a.dyn = dyn;
     Timer t(ctx, MC_K_STEP);
     k_step<P, Tab><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a);
     LAUNCHCHK();
     return MC_OK;
 }
 
-static int32_t step_once(mc_ctx *ctx, double t0, double dt) {
-    if (!ctx->fp32()) return launch_step<P64, double4>(ctx, ctx->p64, t0, dt);
-    if (ctx->bf16()) return launch_step<P32, bf16x4>(ctx, ctx->p32, t0, dt);
-    return launch_step<P32, float4>(ctx, ctx->p32, t0, dt);
+static int32_t step_once(mc_ctx *ctx, double t0, double dt, const double *dyn = nullptr) {
+    if (!ctx->fp32()) return launch_step<P64, double4>(ctx, ctx->p64, t0, dt, dyn);
+    if (ctx->bf16()) return launch_step<P32, bf16x4>(ctx, ctx->p32, t0, dt, dyn);
+    return launch_step<P32, float4>(ctx, ctx->p32, t0, dt, dyn);
 }
 
 // Eq. 1 limits over the active packs at t0: returns the smallest per-pack
@@ -377,17 +380,34 @@ static int32_t pack_limits_t(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, 
     return MC_OK;
 }
 
+// The Eq. 1 limits of this step into the replica lines, with the RF
+// coefficient of the step's start from the device record.
+template <class P, class Tab>
+static int32_t pack_limits_dev(mc_ctx *ctx, PackPtrs<typename P::T> p) {
+    if (ctx->n_slots == 0) return MC_OK;
+    StepArgs<P, Tab> a = step_args<P, Tab>(ctx, p, 0.0, ctx->op.dt);
+    a.dyn = ctx->dt_rec;
+    k_dt_limits<P, Tab><<<grid_for(ctx->n_slots), kBlock, 0, ctx->stream>>>(a, ctx->dt_rep);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
+static int32_t adaptive_buffers(mc_ctx *ctx) {
+    if (ctx->dt_rep) return MC_OK;
+    int32_t rc = dalloc_t(ctx, &ctx->dt_rep, (size_t)kHotLen);
+    if (!rc) rc = dalloc_t(ctx, &ctx->dt_out, 2);
+    if (!rc) rc = dalloc_t(ctx, &ctx->dt_rec, 8);
+    if (rc) return rc;
+    k_dt_reset<<<1, kHotRep, 0, ctx->stream>>>(ctx->dt_rep);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
 static int32_t adaptive_dt(mc_ctx *ctx, double t0, double *dt) {
     double lim = HUGE_VAL;
     bool lang = false;
-    int32_t rc;
-    if (!ctx->dt_rep) {
-        rc = dalloc_t(ctx, &ctx->dt_rep, (size_t)kHotLen);
-        if (!rc) rc = dalloc_t(ctx, &ctx->dt_out, 2);
-        if (rc) return rc;
-        k_dt_reset<<<1, kHotRep, 0, ctx->stream>>>(ctx->dt_rep);
-        LAUNCHCHK();
-    }
+    int32_t rc = adaptive_buffers(ctx);
+    if (rc) return rc;
     if (!ctx->fp32()) rc = pack_limits_t<P64, double4>(ctx, ctx->p64, t0, &lim, &lang);
     else if (ctx->bf16()) rc = pack_limits_t<P32, bf16x4>(ctx, ctx->p32, t0, &lim, &lang);
     else rc = pack_limits_t<P32, float4>(ctx, ctx->p32, t0, &lim, &lang);
@@ -879,6 +899,7 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
     if (!first && op->n_exit_bins != ctx->op.n_exit_bins)
         return fail(ctx, MC_ESTATE, "the number of exit bins is fixed by the first operating point");
     ctx->op = *op;
+    ctx->dt_rec_valid = false;  // RF and step settings may have changed
     ctx->has_op = true;
     for (size_t k = 0; k < ctx->ions.size(); ++k) ctx_alpha(ctx, k);
     int32_t rc = upload_species(ctx);
@@ -935,26 +956,113 @@ int32_t mc_inject(mc_ctx *ctx, int32_t src_id, int64_t n) {
     return emit(ctx, src_id, n);
 }
 
+// Trajectory samples at the start of the current step when it is one of the
+// sampled steps (dyn: the device step record of an adaptive run, whose
+// halted state stops sampling).
+static int32_t sample_if_due(mc_ctx *ctx, const double *dyn) {
+    if (!(ctx->op.sample_every > 0 && ctx->op.sample_stride > 0 && ctx->step % ctx->op.sample_every == 0 &&
+          ctx->n_slots > 0))
+        return MC_OK;
+    const unsigned sgrid = (unsigned)((ctx->n_slots + kSampleThreads - 1) / kSampleThreads);
+    if (ctx->fp32())
+        k_sample<float><<<sgrid, kSampleThreads, 0, ctx->stream>>>(ctx->p32, ctx->sp_dev, ctx->n_slots, ctx->step,
+                                                                   ctx->op.sample_stride, ctx->samples,
+                                                                   ctx->sample_count, ctx->sample_cap, dyn);
+    else
+        k_sample<double><<<sgrid, kSampleThreads, 0, ctx->stream>>>(ctx->p64, ctx->sp_dev, ctx->n_slots, ctx->step,
+                                                                    ctx->op.sample_stride, ctx->samples,
+                                                                    ctx->sample_count, ctx->sample_cap, dyn);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
+// Whether no source emits any more (emission needs each step's length on
+// the host: Eq. 5 counts and weights).
+static bool sources_idle(const mc_ctx *ctx) {
+    for (const Src &S : ctx->srcs)
+        if (S.in.kind != 0 && S.emitted < S.in.n_total) return false;
+    return true;
+}
+
+// Adaptive steps with the step length kept on the device: up to max_steps
+// steps, as many as can run before a space-charge update could fall due
+// (the time grows by at most dt_max per step), then one read of the step
+// record.  *done receives the steps taken.
+static int32_t adaptive_batch(mc_ctx *ctx, int64_t max_steps, int64_t *done) {
+    *done = 0;
+    int32_t rc = adaptive_buffers(ctx);
+    if (rc) return rc;
+    const mc_operating &op = ctx->op;
+    if (!ctx->dt_rec_valid) {
+        double init[8] = {ctx->t, 0.0, 0.0, 0.0, 0.0, ctx->t, 0.0, 0.0};
+        double c[3];
+        rf_stages_at(op, ctx->t, 0.0, c);
+        init[6] = c[0];
+        HIPCHK(hipMemcpyAsync(ctx->dt_rec, init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+        ctx->dt_rec_valid = true;
+    }
+    const double tol = 1e-6 * op.dt, t0 = ctx->t;
+    int64_t k = max_steps;
+    for (int64_t j = 0; j < k; ++j) {
+        rc = sample_if_due(ctx, ctx->dt_rec);
+        if (rc) return rc;
+        if (j == 0 && op.sc_on) {
+            if (t0 >= ctx->t_next_pic - tol) {
+                rc = pic_update(ctx);
+                if (rc) return rc;
+                const double period = op.sc_every * op.dt;
+                while (ctx->t_next_pic <= t0 + tol) ctx->t_next_pic += period;
+            }
+            // the first step whose start could reach the next update's time
+            const double room = ctx->t_next_pic - tol - t0;
+            k = std::min<int64_t>(max_steps, std::max<int64_t>(1, (int64_t)std::ceil(room / op.dt)));
+        }
+        if (!ctx->fp32()) rc = pack_limits_dev<P64, double4>(ctx, ctx->p64);
+        else if (ctx->bf16()) rc = pack_limits_dev<P32, bf16x4>(ctx, ctx->p32);
+        else rc = pack_limits_dev<P32, float4>(ctx, ctx->p32);
+        if (rc) return rc;
+        const double inf = HUGE_VAL;
+        k_dt_finish<<<1, kHotRep, 0, ctx->stream>>>(
+            ctx->dt_rep, ctx->dt_rec, op.dt, (op.v_rf != 0.0 && op.f_rf > 0.0) ? 0.05 / op.f_rf : inf,
+            op.lv_dt_max > 0.0 ? op.lv_dt_max : inf, op.sc_on ? ctx->t_next_pic : inf, 1e-9 * op.dt, op.v_rf,
+            2.0 * kPi * op.f_rf, op.phase_rf, ctx->step);
+        LAUNCHCHK();
+        rc = step_once(ctx, 0.0, op.dt, ctx->dt_rec);
+        if (rc) return rc;
+        ctx->step++;
+        ++*done;
+    }
+    double rec[8];
+    HIPCHK(hipMemcpyAsync(rec, ctx->dt_rec, sizeof(rec), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    uint64_t halted;
+    std::memcpy(&halted, &rec[7], sizeof(halted));
+    ctx->t = rec[5];
+    if (halted) {
+        ctx->step = (int64_t)halted - 1;
+        return fail(ctx, MC_ENUMERIC, "adaptive step collapsed below 1e-9 dt at step " + std::to_string(ctx->step));
+    }
+    ctx->last_dt = rec[1];
+    return MC_OK;
+}
+
 int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
     if (!ctx) return MC_EINVAL;
     if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
     if (n_steps < 0) return fail(ctx, MC_EINVAL, "negative step count");
     HIPCHK(hipSetDevice(ctx->opt.device));
-    for (int64_t it = 0; it < n_steps; ++it) {
+    for (int64_t it = 0; it < n_steps;) {
         int32_t rc;
-        if (ctx->op.sample_every > 0 && ctx->op.sample_stride > 0 && ctx->step % ctx->op.sample_every == 0 &&
-            ctx->n_slots > 0) {
-            const unsigned sgrid = (unsigned)((ctx->n_slots + kSampleThreads - 1) / kSampleThreads);
-            if (ctx->fp32())
-                k_sample<float><<<sgrid, kSampleThreads, 0, ctx->stream>>>(
-                    ctx->p32, ctx->sp_dev, ctx->n_slots, ctx->step, ctx->op.sample_stride, ctx->samples,
-                    ctx->sample_count, ctx->sample_cap);
-            else
-                k_sample<double><<<sgrid, kSampleThreads, 0, ctx->stream>>>(
-                    ctx->p64, ctx->sp_dev, ctx->n_slots, ctx->step, ctx->op.sample_stride, ctx->samples,
-                    ctx->sample_count, ctx->sample_cap);
-            LAUNCHCHK();
+        if (ctx->op.adaptive && sources_idle(ctx)) {
+            int64_t done = 0;
+            rc = adaptive_batch(ctx, n_steps - it, &done);
+            if (rc) return rc;
+            it += done;
+            continue;
         }
+        ctx->dt_rec_valid = false;  // the host advances the time below
+        rc = sample_if_due(ctx, nullptr);
+        if (rc) return rc;
         double t0 = (double)ctx->step * ctx->op.dt, dt = ctx->op.dt;
         if (ctx->op.adaptive) {
             t0 = ctx->t;
@@ -981,6 +1089,7 @@ int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
         ctx->last_dt = dt;
         ctx->t = ctx->op.adaptive ? t0 + dt : (double)(ctx->step + 1) * ctx->op.dt;
         ctx->step++;
+        ++it;
     }
     return MC_OK;
 }
@@ -1270,6 +1379,7 @@ int32_t mc_load_state(mc_ctx *ctx, const char *path) {
     if (!ctx->has_fields || !ctx->has_op) return fail(ctx, MC_ESTATE, "fields and operating point required");
     HIPCHK(hipSetDevice(ctx->opt.device));
     ctx->dep_full = true;  // the restored charge grid may hold charge anywhere
+    ctx->dt_rec_valid = false;
     HIPCHK(hipStreamSynchronize(ctx->stream));
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(ctx, MC_EINVAL, std::string("cannot read ") + path);
