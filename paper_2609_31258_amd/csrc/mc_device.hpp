@@ -101,6 +101,9 @@ struct P64 {
     // square root estimate (within 2^-23) refined by sqrt_seeded
     static __device__ __forceinline__ double sqrt_(double x) { return sqrt_seeded(x, __builtin_amdgcn_rsq(x)); }
     static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    // 1/x for x positive and normal: the hardware estimate refined by
+    // recip_seeded (within 1 ulp)
+    static __device__ __forceinline__ double rcp(double x) { return recip_seeded(x, __builtin_amdgcn_rcp(x)); }
     static __device__ __forceinline__ double exp_(double x) { return exp(x); }
     // every call site passes a positive ratio (the Einstein-model inverse,
     // called in the step kernels only, after prepare_ln)
@@ -130,6 +133,7 @@ struct P32 {
     static __device__ __forceinline__ float ln_fast(float x) { return ln(x); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float exp_(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896f); }
     static __device__ __forceinline__ float log1p_(float x) { return ln(1.0f + x); }
     static __device__ __forceinline__ void sc2pi(float u, float *s, float *c) {

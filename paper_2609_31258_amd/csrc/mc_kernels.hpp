@@ -374,19 +374,21 @@ __device__ __forceinline__ void collide_explicit(const StepArgs<P, Tab> &a, cons
     const T M = m + mg, fm = P::div(mg, M), fi = P::div(m, M), mu = mg * fi;  // no m*mg product (FP32 range)
     const T two_mu = P::div((T)2, mu);
     const T alpha = (T)sp.alpha, skt = (T)sp.skt, theta = (T)sp.theta;
+    const T alpha2 = alpha * alpha;
     const T ux = g.ux, uy = g.uy, uz = g.uz, ngs = g.ngs;
     T rx = vx - ux, ry = vy - uy, rz = vz - uz;
     // candidate cap; a non-finite rate ends the loop at once
     const T nexp = lam * dt;
     const int32_t cap = (nexp < (T)1e6) ? 64 + 8 * (int32_t)ceil(nexp) : (nexp >= (T)1e6 ? 8000064 : 0);
     T tleft = dt;
+    T inv_lam = P::rcp(lam);  // the waits' scale, refreshed with the rate
     for (int32_t c = 0;; ++c) {
         if (c == cap) {
             ++pc.cap;
             break;
         }
         const W4 wa = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c), k0, k1);
-        const T tau = -P::div(P::ln_fast(P::u01(wa.w0)), lam);
+        const T tau = -P::ln_fast(P::u01(wa.w0)) * inv_lam;
         if (!(tau < tleft)) break;
         tleft -= tau;
         ++pc.cand;
@@ -404,9 +406,11 @@ __device__ __forceinline__ void collide_explicit(const StepArgs<P, Tab> &a, cons
         const T wx = wn * st * cph, wy = wn * st * sph, wz = wn * ct;
         const T gx = rx - wx, gy = ry - wy, gz = rz - wz;
         const T g2 = gx * gx + gy * gy + gz * gz;
-        const T gn = P::sqrt_(g2);
-        const T uacc = P::u01(wb.w3);
-        if (!(uacc * (sv + wn) < gn)) continue;
+        // acceptance u (s + |w|) < |g| and the exchange select u (s + |w|) <
+        // alpha |g|, both sides non-negative: compared squared, with no root
+        const T lhs = P::u01(wb.w3) * (sv + wn);
+        const T lhs2 = lhs * lhs;
+        if (!(lhs2 < g2)) continue;
         ++pc.acc;
         const W4 wc = draw(id, a.step, kPurposeCollide, (uint32_t)(3 * c + 2), k0, k1);
         // centre of mass of the ion and the partner (lab velocity u + w)
@@ -414,7 +418,7 @@ __device__ __forceinline__ void collide_explicit(const StepArgs<P, Tab> &a, cons
         const T et = (T)0.5 * mu * g2;
         T etp = et;
         // exchange select: the acceptance residual, uniform given acceptance
-        if (uacc * (sv + wn) < alpha * gn) {  // residual uacc (s + |w|)/|g| < alpha
+        if (lhs2 < alpha2 * g2) {  // residual u (s + |w|)/|g| < alpha
             ++pc.exch;
             const T te = einstein_t<P>(e + el, skt, theta);
             etp = -(T)kB * te * P::ln_fast(P::u01(wc.w2) * P::u01(wc.w3));
@@ -441,6 +445,7 @@ __device__ __forceinline__ void collide_explicit(const StepArgs<P, Tab> &a, cons
         rz = vz - uz;
         sv = P::sqrt_(rx * rx + ry * ry + rz * rz);
         lam = ngs * (sv + abar);
+        inv_lam = P::rcp(lam);
     }
 }
 

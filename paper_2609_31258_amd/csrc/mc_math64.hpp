@@ -14,6 +14,7 @@
 //
 //   div_mid(n, d)        n / d for d in [1, 4), |n| < 1 (its quotient step)
 //   sqrt_seeded(x, r)    sqrt x from a reciprocal-square-root estimate r
+//   recip_seeded(x, r)   1/x from a reciprocal estimate r (within 1 ulp)
 //   ln_pos(x)            natural logarithm, x > 0 normal and finite (series)
 //   ln_tab(x, tab)       the same from a 256-bin table (ln_table_fill)
 //   ln1p_tab(x, tab)     ln(1 + x), x >= 0 (+inf gives +inf), from the table
@@ -69,6 +70,16 @@ MC_HD double sqrt_seeded(double x, double r) {
     h = std::fma(h, e, h);
     y = std::fma(std::fma(-y, y, x), h, y);
     return x > 0.0 ? y : 0.0;
+}
+
+// 1/x for x positive and normal from an estimate r within 2^-20 relative:
+// two Newton steps r + r (1 - x r), each squaring the relative error, leave
+// it below the final rounding (within one unit in the last place; not
+// always the correctly rounded quotient).
+MC_HD double recip_seeded(double x, double r) {
+    r = std::fma(r, std::fma(-x, r, 1.0), r);
+    r = std::fma(r, std::fma(-x, r, 1.0), r);
+    return r;
 }
 
 // 2 atanh f = 2 (f + f^3/3 + f^5/5 + ...) for f = num / den, |f| <= 0.1716

@@ -101,3 +101,38 @@ def test_server_runs_adaptive_queries_and_refuses_a_negative_langevin_cap():
         with pytest.raises(mucite.MucateError) as e:
             s.submit(ion, src, synth.Operating(**{**op.__dict__, "lv_dt_max": -1.0}), n_steps=10, seed=1)
         assert e.value.code == mucite.MC_EINVAL
+
+
+def test_collapsed_step_halts_the_run_like_the_oracle():
+    """A largest step of 1 s against a collision limit near 1e-12 s: the first
+    Eq. 1 step collapses below 1e-9 of the largest step.  Both sides stop
+    there with the step counter at 0, after the samples of step 0; the GPU's
+    later steps of the same call take no samples and advance no pack."""
+    from oracle.binding import OracleSim
+    from paper_2609_31258_amd import mucite
+    f = synth.uniform_fields(16, 128, 5e-5, p=1e5, t_gas=300.0)
+    ion = synth.Ion(500.0, 1, 2e-18, 150)
+    op = synth.Operating(dt=1.0, z_det=f.grid.L, r_det=f.grid.R, collisions_on=1, adaptive=1, sample_every=1,
+                         sample_stride=1)
+    n = 100
+    snap = dict(x=np.zeros(n), y=np.zeros(n), z=np.linspace(1e-3, 2e-3, n), vx=np.zeros(n), vy=np.zeros(n),
+                vz=np.full(n, 50.0), e_int=np.full(n, 1e-19), h=np.zeros(n), w=np.ones(n),
+                id=np.arange(n, dtype=np.int64), tag=np.zeros(n, np.int32))
+    _say("collapsed adaptive step")
+    g = mucite.Sim(seed=7, pack_capacity=n, precision=0, sample_capacity=10 * n)
+    g.setup(f, [ion], [], op)
+    g.write_packs(snap)
+    o = OracleSim(7)
+    o.setup(f, [ion], [], op)
+    o.write_packs(snap)
+    with pytest.raises(mucite.MucateError) as e:
+        g.step(5)
+    assert e.value.code == mucite.MC_ENUMERIC
+    with pytest.raises(Exception):
+        o.step(5)
+    assert g.info()["step"] == o.current_step == 0
+    assert len(g.read_samples()) == len(o.read_samples()) == n
+    assert g.read_tallies()["pack_steps"] == 0
+    p = g.read_packs()
+    assert np.array_equal(p["z"], snap["z"]) and np.array_equal(p["vz"], snap["vz"])
+    g.close()

@@ -6,7 +6,8 @@ products for the logarithms (series and table-driven, the latter also at both
 ends and the centre of every bin), positive ratios over the whole double
 range for log1p, uniform turns for the sine and cosine -- and at the ends of
 each domain; the seeded square root is correctly rounded from estimates eight
-times worse than the hardware's."""
+times worse than the hardware's, and the seeded reciprocal within 1 ulp from
+such estimates."""
 import os
 import subprocess
 
@@ -110,6 +111,15 @@ int main() {
         if (mc::sqrt_seeded(x, r) != std::sqrt(x)) { std::printf("FAIL sqrt %.17g\n", x); return 1; }
     }
     if (mc::sqrt_seeded(0.0, INFINITY) != 0.0) { std::puts("FAIL sqrt 0"); return 1; }
+    // the seeded reciprocal from estimates perturbed by up to 2^-20: within 1 ulp
+    double w_rcp = 0.0;
+    for (long k = 0; k < 1000000; ++k) {
+        const double m = 1.0 + ((double)(uint32_t)rng() + 0.5) * 0x1p-32;
+        const double x = std::ldexp(m, (int)(rng() % 2000) - 1000);
+        const double r = (double)(1.0L / (long double)x) * (1.0 + pert(rng) * 0x1p-20);
+        w_rcp = std::fmax(w_rcp, ulps(mc::recip_seeded(x, r), 1.0L / (long double)x));
+    }
+    if (w_rcp > 1.0) { std::printf("FAIL reciprocal %.3f ulp\n", w_rcp); return 1; }
     // bounds: 2 ulp, and 2.5 for the table sine and cosine (the node's own
     // rounding shows where the result is smaller than the node's value)
     const bool ok = std::fmax(std::fmax(w_ln, w_lnt), w_ln1p) <= 2.0 &&
