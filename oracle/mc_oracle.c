@@ -75,8 +75,8 @@ static void draw(const uint32_t key[2], int64_t id, int64_t step, uint32_t purpo
 }
 
 /* ------------------------------------------------------------------------ */
-/* Field bake: E = -grad(phi) on the nodes ("Electric fields are obtained     */
-/* from the baked potentials", coordinate-system section).  Reading: second- */
+/* Field bake: E = -grad(phi) on the nodes (the field comes from the baked  */
+/* potentials; "Coordinate system, static fields, and RF convention").  Reading: second- */
 /* order central differences, one-sided at the outer edges, E_r = 0 on the   */
 /* axis (symmetry).  Exact for a potential linear in r or z.                 */
 /* Pinned: linear potentials give uniform fields; a quadratic in r gives the  */
@@ -199,9 +199,9 @@ void orc_dst1(const double *in, int32_t m, double *out) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* Charge density from the int64 deposit grid ("Axisymmetric PIC space      */
-/* charge update": the deposited charge of a node is divided by its annular  */
-/* control volume).  The grid holds charge in units of e 2^-32.  Reading:   */
+/* Charge density from the int64 deposit grid (in "Axisymmetric PIC space    */
+/* charge update" a node's deposited charge is normalised by the volume of  */
+/* its ring-shaped control cell).  The grid holds charge in units of e 2^-32.  Reading:   */
 /* the control volume is the finite-volume cell of the radial operator      */
 /* below -- the disk of radius dr/2 on the axis, the annulus of width dr    */
 /* about r_i elsewhere:                                                     */
@@ -224,9 +224,9 @@ void orc_rho_from_charge(int32_t nr, int32_t nz, double dr, double dz, const int
 }
 
 /* ------------------------------------------------------------------------ */
-/* Cylindrical finite-volume Poisson equation ("The cylindrical Poisson      */
-/* operator is discretized in finite volume form over annular control        */
-/* volumes", dPhi/dr = 0 at r = 0, Phi = 0 at the axial and outer radial     */
+/* Cylindrical finite-volume Poisson equation ("Axisymmetric PIC space      */
+/* charge update": the radial operator is a finite-volume balance over ring */
+/* cells; dPhi/dr = 0 at r = 0, Phi = 0 at the axial and outer radial       */
 /* boundaries).  Unknowns Phi[i][j], 0 <= i <= nr-2, 1 <= j <= nz-2:         */
 /*   (A_r Phi)_i + (Phi_{i,j+1} - 2 Phi_{i,j} + Phi_{i,j-1}) / dz^2 = -rho/eps0 */
 /*   (A_r Phi)_0 = 4 (Phi_1 - Phi_0) / dr^2              (disk of radius dr/2) */
@@ -298,9 +298,10 @@ void orc_poisson(int32_t nr, int32_t nz, double dr, double dz, const double *rho
 }
 
 /* ------------------------------------------------------------------------ */
-/* The same equation with the metal-mask Dirichlet condition ("Zero         */
-/* perturbation potential is imposed at ... metal mask nodes"): Phi = 0 on   */
-/* every mask node among the unknowns, the equation above at all others.   */
+/* The same equation with the metal-mask Dirichlet condition (the space-    */
+/* charge section holds the perturbation potential at zero on the mask       */
+/* nodes too): Phi = 0 on every mask node among the unknowns, the equation  */
+/* above at all others.                                                     */
 /* Multiplying row (i, j) by w_i (w_0 = dr/8, w_i = r_i) makes the operator */
 /* symmetric; -W L restricted to the non-mask unknowns is symmetric positive */
 /* definite and is solved by conjugate gradients.  The preconditioner is the */
@@ -696,9 +697,9 @@ static double *dup_or_zero(const double *src, size_t n) {
     return d;
 }
 
-/* Electrode hit table ("A particle is classified as an electrode hit when it */
-/* enters a metal cell or approaches the metal surface within the configured  */
-/* hit distance").  Reading: the surface lies half a cell from a metal node,  */
+/* Electrode hit table ("Gas field and electrode mask coupling": a pack is  */
+/* lost on an electrode once it is inside a metal cell or nearer the metal   */
+/* surface than the hit distance).  Reading: the surface lies half a cell from a metal node,  */
 /* so a node is a hit node if it is metal or a metal node lies within         */
 /* d_hit + min(dr,dz)/2 of it.                                               */
 static void build_hit(orc_sim *s) {
@@ -822,8 +823,8 @@ static void gas_at(const orc_sim *s, double x, double y, double z, double u[3], 
     u[2] = uz;
 }
 
-/* Emission of one pack ("transverse coordinates are sampled from a          */
-/* truncated two-dimensional Gaussian", source section).  Reading for the    */
+/* Emission of one pack ("Continuous current Gaussian source": the          */
+/* transverse position is drawn from a 2-D Gaussian cut off at a radius).  Reading for the    */
 /* synthetic workloads: truncation radius r_trunc, injection at z_inj, and  */
 /* velocity = local gas flow + Maxwellian thermal velocity of the ion at the */
 /* local gas temperature (stands in for the capillary CFD sampling).         */
