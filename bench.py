@@ -151,6 +151,10 @@ def parse():
     ap.add_argument("--forms", default="fp64,fp32,hybrid",
                     help="comma list of the forms to time: fp64 (plain FP64 path), fp32 (FP32 math, BF16 tables, "
                          "two-float positions), hybrid (FP32 form with the Langevin branch in 0-1 mm)")
+    ap.add_argument("--sort-every", type=int, default=100,
+                    help="reorder the pack slots by species and cell every N steps (0 = never); the sorts fall "
+                         "inside the timed windows")
+    ap.add_argument("--large-sort-every", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=300,
                     help="steps of the workload's emission ramp the oracle runs for the CPU baseline")
@@ -212,11 +216,12 @@ def _timed(sim, steps: int):
                 classes=after["class_n"].tolist(), tallies=after, steps=steps, start_step=info["step"] - steps)
 
 
-def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False):
+def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False, sort_every: int = 0):
     """The workload from step 0: its emission ramp (2000 steps, 500 packs per
     step), `warmup` more steps, then the timed window on the full population."""
     from paper_2609_31258_amd import mucite, synth
     f, ions, srcs, op, _ = synth.config_c2()
+    op.sort_every = sort_every
     if langevin:  # hybrid form: aggregated relaxation in the dense first millimetre
         op.langevin_on, op.lv_z_lo, op.lv_z_hi, op.lv_switch = 1, 0.0, 1e-3, 0.05
     ramp = srcs[0].n_total // srcs[0].packs_per_step
@@ -384,7 +389,7 @@ def c5_snapshot(f, ions, n: int, seed: int, weights):
     return snap
 
 
-def run_large(steps: int, fill: bool, n_packs: int = 16_000_000):
+def run_large(steps: int, fill: bool, n_packs: int = 16_000_000, sort_every: int = 0):
     """The large configuration in the FP32 form (1024x8192 grid, 1.6e7 packs
     of ten species, space charge every 5 steps): a timed window of `steps`
     steps on the full population, started from a seeded snapshot of the
@@ -396,6 +401,7 @@ def run_large(steps: int, fill: bool, n_packs: int = 16_000_000):
     from oracle.binding import OracleSim, num_threads
     from paper_2609_31258_amd import mucite, synth
     f, ions, srcs, op, meta = synth.config_c5(n_packs=n_packs)
+    op.sort_every = sort_every
     # each species' pack weight: its share of the current over its packs per step
     w = [src.current_a * op.dt / (ion.charge_z * 1.602176634e-19) / src.packs_per_step for src, ion in zip(srcs, ions)]
     sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=1, timing=True)
@@ -430,7 +436,7 @@ def run_large(steps: int, fill: bool, n_packs: int = 16_000_000):
     _say(f"large: oracle slice {n_cpu * cpu_steps / wall_o:.3e} pack-steps/s ({wall_o:.1f} s)")
     return {"workload": "1024x8192 grid, 1.6e7 packs of ten species (200-5e4 Da, Arrhenius), 50 nA, "
                         "SC every 5 steps, dt=0.25 ns, FP32 form (BF16 tables); window " + start,
-            "steps": steps, "value": ps / r["wall"], "unit": "pack-steps/s",
+            "steps": steps, "sort_every": sort_every, "value": ps / r["wall"], "unit": "pack-steps/s",
             "ms_per_step": r["wall"] * 1e3 / steps, "active": r["active"], "classes": r["classes"],
             "collisions_per_s": r["coll"] / r["wall"], "candidates_per_pack_step": r["cand"] / max(ps, 1),
             "kernel_ms": r["timing"]["ms"], "roofline": roofline(r, "fp32", alpha),
@@ -465,7 +471,8 @@ def full_occupancy_snapshot(n_packs: int):
     return f, ions, op, snap
 
 
-def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_capacity: int = 0, **op_changes):
+def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_capacity: int = 0, sort_every: int = 0,
+                **op_changes):
     """One timed window of a full-population snapshot with some operating
     fields changed (the next rows: masked Poisson, snapshots, adaptive step).
     The first step (and with it the first space-charge update, where the
@@ -473,6 +480,7 @@ def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_
     import torch
     from paper_2609_31258_amd import mucite, synth
     f, ions, op, snap = full_occupancy_snapshot(n_packs)
+    op.sort_every = sort_every
     for k, v in op_changes.items():
         setattr(op, k, v)
     sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=precision, timing=True,
@@ -502,7 +510,7 @@ def run_variant(name: str, steps: int, n_packs: int, precision: int = 1, sample_
             "samples": n_samples, "kernel_ms": tim["ms"]}
 
 
-def run_next_rows(steps: int, n_packs: int = 1_000_000):
+def run_next_rows(steps: int, n_packs: int = 1_000_000, sort_every: int = 0):
     """The next rows on a full-population snapshot of the workload, FP32 form:
     a plain window, the masked Poisson solve (potential zero on the ring
     electrodes' mask nodes), full-population snapshots every 20 steps, and
@@ -512,16 +520,17 @@ def run_next_rows(steps: int, n_packs: int = 1_000_000):
     g = f.grid
     mask = f.mask.reshape(g.nz, g.nr)
     out = {"state": f"{n_packs} packs, seeded snapshot of the full population (FP32 form, BF16 tables)"}
-    out["plain"] = run_variant("plain", steps, n_packs)
-    out["masked_poisson"] = run_variant("masked poisson", steps, n_packs, sc_mask=1)
+    out["plain"] = run_variant("plain", steps, n_packs, sort_every=sort_every)
+    out["masked_poisson"] = run_variant("masked poisson", steps, n_packs, sc_mask=1, sort_every=sort_every)
     out["masked_poisson"]["mask_nodes"] = int(mask[1:-1, :-1].sum())
     out["snapshots"] = run_variant("snapshots", steps, n_packs, sample_capacity=n_packs * (steps // 20 + 2),
-                                   sample_every=20, sample_stride=1)
-    out["adaptive_explicit"] = run_variant("adaptive (explicit collisions)", steps, n_packs, adaptive=1)
+                                   sample_every=20, sample_stride=1, sort_every=sort_every)
+    out["adaptive_explicit"] = run_variant("adaptive (explicit collisions)", steps, n_packs, adaptive=1, sort_every=sort_every)
     out["hybrid_fixed"] = run_variant("hybrid, fixed 0.5 ns", steps, n_packs, langevin_on=1, lv_z_lo=0.0,
-                                      lv_z_hi=1e-3, lv_switch=0.05)
+                                      lv_z_hi=1e-3, lv_switch=0.05, sort_every=sort_every)
     out["adaptive_hybrid"] = run_variant("adaptive hybrid", steps, n_packs, langevin_on=1, lv_z_lo=0.0,
-                                         lv_z_hi=1e-3, lv_switch=0.05, adaptive=1, dt=2e-9, lv_dt_max=2e-9)
+                                         lv_z_hi=1e-3, lv_switch=0.05, adaptive=1, dt=2e-9, lv_dt_max=2e-9,
+                                         sort_every=sort_every)
     return out
 
 
@@ -593,11 +602,11 @@ def main():
         print(json.dumps({"error": f"unknown form list {args.forms!r}"}))
         sys.exit(2)
     if "fp64" in forms:
-        res["fp64"] = run_gpu(0, args.steps, args.warmup)
+        res["fp64"] = run_gpu(0, args.steps, args.warmup, sort_every=args.sort_every)
     if "fp32" in forms:
-        res["fp32"] = run_gpu(1, args.steps, args.warmup)
+        res["fp32"] = run_gpu(1, args.steps, args.warmup, sort_every=args.sort_every)
     if "hybrid" in forms:
-        res["hybrid"] = run_gpu(1, args.steps, args.warmup, langevin=True)
+        res["hybrid"] = run_gpu(1, args.steps, args.warmup, langevin=True, sort_every=args.sort_every)
     main_key = "fp64" if "fp64" in res else ("fp32" if "fp32" in res else "hybrid")
     r = res[main_key]
     value = r["pack_steps"] / r["wall"]
@@ -608,6 +617,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "grid": [256, 1024], "packs": r["slots"], "active": r["active"],
                    "ramp_steps": r["ramp_steps"], "first_timed_step": r["start_step"], "sc_every": 10,
+                   "sort_every": args.sort_every,
                    "dt_s": 0.5e-9, "precision": main_key},
         "roofline": hbm_roofline(r, "fp32", "step", "hybrid") if main_key == "hybrid" else roofline(r, main_key, default_alpha()),
         "collisions_per_s": r["coll"] / r["wall"],
@@ -637,9 +647,9 @@ def main():
     if not args.no_c1:
         out["c1_full"] = run_c1_full()
     if not args.no_large:
-        out["large"] = run_large(args.large_steps, args.large_fill)
+        out["large"] = run_large(args.large_steps, args.large_fill, sort_every=args.large_sort_every)
     if not args.no_next_rows:
-        out["next_rows"] = run_next_rows(args.steps)
+        out["next_rows"] = run_next_rows(args.steps, sort_every=args.sort_every)
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)

@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 4
+#define MC_ABI_VERSION 5
 
 enum {
     MC_OK = 0,
@@ -188,7 +188,21 @@ typedef struct mc_source {
  * the Langevin switch always compares with dt.  The lengths stay on the
  * device (see mc_step).  A step that collapses below 1e-9 dt fails with
  * MC_ENUMERIC.  The serving runtime runs it per query (see
- * mc_query). */
+ * mc_query).
+ *
+ * sort_every: at the start of every step n with n % sort_every == 0 (before
+ * the snapshots, the space-charge update and emission) the active packs are
+ * reordered by (species, lower-left node of their CIC cell) and the slots
+ * of terminal packs are dropped, so mc_read_packs then returns the active
+ * packs only and freed slots take new packs.  Slot order changes no pack's
+ * state and no integer tally (random streams are keyed by pack id and step);
+ * only the FP64 sums over the active population (sum_w_*_active) may change
+ * in their last bits, being reduced in slot order.  Sorting groups packs of
+ * like collision rate and place, for the step's wavefronts, the field
+ * gathers and the deposit (which then adds straight into the grid instead of
+ * grid copies).  0 = never; needs pack_capacity <= 2^28 and at most 2^32 - 2
+ * (species x nodes) keys (MC_EINVAL from mc_step otherwise).  The serving
+ * runtime ignores it. */
 typedef struct mc_operating {
     double dt, v_rf, f_rf, phase_rf, v_off, gas_mass_da;
     int32_t collisions_on, sc_on, sc_every;
@@ -200,6 +214,7 @@ typedef struct mc_operating {
     int32_t sample_every, sample_stride;
     int32_t adaptive;
     double lv_dt_max;
+    int32_t sort_every;
 } mc_operating;
 
 /* Pack population (host arrays of length n) for snapshot read/write.
@@ -259,7 +274,8 @@ typedef struct mc_info {
 } mc_info;
 
 /* Per-kernel timing from HIP events (requires mc_options.timing). */
-enum { MC_K_EMIT = 0, MC_K_STEP = 1, MC_K_DEPOSIT = 2, MC_K_POISSON = 3, MC_K_FIELD = 4, MC_K_TALLY = 5, MC_NKERNEL = 6 };
+enum { MC_K_EMIT = 0, MC_K_STEP = 1, MC_K_DEPOSIT = 2, MC_K_POISSON = 3, MC_K_FIELD = 4, MC_K_TALLY = 5, MC_K_SORT = 6,
+       MC_NKERNEL = 7 };
 typedef struct mc_timing {
     double ms[MC_NKERNEL];
     int64_t launches[MC_NKERNEL];

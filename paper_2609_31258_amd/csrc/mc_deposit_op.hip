@@ -107,8 +107,8 @@ int32_t launch_deposit(const mc_cic_packs *packs, const mc_grid *grid, int64_t *
         a.nr = grid->nr;
         a.nz = grid->nz;
         a.nrep = ncopies;
-        const unsigned nb =
-            (unsigned)std::min<int64_t>((packs->n + kDepositThreads - 1) / kDepositThreads, kDepositBlocks);
+        unsigned nb;
+        deposit_shape(packs->n, &nb, &a.chunk);
         k_deposit<P64><<<nb, kDepositThreads, 0, stream>>>(a);
     }
     // every node of the output written: the sums over the range, zero elsewhere

@@ -825,24 +825,38 @@ struct DepositArgs {
     unsigned long long *qrep;  // nrep zeroed copies of the grid, or null
     int32_t *range;            // lowest and highest node written (with qrep)
     int64_t n_slots, nn;
+    int64_t chunk;             // slots per sub-range (a multiple of the block size; see k_deposit)
     double inv_dr, inv_dz;
     int32_t nr, nz, nrep;
 };
 
 // Block-local aggregation: each block sums its packs' contributions in an
 // LDS hash table (open addressing) keyed by the CIC cell, i.e. the cell's
-// lower-left node: one compare-and-swap per pack, its four quanta added to
-// the entry's four slots (lower-left, upper-left, lower-right, upper-right),
-// and one device atomic per nonzero slot at the flush.  Packs concentrate in
-// a few cells near the source, so the flush still meets the other blocks'
-// flushes on the same few hundred addresses: each block therefore flushes into one of nrep zeroed copies of
-// the grid (block b into copy b mod nrep), which cuts those same-address
-// chains nrep-fold, and k_deposit_sum adds the copies over the node range
-// the blocks wrote into the grid (and clears them for the next update).
-// Integer sums make the result independent of the order.
+// lower-left node: one compare-and-swap per insertion, the four quanta added
+// to the entry's four slots (lower-left, upper-left, lower-right,
+// upper-right), and one device atomic per nonzero slot at the flush.
+//
+// Each block takes one contiguous range of `chunk` slots (a multiple of the
+// block size), so that sorted slots give each block a few cells that few
+// other blocks share (when the ranges were dealt out in several pieces per
+// block, the flushes of more blocks met on each cell and the deposit of
+// sorted packs ran at half the speed).  A thread sums the quanta
+// of its consecutive packs while they stay in one cell and inserts the sums
+// when the cell changes; at the end, where the runs of a wavefront's 64
+// lanes all lie in one cell, their sums are added across the wavefront in
+// registers (DPP row shifts and row broadcasts, no LDS traffic) and one
+// lane inserts them.  Once the slots are sorted by cell -- a cell then
+// holds thousands of consecutive packs -- a block makes a handful of
+// insertions; unsorted, about one per pack.  Packs of the source region concentrate
+// in a few cells, so when the slots are not sorted the blocks' flushes meet
+// on the same few hundred addresses: the caller may then give nrep zeroed
+// copies of the grid, block b flushing into copy b mod nrep, and
+// k_deposit_sum adds the copies over the node range the blocks wrote (and
+// clears them for the next update).  Integer sums make the result
+// independent of the order.
 constexpr int kDepHash = 2048;
 // Grid of the deposit: one block of 16 wavefronts per CU, each thread
-// reading two packs per pass with their loads issued together (four spill).
+// reading two packs per pass with their loads issued together.
 constexpr int64_t kDepositBlocks = 256;
 constexpr int kDepositThreads = 1024, kDepositUnroll = 2;
 // Copies of the grid for the flush: 16, fewer on grids where 16 copies would
@@ -853,9 +867,48 @@ inline int32_t deposit_copies(int64_t nn) {
     const int64_t r = kDepositRepBytes / (8 * nn);
     return (int32_t)(r >= kDepositMaxCopies ? kDepositMaxCopies : r < 1 ? 1 : r);
 }
+// Launch shape for n slots: blocks, and the slots of each block's range (a
+// multiple of the block size).
+inline void deposit_shape(int64_t n, unsigned *nb, int64_t *chunk) {
+    const int64_t b = (n + kDepositThreads - 1) / kDepositThreads;
+    *nb = (unsigned)(b < 1 ? 1 : (b > kDepositBlocks ? kDepositBlocks : b));
+    const int64_t c = (n + *nb - 1) / *nb;
+    *chunk = (c + kDepositThreads - 1) / kDepositThreads * kDepositThreads;
+}
 
-__device__ __forceinline__ void dep_cell(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
-                                         int32_t k, int32_t nr, int64_t a0, int64_t a1, int64_t b0, int64_t b1) {
+// One pack's cell and its four quanta (k = -1 when the position is not
+// finite):
+//   a = rint(Q (1-f)), b = Q - a, a0 = rint(a (1-g)), a1 = a - a0,
+//   b0 = rint(b (1-g)), b1 = b - b0.
+__device__ __forceinline__ void dep_split(double X, double Y, double Z, int64_t Q, double inv_dr, double inv_dz,
+                                          int32_t nr, int32_t nz, int32_t &k, int64_t &a0, int64_t &a1,
+                                          int64_t &b0, int64_t &b1) {
+#pragma clang fp contract(off)
+    k = -1;
+    a0 = a1 = b0 = b1 = 0;
+    if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) return;
+    const double r = sqrt(X * X + Y * Y);
+    const double ur = r * inv_dr, uz = Z * inv_dz;
+    double fi = floor(ur), fj = floor(uz);
+    if (fi > (double)(nr - 2)) fi = (double)(nr - 2);
+    if (fj > (double)(nz - 2)) fj = (double)(nz - 2);
+    if (fj < 0.0) fj = 0.0;
+    double f = ur - fi, g = uz - fj;
+    if (f > 1.0) f = 1.0;
+    if (g > 1.0) g = 1.0;
+    if (g < 0.0) g = 0.0;
+    const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
+    a0 = (int64_t)rint((double)qa * (1.0 - g));
+    a1 = qa - a0;
+    b0 = (int64_t)rint((double)qb * (1.0 - g));
+    b1 = qb - b0;
+    k = (int32_t)fj * nr + (int32_t)fi;
+}
+
+// Quanta of cell k into the block's table (or, when its probes find no
+// room, straight into the grid or its copy).
+__device__ __forceinline__ void dep_insert(int32_t *keys, unsigned long long *vals, unsigned long long *grid,
+                                           int32_t k, int32_t nr, int64_t a0, int64_t a1, int64_t b0, int64_t b1) {
     uint32_t h = ((uint32_t)k * 2654435761u) >> (32 - 11);
     for (int probe = 0; probe < 8; ++probe) {
         const int32_t old = atomicCAS(&keys[h], -1, k);
@@ -869,37 +922,35 @@ __device__ __forceinline__ void dep_cell(int32_t *keys, unsigned long long *vals
         }
         h = (h + 1) & (kDepHash - 1);
     }
-    // table crowded: go straight to the grid (or its copy)
     if (a0) atom_add(&grid[k], a0);
     if (a1) atom_add(&grid[k + nr], a1);
     if (b0) atom_add(&grid[k + 1], b0);
     if (b1) atom_add(&grid[k + nr + 1], b1);
 }
 
-// One pack's four CIC quanta into the block's table; lo/hi track the nodes.
-template <class P>
-__device__ __forceinline__ void dep_pack(const DepositArgs<typename P::T> &a, int32_t *keys, unsigned long long *vals,
-                                         unsigned long long *dst, double X, double Y, double Z, int64_t Q, int32_t &lo,
-                                         int32_t &hi) {
-#pragma clang fp contract(off)
-    if (!isfinite(X) || !isfinite(Y) || !isfinite(Z)) return;
-    const double r = sqrt(X * X + Y * Y);
-    const double ur = r * a.inv_dr, uz = Z * a.inv_dz;
-    double fi = floor(ur), fj = floor(uz);
-    if (fi > (double)(a.nr - 2)) fi = (double)(a.nr - 2);
-    if (fj > (double)(a.nz - 2)) fj = (double)(a.nz - 2);
-    if (fj < 0.0) fj = 0.0;
-    double f = ur - fi, g = uz - fj;
-    if (f > 1.0) f = 1.0;
-    if (g > 1.0) g = 1.0;
-    if (g < 0.0) g = 0.0;
-    const int64_t qa = (int64_t)rint((double)Q * (1.0 - f)), qb = Q - qa;
-    const int64_t a0 = (int64_t)rint((double)qa * (1.0 - g)), a1 = qa - a0;
-    const int64_t b0 = (int64_t)rint((double)qb * (1.0 - g)), b1 = qb - b0;
-    const int32_t k = (int32_t)fj * a.nr + (int32_t)fi;
-    dep_cell(keys, vals, dst, k, a.nr, a0, a1, b0, b1);
-    lo = min(lo, k);
-    hi = max(hi, k + a.nr + 1);
+// 64-bit DPP move of v (row_mask selects the rows that take the moved value;
+// lanes whose source is outside the row, and rows not selected, read 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, kCtrl, kRowMask, 0xf, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), kCtrl, kRowMask, 0xf, true);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Sum of v over the 64 lanes of a wavefront whose lanes are all active: an
+// inclusive scan within each row of 16 lanes (shifts 1, 2, 4, 8), then the
+// row totals carried across rows (broadcasts of lanes 15 and 31), which
+// leaves the total in lane 63.  Modulo 2^64, like the int64 grid.
+__device__ __forceinline__ uint64_t wave_total_u64(uint64_t v) {
+    v += dpp_u64<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_u64<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_u64<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_u64<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_u64<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_u64<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 template <class P>
@@ -918,9 +969,19 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
     }
     __syncthreads();
     unsigned long long *dst = a.qrep ? a.qrep + (int64_t)(blockIdx.x % (unsigned)a.nrep) * a.nn : a.q;
+    const int lane = threadIdx.x & 63;
     int32_t lo = INT32_MAX, hi = -1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t s0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s0 < a.n_slots; s0 += kDepositUnroll * stride) {
+    // the block's range in rows of blockDim.x slots; every wavefront of the
+    // block runs the same passes (its lanes stay together for the wavefront
+    // sums at the end)
+    const int64_t rows = a.chunk / blockDim.x, base = (int64_t)blockIdx.x * a.chunk;
+    const int64_t npass = (rows + kDepositUnroll - 1) / kDepositUnroll;
+    // the thread's run: consecutive packs of the thread in one cell are
+    // summed in registers and inserted once, when the cell changes or at the
+    // end (sorted slots: a cell holds thousands of consecutive packs)
+    int32_t rk = -1;
+    int64_t r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+    for (int64_t ps = 0; ps < npass; ++ps) {
         // the pass's reads first (a slot past the end reads nothing), then its packs
         int32_t st[kDepositUnroll];
         T x[kDepositUnroll], y[kDepositUnroll], z[kDepositUnroll], xl[kDepositUnroll], yl[kDepositUnroll],
@@ -928,11 +989,12 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
         int64_t q[kDepositUnroll];
 #pragma unroll
         for (int u = 0; u < kDepositUnroll; ++u) {
-            const int64_t s = s0 + u * stride;
+            const int64_t r = ps * kDepositUnroll + u;
+            const int64_t s = base + r * blockDim.x + threadIdx.x;
             st[u] = -1;
             x[u] = y[u] = z[u] = xl[u] = yl[u] = zl[u] = (T)0;
             q[u] = 0;
-            if (s < a.n_slots) {
+            if (r < rows && s < a.n_slots) {
                 st[u] = a.p.status[s];
                 x[u] = a.p.x[s];
                 y[u] = a.p.y[s];
@@ -954,7 +1016,38 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
                 Y += (double)yl[u];
                 Z += (double)zl[u];
             }
-            dep_pack<P>(a, keys, vals, dst, X, Y, Z, q[u], lo, hi);
+            int32_t k;
+            int64_t a0, a1, c0, c1;
+            dep_split(X, Y, Z, q[u], a.inv_dr, a.inv_dz, a.nr, a.nz, k, a0, a1, c0, c1);
+            if (k < 0) continue;
+            lo = min(lo, k);
+            hi = max(hi, k + a.nr + 1);
+            if (k != rk) {
+                if (rk >= 0) dep_insert(keys, vals, dst, rk, a.nr, r0, r1, r2, r3);
+                rk = k;
+                r0 = r1 = r2 = r3 = 0;
+            }
+            r0 += a0;
+            r1 += a1;
+            r2 += c0;
+            r3 += c1;
+        }
+    }
+    // the runs left at the end: one insertion of the wavefront's sums when
+    // all of its runs lie in one cell, else one per lane
+    {
+        const uint64_t act = __ballot(rk >= 0);
+        if (act != 0ull) {
+            const int lead = __builtin_ctzll(act);
+            const int32_t kl = __builtin_amdgcn_readlane(rk, lead);
+            if (__ballot(rk == kl || rk < 0) == ~0ull) {
+                const uint64_t s00 = wave_total_u64((uint64_t)r0), s01 = wave_total_u64((uint64_t)r1),
+                               s10 = wave_total_u64((uint64_t)r2), s11 = wave_total_u64((uint64_t)r3);
+                if (lane == lead)
+                    dep_insert(keys, vals, dst, kl, a.nr, (int64_t)s00, (int64_t)s01, (int64_t)s10, (int64_t)s11);
+            } else if (rk >= 0) {
+                dep_insert(keys, vals, dst, rk, a.nr, r0, r1, r2, r3);
+            }
         }
     }
     if (a.range) {
@@ -965,7 +1058,7 @@ __global__ __launch_bounds__(kDepositThreads) void k_deposit(DepositArgs<typenam
             lo = min(lo, __shfl_xor(lo, o, 64));
             hi = max(hi, __shfl_xor(hi, o, 64));
         }
-        if ((threadIdx.x & 63) == 0 && hi >= 0) {
+        if (lane == 0 && hi >= 0) {
             atomicMin(&blo, lo);
             atomicMax(&bhi, hi);
         }
@@ -1027,11 +1120,13 @@ static __global__ __launch_bounds__(256) void k_deposit_sum(unsigned long long *
 constexpr int64_t kDepositSumBlocks = 4096;
 
 // E = -grad(phi) on nodes: central differences, one-sided at the outer
-// edges, E_r = 0 on the axis.
+// edges, E_r = 0 on the axis.  clear (nullable): a charge grid zeroed on
+// the way, for the next deposit that adds into it.
 static __global__ __launch_bounds__(256) void k_bake(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
-                                              double dz) {
+                                                     double dz, unsigned long long *clear) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)nr * nz) return;
+    if (clear) clear[n] = 0ull;
     const int32_t i = (int32_t)(n % nr), j = (int32_t)(n / nr);
     double vr, vz;
     if (i == 0) vr = 0.0;
@@ -1172,7 +1267,11 @@ __global__ __launch_bounds__(256) void k_snapshot(PackPtrs<T> p, const Species *
     if (threadIdx.x < 2 && lact[threadIdx.x]) atomicAdd(&act[threadIdx.x], lact[threadIdx.x]);
 }
 
-static __global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, int64_t nb, double *out) {
+// Sums of the blocks' partials (three channels) in a fixed order; `retired`
+// (nullable) is added to the third: the survival-yield sum of terminal
+// packs whose slots a sort has dropped.
+static __global__ __launch_bounds__(256) void k_reduce_partials(const double *partial, int64_t nb, double *out,
+                                                                const double *retired) {
     __shared__ double red[3][256];
     double a[3] = {0.0, 0.0, 0.0};
     for (int64_t b = threadIdx.x; b < nb; b += blockDim.x)
@@ -1184,8 +1283,10 @@ static __global__ __launch_bounds__(256) void k_reduce_partials(const double *pa
             for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         for (int c = 0; c < 3; ++c) out[c] = red[c][0];
+        if (retired) out[2] += *retired;
+    }
 }
 
 // Trajectory samples: active packs with id % stride == 0, one record each.

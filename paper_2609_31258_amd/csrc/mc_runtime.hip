@@ -18,6 +18,7 @@
 #include "mc_host.hpp"
 #include "mc_kernels.hpp"
 #include "mc_poisson.hpp"
+#include "mc_sort.hpp"
 
 using namespace mc;
 
@@ -58,6 +59,9 @@ struct mc_ctx {
 
     unsigned long long *qgrid = nullptr;
     unsigned long long *qrep = nullptr;  // the deposit's copies of the grid (nrep of them, kept zeroed)
+    // with sorted slots the deposit flushes straight into a zeroed grid: the
+    // other of two grids, cleared by the field bake of the update after it
+    unsigned long long *qnext = nullptr;
     int32_t nrep = 1, dep_slot = 0;
     int32_t *dep_range = nullptr;        // three (lowest, highest) node slots, rotating by update
     bool dep_full = true;                // the next sum writes every node (the grid may hold charge anywhere)
@@ -91,6 +95,13 @@ struct mc_ctx {
     int64_t cap = 0, n_slots = 0;
     PackPtrs<double> p64{};
     PackPtrs<float> p32{};
+    // sorting of the slots (sort_every): the second set of pack arrays the
+    // sorted packs are gathered into, and the radix sort's work arrays
+    PackPtrs<double> p64b{};
+    PackPtrs<float> p32b{};
+    uint32_t *skey[2] = {nullptr, nullptr}, *sidx[2] = {nullptr, nullptr}, *shist = nullptr, *stot = nullptr;
+    unsigned long long *sactive = nullptr;
+    double *retired = nullptr;  // survival-yield sum of the terminal packs whose slots sorts dropped
 
     unsigned long long *tal = nullptr;  // cnt | exit_bins | loss_map | hist_ke | hist_teff | hist_r
     TallyPtrs tp{};
@@ -230,6 +241,33 @@ static int32_t upload_species(mc_ctx *ctx) {
                           ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));
     return MC_OK;
+}
+
+// One set of pack arrays of the context's capacity.
+static int32_t alloc_packs(mc_ctx *ctx, PackPtrs<float> &p) {
+    int32_t rc = MC_OK;
+    const int64_t cap = ctx->cap;
+    float **fl[] = {&p.x, &p.y, &p.z, &p.xl, &p.yl, &p.zl, &p.vx, &p.vy, &p.vz, &p.e, &p.el, &p.h};
+    for (auto f : fl)
+        if (!rc) rc = dalloc_t(ctx, f, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.w, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.id, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.q, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.tag, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.status, cap);
+    return rc;
+}
+static int32_t alloc_packs(mc_ctx *ctx, PackPtrs<double> &p) {
+    int32_t rc = MC_OK;
+    const int64_t cap = ctx->cap;
+    double **fl[] = {&p.x, &p.y, &p.z, &p.vx, &p.vy, &p.vz, &p.e, &p.h, &p.w};
+    for (auto f : fl)
+        if (!rc) rc = dalloc_t(ctx, f, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.id, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.q, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.tag, cap);
+    if (!rc) rc = dalloc_t(ctx, &p.status, cap);
+    return rc;
 }
 
 static void ctx_alpha(mc_ctx *ctx, size_t k) { species_alpha(ctx->sp_host[k], ctx->ions[k], ctx->op.gas_mass_da); }
@@ -466,10 +504,118 @@ static int32_t mask_setup(mc_ctx *ctx) {
     return MC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Sorting of the slots by (species, cell) with the terminal slots dropped
+// (mc_sort.hpp).  The work arrays and the second set of pack arrays are
+// allocated at the first sort.  One host read of the active count per sort.
+// ---------------------------------------------------------------------------
+static int32_t sort_buffers(mc_ctx *ctx) {
+    if (ctx->sactive) return MC_OK;
+    if (ctx->cap > kSortMaxSlots) return fail(ctx, MC_EINVAL, "sorting needs pack_capacity <= 2^28");
+    int32_t rc = ctx->fp32() ? alloc_packs(ctx, ctx->p32b) : alloc_packs(ctx, ctx->p64b);
+    const int64_t tiles = (ctx->cap + kSortTile - 1) / kSortTile;
+    for (int k = 0; k < 2 && !rc; ++k) {
+        rc = dalloc_t(ctx, &ctx->skey[k], ctx->cap);
+        if (!rc) rc = dalloc_t(ctx, &ctx->sidx[k], ctx->cap);
+    }
+    if (!rc) rc = dalloc_t(ctx, &ctx->shist, (size_t)kRadixBins * tiles);
+    if (!rc) rc = dalloc_t(ctx, &ctx->stot, (size_t)(kRadixBins * tiles + kSortTile - 1) / kSortTile);
+    if (!rc) rc = dalloc_t(ctx, &ctx->sactive, 1);
+    if (rc) ctx->sactive = nullptr;
+    return rc;
+}
+
+template <class T>
+static int32_t sort_packs_t(mc_ctx *ctx, PackPtrs<T> &p, PackPtrs<T> &alt) {
+    const int64_t n = ctx->n_slots;
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz, n_keys = (int64_t)ctx->ions.size() * nn;
+    if (n_keys >= (int64_t)0xFFFFFFFF) return fail(ctx, MC_EINVAL, "too many (species x node) keys to sort");
+    int32_t rc = sort_buffers(ctx);
+    if (rc) return rc;
+    const int passes = sort_passes(n_keys);
+    const uint32_t dead = passes == 4 ? 0xFFFFFFFFu : (uint32_t)((1ull << (8 * passes)) - 1);
+    const int64_t tiles = (n + kSortTile - 1) / kSortTile, hlen = kRadixBins * tiles;
+    const unsigned scan_blocks = (unsigned)((hlen + kSortTile - 1) / kSortTile);
+    {
+        Timer t(ctx, MC_K_SORT);
+        k_sort_keys<T><<<grid_for(n), kBlock, 0, ctx->stream>>>(p, n, ctx->nr, ctx->nz, ctx->inv_dr, ctx->inv_dz, nn,
+                                                                dead, ctx->skey[0], ctx->sidx[0], ctx->partial);
+        LAUNCHCHK();
+        k_retire<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, (int64_t)grid_for(n), ctx->sactive, ctx->retired);
+        LAUNCHCHK();
+        int cur = 0;
+        for (int pass = 0; pass < passes; ++pass) {
+            const int32_t shift = 8 * pass;
+            k_radix_count<<<(unsigned)tiles, kSortThreads, 0, ctx->stream>>>(ctx->skey[cur], n, shift, ctx->shist,
+                                                                             tiles);
+            LAUNCHCHK();
+            k_scan_tiles<<<scan_blocks, kSortThreads, 0, ctx->stream>>>(ctx->shist, hlen, ctx->stot);
+            LAUNCHCHK();
+            k_scan_totals<<<1, kSortThreads, 0, ctx->stream>>>(ctx->stot, scan_blocks);
+            LAUNCHCHK();
+            k_radix_scatter<<<(unsigned)tiles, kSortThreads, 0, ctx->stream>>>(
+                ctx->skey[cur], ctx->sidx[cur], ctx->skey[1 - cur], ctx->sidx[1 - cur], n, shift, ctx->shist,
+                ctx->stot, tiles);
+            LAUNCHCHK();
+            cur = 1 - cur;
+        }
+        k_sort_permute<T><<<grid_for(n), kBlock, 0, ctx->stream>>>(p, alt, ctx->sidx[cur], n, ctx->sactive);
+        LAUNCHCHK();
+    }
+    unsigned long long active = 0;
+    HIPCHK(hipMemcpyAsync(&active, ctx->sactive, sizeof(active), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    std::swap(p, alt);
+    ctx->n_slots = (int64_t)active;
+    return MC_OK;
+}
+
+// The sort at the start of step `step` when one is due (every sort_every
+// steps, counted from step 0).
+static int32_t sort_if_due(mc_ctx *ctx) {
+    if (!(ctx->op.sort_every > 0 && ctx->step % ctx->op.sort_every == 0 && ctx->n_slots > 0)) return MC_OK;
+    return ctx->fp32() ? sort_packs_t(ctx, ctx->p32, ctx->p32b) : sort_packs_t(ctx, ctx->p64, ctx->p64b);
+}
+
+// Grid buffer the deposit adds into directly (sorted slots): allocated and
+// zeroed once, and from then on cleared by the field bake of the update
+// after the deposit that used it.
+static int32_t direct_grid(mc_ctx *ctx) {
+    if (ctx->qnext) return MC_OK;
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    int32_t rc = dalloc_t(ctx, &ctx->qnext, nn);
+    if (rc) return rc;
+    HIPCHK(hipMemsetAsync(ctx->qnext, 0, nn * sizeof(unsigned long long), ctx->stream));
+    return MC_OK;
+}
+
 template <class P, class D>
 static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     const int64_t nn = (int64_t)ctx->nr * ctx->nz;
-    {
+    // sorted slots: one deposit kernel adding straight into the zeroed grid
+    const bool direct = ctx->op.sort_every > 0;
+    if (direct) {
+        int32_t rc = direct_grid(ctx);
+        if (rc) return rc;
+        Timer t(ctx, MC_K_DEPOSIT);
+        if (ctx->n_slots > 0) {
+            DepositArgs<typename P::T> a{};
+            a.p = p;
+            a.q = ctx->qnext;
+            a.n_slots = ctx->n_slots;
+            a.nn = nn;
+            a.inv_dr = ctx->inv_dr;
+            a.inv_dz = ctx->inv_dz;
+            a.nr = ctx->nr;
+            a.nz = ctx->nz;
+            unsigned nb;
+            deposit_shape(ctx->n_slots, &nb, &a.chunk);
+            k_deposit<P><<<nb, kDepositThreads, 0, ctx->stream>>>(a);
+            LAUNCHCHK();
+        }
+        std::swap(ctx->qgrid, ctx->qnext);  // qnext now holds the previous deposit: cleared below
+        ctx->dep_full = true;               // a later sum over copies must write every node
+    } else {
         Timer t(ctx, MC_K_DEPOSIT);
         // slots: this deposit's range, the previous deposit's, and the next one's
         int32_t *range = ctx->dep_range + 2 * ctx->dep_slot, *prev = ctx->dep_range + 2 * ((ctx->dep_slot + 2) % 3),
@@ -487,8 +633,8 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
             a.nr = ctx->nr;
             a.nz = ctx->nz;
             a.nrep = ctx->nrep;
-            const unsigned nb = (unsigned)std::min<int64_t>((ctx->n_slots + kDepositThreads - 1) / kDepositThreads,
-                                                            kDepositBlocks);
+            unsigned nb;
+            deposit_shape(ctx->n_slots, &nb, &a.chunk);
             k_deposit<P><<<nb, kDepositThreads, 0, ctx->stream>>>(a);
             LAUNCHCHK();
         }
@@ -513,7 +659,8 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     }
     {
         Timer t(ctx, MC_K_FIELD);
-        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->phi_sc, ctx->e_sc, ctx->nr, ctx->nz, ctx->dr, ctx->dz);
+        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->phi_sc, ctx->e_sc, ctx->nr, ctx->nz, ctx->dr, ctx->dz,
+                                                         direct ? ctx->qnext : nullptr);
         LAUNCHCHK();
         int32_t rc = fold(ctx);
         if (rc) return rc;
@@ -537,11 +684,11 @@ static int32_t snapshot_t(mc_ctx *ctx, PackPtrs<T> p) {
         k_snapshot<T><<<(unsigned)nb, kBlock, 0, ctx->stream>>>(p, ctx->sp_dev, ctx->n_slots, ctx->snap,
                                                                ctx->snap + 2, ctx->snap + 2 + MC_HIST_KE, ctx->partial);
         LAUNCHCHK();
-        k_reduce_partials<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, nb, ctx->sums);
-        LAUNCHCHK();
-    } else {
-        HIPCHK(hipMemsetAsync(ctx->sums, 0, 4 * sizeof(double), ctx->stream));
     }
+    // with no slots the sums are zero, save the terminal packs a sort retired
+    k_reduce_partials<<<1, kBlock, 0, ctx->stream>>>(ctx->partial, ctx->n_slots > 0 ? nb : 0, ctx->sums,
+                                                     ctx->retired);
+    LAUNCHCHK();
     return MC_OK;
 }
 
@@ -601,6 +748,7 @@ std::vector<Blob> ckpt_blobs(mc_ctx *ctx, int64_t n_slots, int64_t n_exits, int6
     v.push_back({ctx->qgrid, nn * 8});
     v.push_back({ctx->samples, (size_t)n_samples * sizeof(mc_sample_rec)});
     v.push_back({ctx->sample_count, 8});
+    v.push_back({ctx->retired, 8});
     return v;
 }
 
@@ -662,27 +810,7 @@ int32_t mc_create(const mc_options *o, mc_ctx **out) {
     }
     ctx->cap = o->pack_capacity;
     const int64_t cap = ctx->cap;
-    int32_t rc = MC_OK;
-    if (ctx->fp32()) {
-        PackPtrs<float> &p = ctx->p32;
-        float **fl[] = {&p.x, &p.y, &p.z, &p.xl, &p.yl, &p.zl, &p.vx, &p.vy, &p.vz, &p.e, &p.el, &p.h};
-        for (auto f : fl)
-            if (!rc) rc = dalloc_t(ctx, f, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.w, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.id, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.q, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.tag, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.status, cap);
-    } else {
-        PackPtrs<double> &p = ctx->p64;
-        double **fl[] = {&p.x, &p.y, &p.z, &p.vx, &p.vy, &p.vz, &p.e, &p.h, &p.w};
-        for (auto f : fl)
-            if (!rc) rc = dalloc_t(ctx, f, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.id, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.q, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.tag, cap);
-        if (!rc) rc = dalloc_t(ctx, &p.status, cap);
-    }
+    int32_t rc = ctx->fp32() ? alloc_packs(ctx, ctx->p32) : alloc_packs(ctx, ctx->p64);
     const int64_t ecap = o->exit_capacity > 0 ? o->exit_capacity : cap;
     ctx->tp.exit_cap = ecap;
     if (!rc) rc = dalloc_t(ctx, &ctx->tp.exits, ecap);
@@ -691,6 +819,9 @@ int32_t mc_create(const mc_options *o, mc_ctx **out) {
     ctx->partial_len = (cap + kBlock - 1) / kBlock;
     if (!rc) rc = dalloc_t(ctx, &ctx->partial, 3 * ctx->partial_len);
     if (!rc) rc = dalloc_t(ctx, &ctx->sums, 4);
+    if (!rc) rc = dalloc_t(ctx, &ctx->retired, 1);
+    if (!rc && hipMemsetAsync(ctx->retired, 0, sizeof(double), ctx->stream) != hipSuccess)
+        rc = fail(ctx, MC_EDEVICE, "clearing the retired sum");
     if (!rc) rc = dalloc_t(ctx, &ctx->snap, 2 + MC_HIST_KE + MC_HIST_TEFF);
     ctx->sample_cap = o->sample_capacity;
     if (!rc && ctx->sample_cap > 0) rc = dalloc_t(ctx, &ctx->samples, ctx->sample_cap);
@@ -795,7 +926,7 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
     for (int k = 0; k < 3; ++k) {
         if (!phis[k]) continue;
         HIPCHK(hipMemcpyAsync(tmp, phis[k], nn * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(tmp, outs[k], g->nr, g->nz, g->dr, g->dz);
+        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(tmp, outs[k], g->nr, g->nz, g->dr, g->dz, nullptr);
         LAUNCHCHK();
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
@@ -891,7 +1022,7 @@ int32_t mc_set_operating(mc_ctx *ctx, const mc_operating *op) {
     if (!op || !(op->dt > 0) || op->sc_every < 1 || op->n_exit_bins < 1 || !(op->exit_bin_dt > 0) ||
         !(op->gas_mass_da > 0) || !(op->r_det > 0) || !(op->d_hit >= 0) ||
         (op->langevin_on && !(op->lv_switch >= 0)) || op->sample_every < 0 || op->sample_stride < 0 ||
-        !(op->lv_dt_max >= 0))
+        !(op->lv_dt_max >= 0) || op->sort_every < 0)
         return fail(ctx, MC_EINVAL, "invalid operating point");
     if (!ctx->has_fields) return fail(ctx, MC_ESTATE, "load fields first");
     HIPCHK(hipSetDevice(ctx->opt.device));
@@ -1003,6 +1134,12 @@ static int32_t adaptive_batch(mc_ctx *ctx, int64_t max_steps, int64_t *done) {
     }
     const double tol = 1e-6 * op.dt, t0 = ctx->t;
     int64_t k = max_steps;
+    if (op.sort_every > 0) {
+        // the stretch ends before the next sorted step
+        rc = sort_if_due(ctx);
+        if (rc) return rc;
+        k = std::min<int64_t>(k, op.sort_every - ctx->step % op.sort_every);
+    }
     for (int64_t j = 0; j < k; ++j) {
         rc = sample_if_due(ctx, ctx->dt_rec);
         if (rc) return rc;
@@ -1015,7 +1152,7 @@ static int32_t adaptive_batch(mc_ctx *ctx, int64_t max_steps, int64_t *done) {
             }
             // the first step whose start could reach the next update's time
             const double room = ctx->t_next_pic - tol - t0;
-            k = std::min<int64_t>(max_steps, std::max<int64_t>(1, (int64_t)std::ceil(room / op.dt)));
+            k = std::min<int64_t>(k, std::max<int64_t>(1, (int64_t)std::ceil(room / op.dt)));
         }
         if (!ctx->fp32()) rc = pack_limits_dev<P64, double4>(ctx, ctx->p64);
         else if (ctx->bf16()) rc = pack_limits_dev<P32, bf16x4>(ctx, ctx->p32);
@@ -1061,6 +1198,8 @@ int32_t mc_step(mc_ctx *ctx, int64_t n_steps) {
             continue;
         }
         ctx->dt_rec_valid = false;  // the host advances the time below
+        rc = sort_if_due(ctx);
+        if (rc) return rc;
         rc = sample_if_due(ctx, nullptr);
         if (rc) return rc;
         double t0 = (double)ctx->step * ctx->op.dt, dt = ctx->op.dt;

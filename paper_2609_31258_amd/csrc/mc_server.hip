@@ -339,9 +339,9 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         a.inv_dz = S->inv_dz;
         a.nr = S->nr;
         a.nz = S->nz;
-        k_deposit<P><<<(unsigned)std::min<int64_t>((Q.n_slots + kDepositThreads - 1) / kDepositThreads,
-                                                   kDepositBlocks),
-                       kDepositThreads, 0, S->stream>>>(a);
+        unsigned nb;
+        deposit_shape(Q.n_slots, &nb, &a.chunk);
+        k_deposit<P><<<nb, kDepositThreads, 0, S->stream>>>(a);
     }
     D *bh = static_cast<D *>(Q.bh);
     SCHK(poisson_solve<D>(S->pg, Q.qgrid, nullptr, bh, Q.phi, false, S->stream));
@@ -378,7 +378,7 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         }
         SCHK(mask_correct<D>(S->pg, S->cap, bh, Q.rhs, Q.phi, S->stream));
     }
-    k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.phi, Q.e_sc, S->nr, S->nz, S->dr, S->dz);
+    k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.phi, Q.e_sc, S->nr, S->nz, S->dr, S->dz, nullptr);
     SCHK(hipGetLastError());
     return fold_query<Tab>(S, Q);
 }
@@ -603,7 +603,7 @@ static int32_t retire_query(mc_server *S, Query &Q, PackPtrs<T> p) {
     if (Q.n_slots > 0) {
         k_snapshot<T><<<(unsigned)nb, kBlk, 0, S->stream>>>(p, Q.sp_dev, Q.n_slots, Q.snap, Q.snap + 2,
                                                            Q.snap + 2 + MC_HIST_KE, Q.partial);
-        k_reduce_partials<<<1, kBlk, 0, S->stream>>>(Q.partial, nb, Q.sums);
+        k_reduce_partials<<<1, kBlk, 0, S->stream>>>(Q.partial, nb, Q.sums, nullptr);
     } else {
         k_zero_u64<<<1, kBlk, 0, S->stream>>>((unsigned long long *)Q.sums, 4);
     }
@@ -853,7 +853,7 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
     for (int k = 0; k < 3; ++k) {
         if (!phis[k]) continue;
         SC2(hipMemcpyAsync(tmp, phis[k], nn * sizeof(double), hipMemcpyHostToDevice, S->stream));
-        k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(tmp, outs[k], g->nr, g->nz, g->dr, g->dz);
+        k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(tmp, outs[k], g->nr, g->nz, g->dr, g->dz, nullptr);
         SC2(hipStreamSynchronize(S->stream));
     }
     const double *gas[4] = {t->gas_ur, t->gas_uz, t->gas_p, t->gas_t};

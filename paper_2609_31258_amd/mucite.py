@@ -23,11 +23,12 @@ PD, PI64, PI32, PU8 = C.POINTER(F64), C.POINTER(I64), C.POINTER(I32), C.POINTER(
 
 MC_OK, MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE, MC_ENUMERIC, MC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PREC_FP64, PREC_FP32 = 0, 1
-ABI_VERSION = 4
+ABI_VERSION = 5
 NCLASS = 6
 HIST_KE, HIST_TEFF, HIST_R = 202, 202, 102
-K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY = range(6)
-KERNEL_NAMES = ("emit", "step", "deposit", "poisson", "field", "tally")
+K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY, K_SORT = range(7)
+KERNEL_NAMES = ("emit", "step", "deposit", "poisson", "field", "tally", "sort")
+NKERNEL = len(KERNEL_NAMES)
 
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
@@ -63,7 +64,8 @@ class Operating(C.Structure):
                 ("gas_mass_da", F64), ("collisions_on", I32), ("sc_on", I32), ("sc_every", I32),
                 ("z_det", F64), ("r_det", F64), ("d_hit", F64), ("exit_bin_dt", F64), ("n_exit_bins", I32),
                 ("langevin_on", I32), ("lv_z_lo", F64), ("lv_z_hi", F64), ("lv_switch", F64), ("sc_mask", I32),
-                ("sample_every", I32), ("sample_stride", I32), ("adaptive", I32), ("lv_dt_max", F64)]
+                ("sample_every", I32), ("sample_stride", I32), ("adaptive", I32), ("lv_dt_max", F64),
+                ("sort_every", I32)]
 
 
 class Packs(C.Structure):
@@ -106,7 +108,7 @@ class Info(C.Structure):
 
 
 class Timing(C.Structure):
-    _fields_ = [("ms", F64 * 6), ("launches", I64 * 6), ("pack_steps", I64)]
+    _fields_ = [("ms", F64 * NKERNEL), ("launches", I64 * NKERNEL), ("pack_steps", I64)]
 
 
 class ServerOptions(C.Structure):

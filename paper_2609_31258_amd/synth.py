@@ -106,6 +106,7 @@ class Operating:
     sample_stride: int = 0        # ... of the packs whose id is a multiple of sample_stride
     adaptive: int = 0             # Eq. 1 adaptive step (dt is then the largest step)
     lv_dt_max: float = 0.0        # adaptive: step cap while any pack is on the Langevin branch
+    sort_every: int = 0           # reorder the slots by species and cell every sort_every steps (0 = never)
 
 
 @dataclasses.dataclass
