@@ -68,6 +68,10 @@ OPS_EXCHANGE = 18         # internal-energy exchange (taken with probability alp
 # (two-float position and internal energy, FP32 velocity and hazard):
 # 64 + 48 B.  An inactive slot costs its status word (4 B).
 BYTES_STEP = {"fp64": 144, "fp32": 112}
+# A pack on the hybrid Langevin branch neither reads nor writes its internal
+# energy and hazard: FP32 form 52 B read (status, tag, id, position,
+# velocity) + 36 B written (position, velocity).
+BYTES_LANGEVIN = {"fp64": 112, "fp32": 88}
 # Deposit: status, position (FP64, or the FP32 form's hi+lo pairs) and the
 # int64 charge of every active pack (the LDS-aggregated grid atomics are
 # counted as L2 traffic, not HBM), plus one write of the int64 grid.
@@ -246,7 +250,9 @@ def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
     avg_s = ms / 1e3 / launches
     if kernel == "step":
         idle = max(r["slots"] * r["steps"] - r["pack_steps"], 0)
-        nbytes = (r["pack_steps"] * BYTES_STEP[precision] + 4 * idle) / launches
+        lang = r.get("langevin", 0)
+        nbytes = ((r["pack_steps"] - lang) * BYTES_STEP[precision] + lang * BYTES_LANGEVIN[precision] +
+                  4 * idle) / launches
     else:
         nbytes = r["active"] * BYTES_DEPOSIT[precision] + GRID_BYTES  # population nearly constant in the window
     achieved = nbytes / avg_s if avg_s > 0 else 0.0

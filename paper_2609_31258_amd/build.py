@@ -5,9 +5,12 @@
 compiles csrc/mc_runtime.hip (single simulations), csrc/mc_server.hip (serving)
 and csrc/mc_deposit_op.hip (the stand-alone deposit), which include the
 kernels, with hipcc into
-paper_2609_31258_amd/libmucite.so.  Flags: -O3, FMA contraction on (the
-kernels turn it off locally where results must be bit-reproducible), packed
-FP32 instructions disabled.
+paper_2609_31258_amd/libmucite.so.  Flags: -O3, FMA contraction within
+each source expression only (-ffp-contract=on: a kernel's rounding then
+follows its source, so the single-simulation and the serving kernels, which
+inline the same step code, round alike; the kernels turn contraction off
+locally where results must be bit-reproducible against plain IEEE
+arithmetic), packed FP32 instructions disabled.
 """
 import os
 import subprocess
@@ -29,7 +32,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=fast-honor-pragmas",
+    cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-shared", "-ffp-contract=on",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall", "-Wno-unused-function",
            "-I" + os.path.join(ROOT, "include"), "-o", tmp] + SOURCES
     if verbose:

@@ -11,7 +11,9 @@
 //   k_hit       electrode hit table from the mask and hit distance
 //   k_snapshot  read-time tallies of the active population
 //
-// The library is compiled with FMA contraction on; the blocks whose results
+// The library is compiled with FMA contraction within each source
+// expression (-ffp-contract=on), so the kernels that inline the same step
+// code round alike; the blocks whose results
 // must be reproducible bit for bit on any IEEE implementation given the same
 // positions (classification, deposit, hit table, histogram bins) switch it
 // off locally with `#pragma clang fp contract(off)`.
@@ -463,29 +465,41 @@ template <class P, class Tab>
 __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n, uint32_t k0, uint32_t k1) {
     using T = typename P::T;
     PackCount pc{0, 0, 0, 0, 0, 0};
-    if (s < a.n_slots && a.p.status[s] == ST_ACTIVE) {
-        n.act = 1;
-        // the species record by reference, so each field is read where it is
-        // used and the dissociation constants hold no registers through the
-        // collision loop (at five waves in the FP32 form and three in the FP64
-        // form they would spill)
-        const Species &sp = a.sp[a.p.tag[s]];
-        const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
-        const T x0 = a.p.x[s], y0 = a.p.y[s], z0 = a.p.z[s];
-        T xl = 0, yl = 0, zl = 0;
+    // the state is read together with the status word rather than after it
+    // (one memory round trip fewer before the first field gather; a slot that
+    // turns out inactive discards its reads)
+    int32_t status = -1, tag = 0;
+    T x0 = 0, y0 = 0, z0 = 0, xl = 0, yl = 0, zl = 0, vx0 = 0, vy0 = 0, vz0 = 0;
+    // the random-stream key: in the FP32 form read with the state (a read
+    // issued where the draws start would stall a Langevin step on memory a
+    // second time); the FP64 form reads it where the draws start, which
+    // keeps its registers free through the push
+    int64_t id = 0;
+    if (s < a.n_slots) {
+        status = a.p.status[s];
+        tag = a.p.tag[s];
+        x0 = a.p.x[s];
+        y0 = a.p.y[s];
+        z0 = a.p.z[s];
         if constexpr (P::kTwo) {
             xl = a.p.xl[s];
             yl = a.p.yl[s];
             zl = a.p.zl[s];
         }
-        const T xl0 = xl, yl0 = yl, zl0 = zl;
-        const T vx0 = a.p.vx[s], vy0 = a.p.vy[s], vz0 = a.p.vz[s];
-        // the random-stream key: in the FP32 form read with the state (a read
-        // issued where the draws start would stall a Langevin step on memory a
-        // second time); the FP64 form reads it where the draws start, which
-        // keeps its registers free through the push
-        int64_t id = 0;
+        vx0 = a.p.vx[s];
+        vy0 = a.p.vy[s];
+        vz0 = a.p.vz[s];
         if constexpr (P::kTwo) id = a.p.id[s];
+    }
+    if (status == ST_ACTIVE) {
+        n.act = 1;
+        // the species record by reference, so each field is read where it is
+        // used and the dissociation constants hold no registers through the
+        // collision loop (at five waves in the FP32 form and three in the FP64
+        // form they would spill)
+        const Species &sp = a.sp[tag];
+        const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
+        const T xl0 = xl, yl0 = yl, zl0 = zl;
 
         // ---- classical RK4 on (x, v); stages at t, t + dt/2, t + dt/2, t + dt ----
         T ex, ey, ez;
@@ -515,8 +529,6 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         acc2(y1, yl, d6 * sxy);
         acc2(z1, zl, d6 * sxz);
         T vx = vx0 + d6 * svx, vy = vy0 + d6 * svy, vz = vz0 + d6 * svz;
-        T e = a.p.e[s], el = (T)0;
-        if constexpr (P::kTwo) el = a.p.el[s];
 
         // ---- terminal classification at the new position ----
         // (the FP64 form performs exactly the IEEE operations of its reference;
@@ -551,6 +563,20 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         }
         }
 
+        // internal energy: read now unless the pack is in the Langevin window,
+        // whose branch leaves it unchanged (then it is read only if the pack
+        // turns out to need it, and not written back)
+        T e = (T)0, el = (T)0;
+        bool have_e = false;
+        const auto read_e = [&]() {
+            if (!have_e) {
+                e = a.p.e[s];
+                if constexpr (P::kTwo) el = a.p.el[s];
+                have_e = true;
+            }
+        };
+        if (!(a.langevin_on && (!(a.lv_z_hi > a.lv_z_lo) || (Z1 >= a.lv_z_lo && Z1 < a.lv_z_hi)))) read_e();
+
         // the position is final: store it now so it is not held through the collision loop
         a.p.x[s] = x1;
         a.p.y[s] = y1;
@@ -579,17 +605,23 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
                     langevin_relax(a, sp, P::kTwo ? id : a.p.id[s], k0, k1, g, vx, vy, vz);
                     ++pc.lang;
                 } else {
+                    read_e();
                     collide_explicit(a, sp, id, k0, k1, g, ag, abar, sv, lam, vx, vy, vz, e, el, pc);
                 }
             }
         }
         if (cls == ST_ACTIVE) {
             // ---- Eq. 7: hazard with the post-collision effective temperature ----
-            // (not accumulated in an aggregated Langevin step)
-            if (!lang) accumulate_hazard(a, sp, s, e, el);
-            a.p.e[s] = e;
-            if constexpr (P::kTwo) a.p.el[s] = el;
+            // (not accumulated in an aggregated Langevin step, which leaves the
+            // internal energy as it was)
+            if (!lang) {
+                read_e();
+                accumulate_hazard(a, sp, s, e, el);
+                a.p.e[s] = e;
+                if constexpr (P::kTwo) a.p.el[s] = el;
+            }
         } else {
+            read_e();
             record_exit(a, s, cls, in, jn, X1, Y1, Z1, (double)vx, (double)vy, (double)vz, tcross, rcross,
                         (double)e + (double)el, (double)a.p.h[s], sp);
             a.p.status[s] = cls;
