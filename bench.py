@@ -290,18 +290,21 @@ def default_alpha() -> float:
     return 4 * mg * ma / (mg + ma) ** 2
 
 
-def precision_report(t64, t32):
-    """Error of the FP32 form against the FP64 path on the same packs, seed and
-    steps: relative differences of the weighted mean kinetic and internal
-    energies, total-variation distance and Kolmogorov-Smirnov statistic of the
-    KE and T_eff histograms of the active population, class fractions."""
+def precision_report(t64, t32, hists=("act_hist_ke", "act_hist_teff")):
+    """Error of a run's tallies (t32) against a reference run's (t64) on the
+    same packs, seed and steps: relative differences of the weighted mean
+    kinetic and internal energies of the active population, total-variation
+    distance and Kolmogorov-Smirnov statistic of the histograms named, class
+    fractions by count and by weight."""
     import numpy as np
     out = {}
     w64, w32 = t64["class_w"][0], t32["class_w"][0]
     for k in ("sum_w_ke_active", "sum_w_eint_active"):
         a, b = t64[k] / max(w64, 1), t32[k] / max(w32, 1)
         out[k.replace("sum_w_", "rel_err_mean_")] = abs(b - a) / abs(a) if a else None
-    for h in ("act_hist_ke", "act_hist_teff"):
+    ew64, ew32 = max(t64["emitted_w"], 1), max(t32["emitted_w"], 1)
+    out["class_weight_fraction_diff"] = [float(a / ew64 - b / ew32) for a, b in zip(t64["class_w"], t32["class_w"])]
+    for h in hists:
         p, q = np.asarray(t64[h], float), np.asarray(t32[h], float)
         p, q = p / max(p.sum(), 1), q / max(q.sum(), 1)
         out["tv_" + h] = 0.5 * float(np.abs(p - q).sum())
@@ -309,6 +312,44 @@ def precision_report(t64, t32):
     n64, n32 = max(t64["class_n"].sum(), 1), max(t32["class_n"].sum(), 1)
     out["class_fraction_diff"] = [float(a / n64 - b / n32) for a, b in zip(t64["class_n"], t32["class_n"])]
     out["candidates_rel_diff"] = abs(t32["n_cand"] - t64["n_cand"]) / max(t64["n_cand"], 1)
+    return out
+
+
+def precision_vs_oracle():
+    """Each GPU form's error against the FP64 oracle on the same packs, seed
+    and steps, in two runs the oracle finishes in seconds: the space-charge
+    workload at a twentieth of its pack rate (25 packs per step, weights x20,
+    the same 10 nA) over 300 steps (30 space-charge updates; read-time
+    histograms of the active population), and the terminal-event variant of
+    the low-pressure fields (6000 packs in two bursts, 1200 steps of 5 ns:
+    every terminal class, transmitted KE/T_eff/exit-radius histograms)."""
+    from oracle.binding import OracleSim
+    from paper_2609_31258_amd import mucite, synth
+    out = {}
+    runs = {"space_charge": (lambda: synth.config_c2(n_packs=7500, packs_per_step=25), 300, None),
+            "terminal_events": (lambda: synth.config_c1x(4000, 2000), 1200, (4000, 2000))}
+    for name, (cfg, steps, bursts) in runs.items():
+        tallies = {}
+        for form, prec in (("oracle", None), ("fp64", 0), ("fp32", 1)):
+            f, ions, srcs, op, _ = cfg()
+            sim = OracleSim(synth.SEED) if prec is None else mucite.Sim(seed=synth.SEED, pack_capacity=7500, precision=prec)
+            sim.setup(f, ions, srcs, op)
+            for k, nb in enumerate(bursts or ()):
+                sim.inject(k, nb)
+            sim.step(steps)
+            tallies[form] = sim.read_tallies()
+            sim.close()
+        hists = ("act_hist_ke", "act_hist_teff") + (("hist_ke", "hist_teff", "hist_r", "exit_bins") if bursts else ())
+        out[name] = {form: precision_report(tallies["oracle"], tallies[form], hists) for form in ("fp64", "fp32")}
+        cls = tallies["oracle"]["class_n"]
+        out[name]["classes_oracle"] = cls.tolist()
+        # the statistical scale of the FP32 form's differences, whose paths
+        # part from the FP64 ones: two-sample KS critical values at alpha =
+        # 1e-3 for the active and the transmitted populations
+        ks = lambda n: 1.95 * math.sqrt(2.0 / n) if n > 0 else None
+        out[name]["ks_critical_active"] = ks(int(cls[0]))
+        out[name]["ks_critical_transmitted"] = ks(int(cls[1]))
+        _say(f"precision vs oracle, {name}: classes {tallies['oracle']['class_n'].tolist()}")
     return out
 
 
@@ -650,6 +691,8 @@ def main():
                               if ref else None,
                               "roofline": hbm_roofline(h, "fp32", "step", "hybrid"), "kernel_ms": h["timing"]["ms"]}
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(args.cpu_steps)
+    if not args.no_cpu_baseline:
+        out["error_vs_oracle"] = precision_vs_oracle()
     if not args.no_c1:
         out["c1_full"] = run_c1_full()
     if not args.no_large:
