@@ -66,13 +66,18 @@ class Probe(C.Structure):
 
 
 def lib():
-    """Load (building first if absent) the oracle shared library."""
+    """Load (building first if absent) the oracle shared library.  The
+    environment variable MC_ORACLE_LIB names another build of the oracle to
+    load instead (the mutation tests load copies with a planted mistake)."""
     global _LIB
     if _LIB is not None:
         return _LIB
-    if not os.path.exists(_build.LIB):
-        _build.build()
-    L = C.CDLL(_build.LIB)
+    path = os.environ.get("MC_ORACLE_LIB")
+    if not path:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+    L = C.CDLL(path)
     sig = {
         "orc_philox4x32_10": (None, [C.POINTER(U32), C.POINTER(U32), C.POINTER(U32)]),
         "orc_bake": (None, [PD, I32, I32, F64, F64, PD, PD]),

@@ -52,6 +52,13 @@ def test_acceleration_term():
     # a moving pack: a tenth of its speed per step (CFL looser here)
     v = 2.0
     assert _first_dt(f, op, _snap([2e-3], [v])) == pytest.approx(0.1 * v / a, rel=1e-12)
+    # in a still gas at 300 K (collisions off) the speed scale adds the ion's
+    # thermal speed sqrt(kB T / m): a pack at rest takes a tenth of it
+    tg = 300.0
+    g = synth.uniform_fields(16, 256, h, ez=ez, p=1e3, t_gas=tg)
+    vth = math.sqrt(KB * tg / (m * DA))
+    assert _first_dt(g, op, _snap([2e-3], [0.0])) == pytest.approx(0.1 * vth / a, rel=1e-12)
+    assert _first_dt(g, op, _snap([2e-3], [v])) == pytest.approx(0.1 * (v + vth) / a, rel=1e-12)
 
 
 def test_collision_term_limits_the_collision_probability():

@@ -77,8 +77,9 @@ def _box(p, tg, ez=0.0, nz=256):
 
 def test_drawn_normals_follow_the_normal_law_and_freeze_internal_state():
     """With gamma dt >> 1 one step leaves v = sqrt(kB T/m) xi: the 3 n
-    components must be standard normal (KS test), independent across axes;
-    internal energy and hazard stay exactly as they were."""
+    components must be standard normal (KS test), independent across axes
+    (uncorrelated, and their squares' products of mean 1); internal energy
+    and hazard stay exactly as they were."""
     tg = 350.0
     f = _box(1e5, tg)
     ion = synth.Ion(500.0, 1, 2e-18, 150, act_kind=1, act_p1=100e3, act_p2=-80.0)
@@ -96,6 +97,12 @@ def test_drawn_normals_follow_the_normal_law_and_freeze_internal_state():
         assert stats.kstest(row, "norm").pvalue > 1e-3
     c = np.corrcoef(xi)
     assert np.abs(c[np.triu_indices(3, 1)]).max() < 0.03
+    # independence beyond correlation: for independent standard normals
+    # E[xi_a^2 xi_b^2] = 1 (variance 8); normals that share a Box-Muller
+    # radius or angle across axes are uncorrelated but fail this
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        m22 = float(np.mean(xi[a] ** 2 * xi[b] ** 2))
+        assert abs(m22 - 1.0) < 6.0 * math.sqrt(8.0 / n), (a, b, m22)
 
 
 def test_equipartition_and_rest_mean():
