@@ -187,9 +187,11 @@ __device__ __forceinline__ Q4<float> load4(const float4 *t, int64_t k, const flo
     const float4 v = t[k];
     return Q4<float>{v.x, v.y, v.z, v.w};
 }
-__device__ __forceinline__ Q4<float> load4(const bf16x4 *t, int64_t k, const float *sc) {
+// BF16 records are read unscaled; gather4 applies the channel scales once,
+// after the interpolation (a scale is linear in the record values)
+__device__ __forceinline__ Q4<float> load4(const bf16x4 *t, int64_t k, const float *) {
     const bf16x4 v = t[k];
-    return Q4<float>{bf16_to_f(v.a) * sc[0], bf16_to_f(v.b) * sc[1], bf16_to_f(v.c) * sc[2], bf16_to_f(v.d) * sc[3]};
+    return Q4<float>{bf16_to_f(v.a), bf16_to_f(v.b), bf16_to_f(v.c), bf16_to_f(v.d)};
 }
 
 // Cell location with clamping (constant extension outside the grid).
@@ -240,7 +242,14 @@ __device__ __forceinline__ Q4<T> interp(const Nodes4<T> &n, const Cell<T> &c) {
 
 template <class T, class Tab>
 __device__ __forceinline__ Q4<T> gather4(const Tab *tab, const float *sc, const Cell<T> &c, int32_t nr) {
-    return interp(load_nodes<T>(tab, sc, c.i, c.j, nr), c);
+    Q4<T> q = interp(load_nodes<T>(tab, sc, c.i, c.j, nr), c);
+    if constexpr (sizeof(Tab) == sizeof(bf16x4)) {
+        q.a *= sc[0];
+        q.b *= sc[1];
+        q.c *= sc[2];
+        q.d *= sc[3];
+    }
+    return q;
 }
 
 // Einstein model inverse: T = theta / ln(1 + s kB theta / U).

@@ -534,12 +534,21 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         // (the FP64 form performs exactly the IEEE operations of its reference;
         // the two-float form classifies its full-precision position in FP64)
         const double X1 = (double)x1 + (double)xl, Y1 = (double)y1 + (double)yl, Z1 = (double)z1 + (double)zl;
+        double r1;
+        {
+#pragma clang fp contract(off)
+        r1 = sqrt(X1 * X1 + Y1 * Y1);
+        }
+        // the gas at the new position, gathered before the hit test so that
+        // the two reads overlap (a pack that turns out terminal discards it;
+        // the gather's cell is clamped, so any position reads in bounds)
+        GasAt<T> g{};
+        if (a.collisions_on) g = gas_at(a, sp, (T)r1, x1, y1, z1);
         int32_t cls = ST_ACTIVE, in = -1, jn = -1;
-        double tcross = 0.0, rcross = 0.0, r1;
+        double tcross = 0.0, rcross = 0.0;
         {
 #pragma clang fp contract(off)
         const double X0 = (double)x0 + (double)xl0, Y0 = (double)y0 + (double)yl0, Zo = (double)z0 + (double)zl0;
-        r1 = sqrt(X1 * X1 + Y1 * Y1);
         const bool finite = isfinite(X1) && isfinite(Y1) && isfinite(Z1) && isfinite((double)vx) &&
                             isfinite((double)vy) && isfinite((double)vz);
         if (!finite) {
@@ -589,8 +598,6 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         bool lang = false;
         if (cls == ST_ACTIVE && a.collisions_on) {
             // ---- collisions with the gas at the new position ----
-            const T rr = (T)r1;
-            const GasAt<T> g = gas_at(a, sp, rr, x1, y1, z1);
             if (g.gas) {
                 const T ag = P::sqrt_(P::div((T)kB * g.tg, (T)a.mg));
                 const T abar = ag * (T)1.5957691216057308;  // sqrt(8/pi)

@@ -181,14 +181,22 @@ static void dfree_all(mc_ctx *ctx) {
     ctx->device_bytes = 0;
 }
 
-static hipEvent_t ev_get(mc_ctx *ctx) {
-    if (!ctx->ev_pool.empty()) {
-        hipEvent_t e = ctx->ev_pool.back();
-        ctx->ev_pool.pop_back();
-        return e;
+// Timing events come from a pool that is refilled in batches (creating an
+// event inside a stretch of steps would stall the host between launches);
+// read_timing and reset_timing return the used ones to it.
+constexpr int kEventBatch = 1024;
+static void ev_fill(mc_ctx *ctx, int n) {
+    for (int k = 0; k < n; ++k) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) break;
+        ctx->ev_pool.push_back(e);
     }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
+}
+static hipEvent_t ev_get(mc_ctx *ctx) {
+    if (ctx->ev_pool.empty()) ev_fill(ctx, kEventBatch);
+    if (ctx->ev_pool.empty()) return nullptr;
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
     return e;
 }
 
@@ -199,12 +207,13 @@ struct Timer {
     Timer(mc_ctx *c, int k) : ctx(c), kind(k) {
         if (ctx->opt.timing) {
             a = ev_get(ctx);
-            (void)hipEventRecord(a, ctx->stream);
+            if (a) (void)hipEventRecord(a, ctx->stream);
         }
     }
     ~Timer() {
         if (a) {
             hipEvent_t b = ev_get(ctx);
+            if (!b) return;
             (void)hipEventRecord(b, ctx->stream);
             ctx->ev_used.push_back(EvPair{a, b, kind});
         }
@@ -1634,6 +1643,9 @@ int32_t mc_reset_timing(mc_ctx *ctx) {
         ctx->t_ms[k] = 0;
         ctx->t_launch[k] = 0;
     }
+    // events for the stretch that follows (a timed window of steps)
+    if (ctx->opt.timing && ctx->ev_pool.size() < 4 * (size_t)kEventBatch)
+        ev_fill(ctx, 4 * kEventBatch - (int)ctx->ev_pool.size());
     return MC_OK;
 }
 
