@@ -9,7 +9,10 @@
 //                    chirp z-transform: power-of-two FFTs held in LDS
 //   k_dst_rows, k_idst_rows  the same transforms as direct sums (used when
 //                    the FFT length does not fit in a workgroup's LDS)
-//   k_thomas_coef, k_thomas  per-mode tridiagonal solve in r, FP64 always
+//   k_pcr            per-mode tridiagonal solve in r by parallel cyclic
+//                    reduction, one wavefront per mode, FP64 always
+//   k_thomas_coef, k_thomas  the same solve by Thomas sweeps (one thread per
+//                    mode), for grids taller than k_pcr takes
 //   k_mask_*         the metal-mask Dirichlet condition by a capacitance-
 //                    matrix correction (induced charges on the mask nodes)
 //
@@ -169,6 +172,86 @@ __global__ __launch_bounds__(256) void k_thomas(D *bh, const double *cp, const d
         const int64_t o = (int64_t)i * m + k;
         x = (double)bh[o] - cp[o] * x;
         bh[o] = (D)x;
+    }
+}
+
+// The same systems by parallel cyclic reduction: one wavefront per mode k,
+// its nu = nr - 1 rows padded with identity rows to 64 R (R rows per lane,
+// held in LDS), W wavefronts (modes) per block.  Step h = 1, 2, 4, ...
+// eliminates every row's couplings to the rows h away:
+//   alpha = -a_i / b_{i-h},  gamma = -c_i / b_{i+h},
+//   a_i <- alpha a_{i-h},  c_i <- gamma c_{i+h},
+//   b_i <- b_i + alpha c_{i-h} + gamma a_{i+h},  d_i <- d_i + alpha d_{i-h} + gamma d_{i+h},
+// rows outside [0, 64 R) taken as identity rows; after log2(64 R) steps
+// x_i = d_i / b_i.  FP64 throughout; each step reads one LDS copy of the
+// rows and writes the other.  The rows are those of k_thomas_coef
+// (lower lo_i, upper up_i, diagonal -(lo_i + up_i) + lambda_k; the axis row
+// -4/dr^2 + lambda_k, 4/dr^2; x = 0 beyond the last row): strictly
+// diagonally dominant since lambda_k < 0, where cyclic reduction is stable.
+// 1022 modes of 255 rows are 1022 wavefronts across the chip instead of
+// 1022 threads stepping through 255 dependent rows.
+template <class D, int R, int W>
+__global__ __launch_bounds__(64 * W) void k_pcr(D *bh, int32_t nr, int32_t nz, double dr, double dz) {
+    constexpr int N = 64 * R;
+    // two copies of (a, b, c, d): each step reads one and writes the other
+    __shared__ double s_abcd[2][4][W][N];
+    const int32_t m = nz - 2, nu = nr - 1;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int32_t k = blockIdx.x * W + w + 1;  // mode 1..m (uniform per wavefront)
+    const bool live = k <= m;
+    double lam = 0.0;
+    if (live) {
+        const double sk = sin(kPi * (double)k / (2.0 * (double)(nz - 1)));
+        lam = -(4.0 / (dz * dz)) * sk * sk;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int32_t i = lane + 64 * q;
+        double a = 0.0, b = 1.0, c = 0.0, d = 0.0;
+        if (live && i < nu) {
+            if (i == 0) {
+                b = -4.0 / (dr * dr) + lam;
+                c = 4.0 / (dr * dr);
+            } else {
+                const double ri = (double)i * dr;
+                a = (ri - 0.5 * dr) / (ri * dr * dr);
+                c = (ri + 0.5 * dr) / (ri * dr * dr);
+                b = -(a + c) + lam;
+            }
+            if (i == nu - 1) c = 0.0;  // Phi = 0 at r = R
+            d = (double)bh[(int64_t)i * m + (k - 1)];
+        }
+        s_abcd[0][0][w][i] = a;
+        s_abcd[0][1][w][i] = b;
+        s_abcd[0][2][w][i] = c;
+        s_abcd[0][3][w][i] = d;
+    }
+    __syncthreads();
+    int src = 0;
+    for (int h = 1; h < N; h <<= 1) {
+        const double *A = s_abcd[src][0][w], *B = s_abcd[src][1][w], *C = s_abcd[src][2][w], *Dv = s_abcd[src][3][w];
+        double *A2 = s_abcd[1 - src][0][w], *B2 = s_abcd[1 - src][1][w], *C2 = s_abcd[1 - src][2][w],
+               *D2 = s_abcd[1 - src][3][w];
+#pragma unroll 4
+        for (int q = 0; q < R; ++q) {
+            const int32_t i = lane + 64 * q, l = i - h, u = i + h;
+            const double al = l >= 0 ? A[l] : 0.0, bl = l >= 0 ? B[l] : 1.0, cl = l >= 0 ? C[l] : 0.0,
+                         dl = l >= 0 ? Dv[l] : 0.0;
+            const double au = u < N ? A[u] : 0.0, bu = u < N ? B[u] : 1.0, cu = u < N ? C[u] : 0.0,
+                         du = u < N ? Dv[u] : 0.0;
+            const double alpha = -A[i] / bl, gamma = -C[i] / bu;
+            A2[i] = alpha * al;
+            C2[i] = gamma * cu;
+            B2[i] = B[i] + alpha * cl + gamma * au;
+            D2[i] = Dv[i] + alpha * dl + gamma * du;
+        }
+        __syncthreads();
+        src = 1 - src;
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int32_t i = lane + 64 * q;
+        if (live && i < nu) bh[(int64_t)i * m + (k - 1)] = (D)(s_abcd[src][3][w][i] / s_abcd[src][1][w][i]);
     }
 }
 
@@ -410,7 +493,15 @@ inline hipError_t poisson_solve(const PoissonGrid &g, const unsigned long long *
         k_dst_rows<D><<<nu, 256, m * sizeof(D), st>>>(q, rhs, g.sine, bh, g.nr, g.nz, g.dr, g.dz);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_thomas<D><<<(m + 255) / 256, 256, 0, st>>>(bh, g.tcp, g.tinv, g.nr, g.nz, g.dr);
+    // tridiagonal solves: cyclic reduction up to 1024 rows, Thomas sweeps above
+    if (nu <= 256)
+        k_pcr<D, 4, 4><<<(m + 3) / 4, 256, 0, st>>>(bh, g.nr, g.nz, g.dr, g.dz);
+    else if (nu <= 512)
+        k_pcr<D, 8, 2><<<(m + 1) / 2, 128, 0, st>>>(bh, g.nr, g.nz, g.dr, g.dz);
+    else if (nu <= 1024)
+        k_pcr<D, 16, 1><<<m, 64, 0, st>>>(bh, g.nr, g.nz, g.dr, g.dz);
+    else
+        k_thomas<D><<<(m + 255) / 256, 256, 0, st>>>(bh, g.tcp, g.tinv, g.nr, g.nz, g.dr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (B.L > 0)
         k_dst_bluestein<D, false><<<nu, 1024, B.lds, st>>>(nullptr, nullptr, bh, phi, accumulate ? 1 : 0, chirp, fb,

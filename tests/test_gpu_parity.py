@@ -211,7 +211,11 @@ def test_pic_update_bit_exact_deposit_and_poisson():
 # about log2(L) ~ 14 butterfly levels in each of four FFTs), Phi within 5e-6
 # of max|Phi| and E within 1e-4 of max|E| (differences over a node amplify
 # the relative error by the ratio of the potential's length scale to dz).
-@pytest.mark.parametrize("precision,nr,nz", [(1, 0, 0), (0, 16, 4096), (1, 16, 8192), (0, 12, 8192)])
+# The radial systems take cyclic reduction with 4, 8 or 16 rows per lane
+# (nr - 1 <= 256, 512, 1024: the 256 x 1024 grid, nr = 300, nr = 700) and
+# Thomas sweeps above 1024 rows (nr = 1100).
+@pytest.mark.parametrize("precision,nr,nz", [(1, 0, 0), (0, 16, 4096), (1, 16, 8192), (0, 12, 8192), (0, 300, 64),
+                                             (1, 700, 64), (0, 1100, 64)])
 def test_poisson_transforms_match_oracle(precision, nr, nz):
     n = 100_000
     if nr == 0:
