@@ -275,11 +275,25 @@ struct Species {
     int32_t act_kind, n_atoms;
 };
 
-// Wavefront sum of a 64-bit counter (all lanes participate).
-__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// 32-bit DPP move of v (row_mask selects the rows that take the moved value;
+// lanes whose source is outside the row, and rows not selected, read 0).
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kCtrl, kRowMask, 0xf, true);
+}
+
+// Sum of v over the 64 lanes of a wavefront whose lanes are all active, in
+// every lane: an inclusive scan within each row of 16 lanes (shifts 1, 2, 4,
+// 8), the row totals carried across rows (broadcasts of lanes 15 and 31),
+// then lane 63 read into a scalar.  Modulo 2^32.
+__device__ __forceinline__ uint32_t wave_total_u32(uint32_t v) {
+    v += dpp_u32<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_u32<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_u32<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_u32<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_u32<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_u32<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 }  // namespace mc

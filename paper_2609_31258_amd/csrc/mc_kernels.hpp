@@ -274,11 +274,13 @@ __device__ __forceinline__ void record_exit(const StepArgs<P, Tab> &a, int64_t s
     }
 }
 
+// Per thread and step: act, cap and lang are 0 or 1; a pack draws at most
+// 8000064 candidates (the loop's cap), so a wavefront's sums stay below 2^29.
 struct StepCount {
-    uint64_t cand, acc, cap, clamp, act, lang, exch;
+    uint32_t cand, acc, cap, clamp, act, lang, exch;
 };
 
-// Per pack and step: < 2^32 each.
+// Per pack and step.
 struct PackCount {
     uint32_t cand, acc, cap, clamp, lang, exch;
 };
@@ -647,14 +649,22 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
 
 // Block-aggregated counters: wavefront sums, then LDS, then one atomic per
 // counter and block into the block's replica (every thread of the block
-// calls this; all of a block's threads belong to one query).
+// calls this; all of a block's threads belong to one query).  The 0/1
+// counters are counted from the wavefront's ballot (scalar unit); the others
+// are summed across lanes by DPP, skipped where the whole wavefront holds
+// zero (a Langevin step draws no candidates).
 __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount &n) {
     __shared__ unsigned long long red[HOT_N];
     if (threadIdx.x < HOT_N) red[threadIdx.x] = 0ull;
     __syncthreads();
-    const uint64_t v[HOT_N] = {wave_sum_u64(n.act), wave_sum_u64(n.cand), wave_sum_u64(n.acc),
-                               wave_sum_u64(n.cap),   wave_sum_u64(n.clamp), wave_sum_u64(n.lang),
-                               wave_sum_u64(n.exch)};
+    const auto sum = [](uint32_t x) -> uint64_t { return __ballot(x != 0u) ? wave_total_u32(x) : 0u; };
+    const uint64_t v[HOT_N] = {(uint64_t)__popcll(__ballot(n.act != 0u)),
+                               sum(n.cand),
+                               sum(n.acc),
+                               (uint64_t)__popcll(__ballot(n.cap != 0u)),
+                               sum(n.clamp),
+                               (uint64_t)__popcll(__ballot(n.lang != 0u)),
+                               sum(n.exch)};
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < HOT_N; ++k)
