@@ -298,46 +298,119 @@ __device__ __forceinline__ Cx<D> cmul(Cx<D> a, Cx<D> b) {
     return Cx<D>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 
-// In-place radix-2 FFT on LDS.  Forward (DIF, twiddles exp(-2 pi i k / L)):
-// natural order in, bit-reversed out.  Inverse (DIT, conjugate twiddles,
-// scaled by 1/L): bit-reversed in, natural out.
-template <class D, bool kInverse>
-__device__ void fft_lds(Cx<D> *a, int32_t L, const Cx<D> *tw) {
-    const int32_t half_total = L >> 1;
-    if (!kInverse) {
-        for (int32_t len = L; len >= 2; len >>= 1) {
-            const int32_t half = len >> 1, stride = L / len;
-#pragma unroll 4
-            for (int32_t b = threadIdx.x; b < half_total; b += blockDim.x) {
-                // butterfly b of this stage: k = b mod half, i0 = (b div half) len + k = 2b - k
-                const int32_t k = b & (half - 1), i0 = 2 * b - k, i1 = i0 + half;
-                const Cx<D> u = a[i0], v = a[i1];
-                a[i0] = Cx<D>{u.re + v.re, u.im + v.im};
-                a[i1] = cmul(Cx<D>{u.re - v.re, u.im - v.im}, tw[k * stride]);
-            }
-            __syncthreads();
+// LDS slot of complex value i: one spare slot after every 8 values, so that
+// the passes which give a thread 8 consecutive values (stride 8 across the
+// wavefront) spread their accesses over the banks.
+__device__ __forceinline__ int32_t cslot(int32_t i) { return i + (i >> 3); }
+
+// The FFTs are in-place radix-2 transforms (forward: decimation in frequency,
+// twiddles exp(-2 pi i k / L), natural order in, bit-reversed out; inverse:
+// decimation in time with conjugate twiddles, bit-reversed in, natural out,
+// unscaled) whose consecutive stages are taken G at a time: a thread loads
+// the 2^G values that those stages combine, applies the G stages in
+// registers, and stores them back, so a transform of L = 2^S values takes
+// about S/3 passes (and barriers) instead of S.  The arithmetic of each
+// butterfly is that of the radix-2 stage it belongs to.
+//
+// Forward stages of lengths len, len/2, ..., len/2^(G-1): a group holds
+// the values B + o + j sub (j < 2^G, sub = len / 2^G, o < sub) of one block
+// of len values.
+template <class D, int G>
+__device__ __forceinline__ void dif_stages(Cx<D> (&v)[1 << G], int32_t o, int32_t sub, int32_t len, int32_t L,
+                                           const Cx<D> *tw) {
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const int h = 1 << (G - 1 - t);  // partner distance within the group
+        const int32_t stride = L / (len >> t);
+#pragma unroll
+        for (int j = 0; j < (1 << G); ++j) {
+            if (j & h) continue;
+            const Cx<D> u = v[j], w = v[j + h];
+            v[j] = Cx<D>{u.re + w.re, u.im + w.im};
+            v[j + h] = cmul(Cx<D>{u.re - w.re, u.im - w.im}, tw[(o + (j & (h - 1)) * sub) * stride]);
         }
-    } else {
-        for (int32_t len = 2; len <= L; len <<= 1) {
-            const int32_t half = len >> 1, stride = L / len;
-#pragma unroll 4
-            for (int32_t b = threadIdx.x; b < half_total; b += blockDim.x) {
-                const int32_t k = b & (half - 1), i0 = 2 * b - k, i1 = i0 + half;
-                const Cx<D> w = tw[k * stride];
-                const Cx<D> t = cmul(a[i1], Cx<D>{w.re, -w.im});
-                const Cx<D> u = a[i0];
-                a[i0] = Cx<D>{u.re + t.re, u.im + t.im};
-                a[i1] = Cx<D>{u.re - t.re, u.im - t.im};
-            }
-            __syncthreads();
-        }
-        const D s = (D)1 / (D)L;
-        for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
-            a[n].re *= s;
-            a[n].im *= s;
-        }
-        __syncthreads();
     }
+}
+
+// Inverse stages of lengths ls, 2 ls, ..., 2^(G-1) ls: a group holds the
+// values B + o + j hs (j < 2^G, hs = ls / 2, o < hs) of one block of
+// 2^(G-1) ls values.
+template <class D, int G>
+__device__ __forceinline__ void dit_stages(Cx<D> (&v)[1 << G], int32_t o, int32_t hs, int32_t ls, int32_t L,
+                                           const Cx<D> *tw) {
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const int h = 1 << t;
+        const int32_t stride = L / (ls << t);
+#pragma unroll
+        for (int j = 0; j < (1 << G); ++j) {
+            if (j & h) continue;
+            const Cx<D> w = tw[(o + (j & (h - 1)) * hs) * stride];
+            const Cx<D> tt = cmul(v[j + h], Cx<D>{w.re, -w.im});
+            const Cx<D> u = v[j];
+            v[j] = Cx<D>{u.re + tt.re, u.im + tt.im};
+            v[j + h] = Cx<D>{u.re - tt.re, u.im - tt.im};
+        }
+    }
+}
+
+// One pass of G forward stages starting at block length len, every group
+// of the transform, then a barrier.
+template <class D, int G>
+__device__ __forceinline__ void dif_pass(Cx<D> *a, int32_t len, int32_t L, const Cx<D> *tw) {
+    const int32_t sub = len >> G;
+    for (int32_t gi = threadIdx.x; gi < (L >> G); gi += blockDim.x) {
+        const int32_t o = gi & (sub - 1), base = (gi - o) << G | o;  // (gi / sub) len + o
+        Cx<D> v[1 << G];
+#pragma unroll
+        for (int j = 0; j < (1 << G); ++j) v[j] = a[cslot(base + j * sub)];
+        dif_stages<D, G>(v, o, sub, len, L, tw);
+#pragma unroll
+        for (int j = 0; j < (1 << G); ++j) a[cslot(base + j * sub)] = v[j];
+    }
+    __syncthreads();
+}
+
+template <class D, int G>
+__device__ __forceinline__ void dit_pass(Cx<D> *a, int32_t ls, int32_t L, const Cx<D> *tw) {
+    const int32_t hs = ls >> 1;
+    for (int32_t gi = threadIdx.x; gi < (L >> G); gi += blockDim.x) {
+        const int32_t o = gi & (hs - 1), base = (gi - o) << G | o;  // (gi / hs) 2^(G-1) ls + o
+        Cx<D> v[1 << G];
+#pragma unroll
+        for (int j = 0; j < (1 << G); ++j) v[j] = a[cslot(base + j * hs)];
+        dit_stages<D, G>(v, o, hs, ls, L, tw);
+#pragma unroll
+        for (int j = 0; j < (1 << G); ++j) a[cslot(base + j * hs)] = v[j];
+    }
+    __syncthreads();
+}
+
+// Forward stages of lengths L down to 16 (all but the last three), values
+// in LDS slots cslot(i); L = 2^S with S >= 6.  The first pass takes the
+// S mod 3 stages that do not make a full group of three.
+template <class D>
+__device__ __forceinline__ void fft_forward_head(Cx<D> *a, int32_t L, int32_t S, const Cx<D> *tw) {
+    int32_t len = L;
+    const int32_t r = S % 3;
+    if (r == 1) {
+        dif_pass<D, 1>(a, len, L, tw);
+        len >>= 1;
+    } else if (r == 2) {
+        dif_pass<D, 2>(a, len, L, tw);
+        len >>= 2;
+    }
+    for (; len > 8; len >>= 3) dif_pass<D, 3>(a, len, L, tw);
+}
+
+// Inverse stages of lengths 16 up to L (all but the first three).
+template <class D>
+__device__ __forceinline__ void fft_inverse_tail(Cx<D> *a, int32_t L, int32_t S, const Cx<D> *tw) {
+    int32_t ls = 16;
+    for (int32_t p = 0; p < (S - 3) / 3; ++p, ls <<= 3) dit_pass<D, 3>(a, ls, L, tw);
+    const int32_t r = S % 3;
+    if (r == 1) dit_pass<D, 1>(a, ls, L, tw);
+    else if (r == 2) dit_pass<D, 2>(a, ls, L, tw);
 }
 
 // Tables for one grid: chirp[n] = c_{n+1} (n < m), tw[k] = exp(-2 pi i k/L)
@@ -375,26 +448,31 @@ __global__ __launch_bounds__(1024) void k_bluestein_filter(Cx<D> *fb, const Cx<D
             sincospi((double)q / (double)(2 * (m + 1)), &sv, &cv);
             v = Cx<D>{(D)cv, (D)(-sv)};
         }
-        a[n] = v;
+        a[cslot(n)] = v;
     }
     __syncthreads();
-    fft_lds<D, false>(a, L, tw);
-    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) fb[n] = a[n];
+    const int32_t S = __builtin_ctz((uint32_t)L);
+    fft_forward_head<D>(a, L, S, tw);
+    dif_pass<D, 3>(a, 8, L, tw);
+    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) fb[n] = a[cslot(n)];
 }
 
-// One radial row per block.  kForward: input -rho/eps0 of column i from the
-// int64 charge grid, output bh[i][:] scaled by 2/N.  Inverse: input bh[i][:],
-// output Phi[1..m][i].
+// One radial row per block (kDstThreads threads).  kForward: input
+// -rho/eps0 of column i from the int64 charge grid, output bh[i][:] scaled
+// by 2/N.  Inverse: input bh[i][:], output Phi[1..m][i].
+constexpr int kDstThreads = 256;
+
 template <class D, bool kForward>
-__global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long *q, const double *rhs, D *bh,
-                                                        double *phi, int32_t accumulate,
-                                                        const Cx<D> *chirp, const Cx<D> *fb, const Cx<D> *tw,
-                                                        int32_t nr, int32_t nz, int32_t L, double dr, double dz) {
+__global__ __launch_bounds__(kDstThreads) void k_dst_bluestein(const unsigned long long *q, const double *rhs, D *bh,
+                                                               double *phi, int32_t accumulate, const Cx<D> *chirp,
+                                                               const Cx<D> *fb, const Cx<D> *tw, int32_t nr,
+                                                               int32_t nz, int32_t L, double dr, double dz) {
     extern __shared__ unsigned char smem_raw[];
     Cx<D> *a = reinterpret_cast<Cx<D> *>(smem_raw);
-    const int32_t i = blockIdx.x, m = nz - 2;
+    const int32_t i = blockIdx.x, m = nz - 2, S = __builtin_ctz((uint32_t)L);
     const double vol = control_volume(i, dr, dz);
     const double scale = -kQe * 0x1p-32 / (vol * kEps0);
+#pragma unroll 4
     for (int32_t n = threadIdx.x; n < L; n += blockDim.x) {
         Cx<D> v{(D)0, (D)0};
         if (n < m) {
@@ -403,16 +481,32 @@ __global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long
             const Cx<D> c = chirp[n];
             v = Cx<D>{x * c.re, x * c.im};
         }
-        a[n] = v;
+        a[cslot(n)] = v;
     }
     __syncthreads();
-    fft_lds<D, false>(a, L, tw);
-    for (int32_t n = threadIdx.x; n < L; n += blockDim.x) a[n] = cmul(a[n], fb[n]);
+    fft_forward_head<D>(a, L, S, tw);
+    // the last three forward stages, the product with the filter spectrum
+    // (both in bit-reversed order) and the first three inverse stages all act
+    // on the same 8 consecutive values: one pass
+    for (int32_t gi = threadIdx.x; gi < (L >> 3); gi += blockDim.x) {
+        const int32_t base = gi << 3;
+        Cx<D> v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = a[cslot(base + j)];
+        dif_stages<D, 3>(v, 0, 1, 8, L, tw);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = cmul(v[j], fb[base + j]);
+        dit_stages<D, 3>(v, 0, 1, 2, L, tw);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[cslot(base + j)] = v[j];
+    }
     __syncthreads();
-    fft_lds<D, true>(a, L, tw);
-    const D norm = kForward ? (D)(2.0 / (double)(nz - 1)) : (D)1;
+    fft_inverse_tail<D>(a, L, S, tw);
+    // the inverse transform's 1/L folded into the output scale (a power of two)
+    const D norm = (D)((kForward ? 2.0 / (double)(nz - 1) : 1.0) / (double)L);
+#pragma unroll 4
     for (int32_t k = threadIdx.x; k < m; k += blockDim.x) {
-        const Cx<D> c = chirp[k], y = a[k];
+        const Cx<D> c = chirp[k], y = a[cslot(k)];
         const D X = (c.re * y.im + c.im * y.re) * norm;  // Im(c y)
         if (kForward) bh[(int64_t)i * m + k] = X;
         else {
@@ -441,11 +535,17 @@ inline size_t lds_per_block() {
     return std::min(kLdsLimit, (size_t)v);
 }
 
+// FFT length: the smallest power of two >= 2m - 1, at least 16 (the passes
+// take the last three forward and first three inverse stages together).
 inline int32_t bluestein_length(int32_t m) {
-    int32_t L = 1;
+    int32_t L = 16;
     while (L < 2 * m - 1) L <<= 1;
     return L;
 }
+
+// LDS bytes of one row's transform: L complex values of cx bytes and one
+// spare slot per 8 (cslot).
+inline size_t bluestein_lds(int32_t L, size_t cx) { return ((size_t)L + (size_t)(L >> 3)) * cx; }
 
 template <class D>
 inline hipError_t bluestein_prepare(Bluestein &B, int32_t m, hipStream_t st) {
@@ -487,7 +587,7 @@ inline hipError_t poisson_solve(const PoissonGrid &g, const unsigned long long *
     const Bluestein &B = *g.blu;
     const Cx<D> *chirp = (const Cx<D> *)B.chirp, *fb = (const Cx<D> *)B.fb, *tw = (const Cx<D> *)B.tw;
     if (B.L > 0)
-        k_dst_bluestein<D, true><<<nu, 1024, B.lds, st>>>(q, rhs, bh, nullptr, 0, chirp, fb, tw, g.nr, g.nz, B.L,
+        k_dst_bluestein<D, true><<<nu, kDstThreads, B.lds, st>>>(q, rhs, bh, nullptr, 0, chirp, fb, tw, g.nr, g.nz, B.L,
                                                            g.dr, g.dz);
     else
         k_dst_rows<D><<<nu, 256, m * sizeof(D), st>>>(q, rhs, g.sine, bh, g.nr, g.nz, g.dr, g.dz);
@@ -504,7 +604,7 @@ inline hipError_t poisson_solve(const PoissonGrid &g, const unsigned long long *
         k_thomas<D><<<(m + 255) / 256, 256, 0, st>>>(bh, g.tcp, g.tinv, g.nr, g.nz, g.dr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (B.L > 0)
-        k_dst_bluestein<D, false><<<nu, 1024, B.lds, st>>>(nullptr, nullptr, bh, phi, accumulate ? 1 : 0, chirp, fb,
+        k_dst_bluestein<D, false><<<nu, kDstThreads, B.lds, st>>>(nullptr, nullptr, bh, phi, accumulate ? 1 : 0, chirp, fb,
                                                             tw, g.nr, g.nz, B.L, g.dr, g.dz);
     else
         k_idst_rows<D><<<nu, 256, m * sizeof(D), st>>>(bh, g.sine, phi, g.nr, g.nz, accumulate ? 1 : 0);

@@ -496,9 +496,9 @@ static int32_t mask_setup(mc_ctx *ctx) {
         rc = dalloc_t(ctx, &bh64, (size_t)nu * m);
         const int32_t L = bluestein_length(m);
         const size_t cx = 2 * sizeof(double);
-        if (!rc && (size_t)L * cx <= lds_per_block()) {
+        if (!rc && bluestein_lds(L, cx) <= lds_per_block()) {
             b64.L = L;
-            b64.lds = (size_t)L * cx;
+            b64.lds = bluestein_lds(L, cx);
             rc = dalloc(ctx, &b64.chirp, (size_t)m * cx);
             if (!rc) rc = dalloc(ctx, &b64.tw, (size_t)std::max(L / 2, 1) * cx);
             if (!rc) rc = dalloc(ctx, &b64.fb, (size_t)L * cx);
@@ -969,9 +969,9 @@ int32_t mc_load_fields(mc_ctx *ctx, const mc_grid *g, const mc_field_tables *t) 
         Bluestein &B = ctx->blu;
         const size_t cx = ctx->fp32() ? 2 * sizeof(float) : 2 * sizeof(double);
         const int32_t L = bluestein_length(m);
-        if ((size_t)L * cx <= lds_per_block()) {
+        if (bluestein_lds(L, cx) <= lds_per_block()) {
             B.L = L;
-            B.lds = (size_t)L * cx;
+            B.lds = bluestein_lds(L, cx);
             int32_t rc2 = dalloc(ctx, &B.chirp, (size_t)m * cx);
             if (!rc2) rc2 = dalloc(ctx, &B.tw, (size_t)std::max(L / 2, 1) * cx);
             if (!rc2) rc2 = dalloc(ctx, &B.fb, (size_t)L * cx);

@@ -362,9 +362,9 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
                 const int32_t L = bluestein_length(m);
                 const size_t cx = 2 * sizeof(double);
                 if (salloc_t(S, &bh64, (size_t)nu * m)) return MC_ENOMEM;
-                if ((size_t)L * cx <= lds_per_block()) {
+                if (bluestein_lds(L, cx) <= lds_per_block()) {
                     b64.L = L;
-                    b64.lds = (size_t)L * cx;
+                    b64.lds = bluestein_lds(L, cx);
                     if (salloc(S, &b64.chirp, (size_t)m * cx) || salloc(S, &b64.tw, (size_t)std::max(L / 2, 1) * cx) ||
                         salloc(S, &b64.fb, (size_t)L * cx))
                         return MC_ENOMEM;
@@ -888,9 +888,9 @@ int32_t mc_server_create(const mc_server_options *o, const mc_grid *g, const mc_
         Bluestein &B = S->blu;
         const size_t cx = S->fp32() ? 2 * sizeof(float) : 2 * sizeof(double);
         const int32_t L = bluestein_length(m);
-        if ((size_t)L * cx <= lds_per_block()) {
+        if (bluestein_lds(L, cx) <= lds_per_block()) {
             B.L = L;
-            B.lds = (size_t)L * cx;
+            B.lds = bluestein_lds(L, cx);
             if (salloc(S, &B.chirp, (size_t)m * cx) || salloc(S, &B.tw, (size_t)std::max(L / 2, 1) * cx) ||
                 salloc(S, &B.fb, (size_t)L * cx))
                 return bail(MC_ENOMEM);
