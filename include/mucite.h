@@ -40,7 +40,7 @@
 extern "C" {
 #endif
 
-#define MC_ABI_VERSION 5
+#define MC_ABI_VERSION 6
 
 enum {
     MC_OK = 0,
@@ -423,6 +423,12 @@ int32_t mc_read_hit(mc_ctx *ctx, uint8_t *hit);
 /* Per-kernel HIP-event times (mc_options.timing) and their reset. */
 int32_t mc_read_timing(mc_ctx *ctx, mc_timing *out);
 int32_t mc_reset_timing(mc_ctx *ctx);
+/* Per-kernel events on (on != 0) or off for the launches that follow; the
+ * times gathered so far are kept.  The events add a marker to the stream on
+ * both sides of every launch, which lengthens short steps: a caller may time
+ * the kernels over one stretch of steps and the whole step without events
+ * over another.  MC_EINVAL on a null context. */
+int32_t mc_set_timing(mc_ctx *ctx, int32_t on);
 
 /* ------------------------------------------------------------------------- */
 /* Stand-alone CIC deposit on caller-owned device arrays.                     */

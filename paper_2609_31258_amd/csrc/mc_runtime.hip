@@ -1649,4 +1649,13 @@ int32_t mc_reset_timing(mc_ctx *ctx) {
     return MC_OK;
 }
 
+int32_t mc_set_timing(mc_ctx *ctx, int32_t on) {
+    if (!ctx) return MC_EINVAL;
+    HIPCHK(hipSetDevice(ctx->opt.device));
+    ctx->opt.timing = on ? 1 : 0;
+    if (ctx->opt.timing && ctx->ev_pool.size() < 4 * (size_t)kEventBatch)
+        ev_fill(ctx, 4 * kEventBatch - (int)ctx->ev_pool.size());
+    return MC_OK;
+}
+
 }  // extern "C"

@@ -23,7 +23,7 @@ PD, PI64, PI32, PU8 = C.POINTER(F64), C.POINTER(I64), C.POINTER(I32), C.POINTER(
 
 MC_OK, MC_EINVAL, MC_ESTATE, MC_ENOMEM, MC_EBUDGET, MC_EDEVICE, MC_ENUMERIC, MC_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 PREC_FP64, PREC_FP32 = 0, 1
-ABI_VERSION = 5
+ABI_VERSION = 6
 NCLASS = 6
 HIST_KE, HIST_TEFF, HIST_R = 202, 202, 102
 K_EMIT, K_STEP, K_DEPOSIT, K_POISSON, K_FIELD, K_TALLY, K_SORT = range(7)
@@ -176,6 +176,7 @@ _SIGS = {
     "mc_read_hit": (I32, [C.c_void_p, PU8]),
     "mc_read_timing": (I32, [C.c_void_p, C.POINTER(Timing)]),
     "mc_reset_timing": (I32, [C.c_void_p]),
+    "mc_set_timing": (I32, [C.c_void_p, I32]),
     "mc_deposit_cic": (I32, [C.POINTER(CicPacks), C.POINTER(Grid), C.c_void_p, C.c_void_p]),
     "mc_deposit_cic_noalloc": (I32, [C.POINTER(CicPacks), C.POINTER(Grid), C.c_void_p, C.c_void_p]),
     "mc_server_create": (I32, [C.POINTER(ServerOptions), C.POINTER(Grid), C.POINTER(FieldTables),
@@ -457,6 +458,9 @@ class Sim:
 
     def reset_timing(self) -> None:
         self._chk(self.L.mc_reset_timing(self._h), "mc_reset_timing")
+
+    def set_timing(self, on: bool) -> None:
+        self._chk(self.L.mc_set_timing(self._h, 1 if on else 0), "mc_set_timing")
 
 
 def _tally_buffers(nz: int, nr: int, n_exit_bins: int):

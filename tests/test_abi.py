@@ -15,7 +15,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 20
     for n in names:
         assert hasattr(L, n), n
-    assert L.mc_abi_version() == mucite.ABI_VERSION == 5
+    assert L.mc_abi_version() == mucite.ABI_VERSION == 6
 
 
 def test_binding_struct_layouts_match_the_header(tmp_path):
