@@ -11,7 +11,9 @@ update every 10th step).
 The run first advances the workload through its emission ramp (steps
 0..1999, untimed set-up that does not depend on --warmup), so the population
 is the full 1e6 packs; then `warmup` untimed steps; then exactly `steps`
-steps timed with the device synchronised on both sides.  value = active
+steps timed with the device synchronised on both sides, with no per-kernel
+timing events (the kernel times behind the rooflines come from the next
+`steps` steps, timed with them).  value = active
 pack-steps advanced in the timed window / wall seconds, FP64 path; the FP32
 form (FP32 math, BF16 tables, two-float positions) is timed the same way
 and reported beside it, and so is the hybrid form (the FP32 form with the
@@ -22,8 +24,9 @@ launch of the fused step kernel), the deposit's, windows of the masked
 Poisson solve, the snapshots and the adaptive step (`next_rows`), the large
 1024 x 8192 configuration, the plain 128 x 512 configuration over its whole
 horizon with the oracle timed beside it, serving latency under overload and
-at a sustainable load, and the CPU oracle's rate on a bounded sample of the
-same workload on this host's cores.
+at a sustainable load with the oracle's service time on a sample of the
+queries, and the CPU oracle's rate on a bounded sample of the same workload
+on this host's cores.
 """
 from __future__ import annotations
 
@@ -629,6 +632,62 @@ def run_serving(n_queries: int, rate_hz: float, steps: int, precision: int, budg
             "dtype": "f32 (BF16 tables)" if precision == 1 else "f64"}
 
 
+def serving_oracle_sample(n_queries: int, rate_hz: float, steps: int, precision: int, n_sample: int = 8,
+                          budget_pack_steps: float = 2e6):
+    """The oracle's service time on a seeded sample of the serving queries
+    (the first n_sample of the same list): each query runs alone on the GPU
+    (one context, the serving form) over its whole horizon, which gives its
+    GPU service time and its pack-steps; its packs at the end of emission
+    (half the horizon) are handed to the oracle, timed over about
+    budget_pack_steps pack-steps at that occupancy on this host's cores, and
+    the query's oracle service time is its pack-steps over that rate."""
+    import torch
+    from paper_2609_31258_amd import mucite, synth
+    from oracle.binding import OracleSim, num_threads
+    f = synth.ring_fields(256, 1024)
+    qs = synth.serving_queries(n_queries, rate_hz=rate_hz)[:n_sample]
+    rows = []
+    for k, q in enumerate(qs):
+        ion, src, op = serving_query(f, q, steps)
+        sim = mucite.Sim(seed=q["seed"], pack_capacity=src.n_total, precision=precision)
+        sim.setup(f, [ion], [src], op)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps // 2)
+        sim.synchronize()
+        t_half = time.perf_counter() - t0
+        p = sim.read_packs()
+        t0 = time.perf_counter()
+        sim.step(steps - steps // 2)
+        sim.synchronize()
+        gpu_s = t_half + time.perf_counter() - t0
+        ps = int(sim.read_tallies()["pack_steps"])
+        sim.close()
+        act = p["status"] == 0
+        snap = {key: p[key][act] for key in ("x", "y", "z", "vx", "vy", "vz", "e_int", "h", "w", "id", "tag")}
+        n_act = int(act.sum())
+        o = OracleSim(q["seed"])
+        o.setup(f, [ion], [], op)  # the packs as they stand; the source has finished emitting
+        o.write_packs(snap)
+        o_steps = max(1, int(budget_pack_steps // max(n_act, 1)))
+        t0 = time.perf_counter()
+        o.step(o_steps)
+        wall_o = time.perf_counter() - t0
+        o.close()
+        rate_o = n_act * o_steps / wall_o
+        rows.append({"n_packs": q["n_packs"], "mass_da": q["mass_da"], "charge_z": q["charge_z"], "pack_steps": ps,
+                     "gpu_service_s": gpu_s, "oracle_rate": rate_o, "oracle_service_s": ps / rate_o,
+                     "oracle_timed_steps": o_steps, "oracle_timed_packs": n_act})
+        _say(f"serving oracle sample {k + 1}/{n_sample}: {q['n_packs']} packs, GPU {gpu_s:.2f} s, "
+             f"oracle {ps / rate_o:.1f} s (extrapolated from {o_steps} steps)")
+    tot_g = sum(r["gpu_service_s"] for r in rows)
+    tot_o = sum(r["oracle_service_s"] for r in rows)
+    return {"queries": rows, "gpu_service_s_total": tot_g, "oracle_service_s_total": tot_o,
+            "speedup": tot_o / tot_g if tot_g > 0 else None, "cores": num_threads(), "kind": "oracle",
+            "sample": f"the first {n_sample} queries of the serving list, each alone; oracle timed on about "
+                      f"{budget_pack_steps:.0e} pack-steps from its end-of-emission state"}
+
+
 def copy_calibration():
     import torch
     n = 1 << 30
@@ -715,6 +774,9 @@ def main():
                                      args.serving_budget_gib, 64)
         out["serving_sustained"] = run_serving(args.sustained_queries, args.sustained_rate, args.serving_steps, 1,
                                                args.serving_budget_gib, 64, label="serving (sustained)")
+        if not args.no_cpu_baseline:
+            out["serving"]["oracle_sample"] = serving_oracle_sample(args.serving_queries, args.serving_rate,
+                                                                    args.serving_steps, 1)
     print(json.dumps(out), flush=True)
 
 
