@@ -647,16 +647,14 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
     n.exch = pc.exch;
 }
 
-// Block-aggregated counters: wavefront sums, then LDS, then one atomic per
-// counter and block into the block's replica (every thread of the block
-// calls this; all of a block's threads belong to one query).  The 0/1
+// Block-aggregated counters: wavefront sums, then (blocks of several
+// wavefronts) LDS, then one atomic per counter and block into the block's
+// replica (every thread of the block calls this; all of a block's threads
+// belong to one query).  The 0/1
 // counters are counted from the wavefront's ballot (scalar unit); the others
 // are summed across lanes by DPP, skipped where the whole wavefront holds
 // zero (a Langevin step draws no candidates).
 __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount &n) {
-    __shared__ unsigned long long red[HOT_N];
-    if (threadIdx.x < HOT_N) red[threadIdx.x] = 0ull;
-    __syncthreads();
     const auto sum = [](uint32_t x) -> uint64_t { return __ballot(x != 0u) ? wave_total_u32(x) : 0u; };
     const uint64_t v[HOT_N] = {(uint64_t)__popcll(__ballot(n.act != 0u)),
                                sum(n.cand),
@@ -665,14 +663,25 @@ __device__ __forceinline__ void flush_counts(const TallyPtrs &t, const StepCount
                                sum(n.clamp),
                                (uint64_t)__popcll(__ballot(n.lang != 0u)),
                                sum(n.exch)};
+    unsigned long long *rep = t.hot + (int64_t)(blockIdx.x & (kHotRep - 1)) * kHotStride;
+    if (blockDim.x == 64) {  // a block of one wavefront adds its sums straight into its replica
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < HOT_N; ++k)
+                if (v[k]) atomicAdd(&rep[k], (unsigned long long)v[k]);
+        }
+        return;
+    }
+    __shared__ unsigned long long red[HOT_N];
+    if (threadIdx.x < HOT_N) red[threadIdx.x] = 0ull;
+    __syncthreads();
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < HOT_N; ++k)
             if (v[k]) atomicAdd(&red[k], (unsigned long long)v[k]);
     }
     __syncthreads();
-    if (threadIdx.x < HOT_N && red[threadIdx.x])
-        atomicAdd(&t.hot[(int64_t)(blockIdx.x & (kHotRep - 1)) * kHotStride + threadIdx.x], red[threadIdx.x]);
+    if (threadIdx.x < HOT_N && red[threadIdx.x]) atomicAdd(&rep[threadIdx.x], red[threadIdx.x]);
 }
 
 // Waves per SIMD the step kernel is compiled for (its register budget):
