@@ -34,6 +34,9 @@ constexpr int kRing = 8;
 constexpr int64_t kAggMax = 1024;
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlk - 1) / kBlk); }
+// blocks of the co-step's step kernel: one wavefront each, as in a single
+// context (the smallest last, partly filled round of blocks)
+constexpr int kStepBlk = 64;
 
 struct Query {
     uint64_t id = 0;
@@ -570,7 +573,7 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
                                                                                  Q.q.op.dt);
             ps[ns] = bs;
             sd[ns++] = a;
-            bs += (int)blocks_for(Q.n_slots);
+            bs += (int)((Q.n_slots + kStepBlk - 1) / kStepBlk);
         }
         if (Q.q.op.adaptive) Q.t += Q.dt_now;
         Q.step++;
@@ -585,7 +588,7 @@ static int32_t co_step(mc_server *S, std::vector<Query *> &act) {
         SCHK(hipGetLastError());
     }
     if (ns > 0) {
-        k_step_multi<P, Tab><<<bs, kBlk, 0, S->stream>>>(
+        k_step_multi<P, Tab><<<bs, kStepBlk, 0, S->stream>>>(
             (const StepArgs<P, Tab> *)(d + pre + maxres * sizeof(EmitArgs<P, Tab>)), dps, ns);
         SCHK(hipGetLastError());
     }
