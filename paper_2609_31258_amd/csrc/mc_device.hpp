@@ -252,10 +252,16 @@ __device__ __forceinline__ Q4<T> gather4(const Tab *tab, const float *sc, const 
     return q;
 }
 
-// Einstein model inverse: T = theta / ln(1 + s kB theta / U).
+// Einstein model inverse: T = theta / ln(1 + s kB theta / U).  FP64 form:
+// both quotients by the refined reciprocal (each within one unit in the
+// last place) for a normal U, by division for a subnormal one (whose
+// reciprocal the hardware estimate does not cover).
 template <class P>
 __device__ __forceinline__ typename P::T einstein_t(typename P::T e, typename P::T skt, typename P::T theta) {
     using T = typename P::T;
+    if constexpr (!P::kTwo) {
+        if (e >= 0x1p-1022) return theta * P::rcp(P::log1p_(skt * P::rcp(e)));
+    }
     return e > (T)0 ? P::div(theta, P::log1p_(P::div(skt, e))) : (T)0;
 }
 
