@@ -457,13 +457,15 @@ __global__ __launch_bounds__(1024) void k_bluestein_filter(Cx<D> *fb, const Cx<D
     for (int32_t n = threadIdx.x; n < L; n += blockDim.x) fb[n] = a[cslot(n)];
 }
 
-// One radial row per block (kDstThreads threads).  kForward: input
-// -rho/eps0 of column i from the int64 charge grid, output bh[i][:] scaled
-// by 2/N.  Inverse: input bh[i][:], output Phi[1..m][i].
-constexpr int kDstThreads = 256;
+// One radial row per block of dst_threads(L) threads (one group of 8 values
+// per thread and pass, 64 to 1024 threads: long rows, whose LDS allows one
+// block per CU, get the most).  kForward: input -rho/eps0 of column i from
+// the int64 charge grid, output bh[i][:] scaled by 2/N.  Inverse: input
+// bh[i][:], output Phi[1..m][i].
+inline int dst_threads(int32_t L) { return std::min(1024, std::max(64, L / 8)); }
 
 template <class D, bool kForward>
-__global__ __launch_bounds__(kDstThreads) void k_dst_bluestein(const unsigned long long *q, const double *rhs, D *bh,
+__global__ __launch_bounds__(1024) void k_dst_bluestein(const unsigned long long *q, const double *rhs, D *bh,
                                                                double *phi, int32_t accumulate, const Cx<D> *chirp,
                                                                const Cx<D> *fb, const Cx<D> *tw, int32_t nr,
                                                                int32_t nz, int32_t L, double dr, double dz) {
@@ -524,6 +526,12 @@ struct Bluestein {
 };
 
 constexpr size_t kLdsLimit = 160 * 1024;  // LDS per workgroup on gfx950
+
+// Modes from which systems of more than 256 rows take Thomas sweeps: on the
+// 1024 x 8192 grid (8190 modes of 1023 rows) the sweeps took 0.21 ms and
+// cyclic reduction 0.80 ms; on the 256 x 1024 grid (1022 modes of 255 rows)
+// the sweeps took 0.056 ms and cyclic reduction 0.015 ms.
+constexpr int32_t kPcrMaxModes = 4096;
 
 // LDS a workgroup may take on the current device (the smaller of the
 // architectural limit and what the runtime reports).
@@ -587,24 +595,26 @@ inline hipError_t poisson_solve(const PoissonGrid &g, const unsigned long long *
     const Bluestein &B = *g.blu;
     const Cx<D> *chirp = (const Cx<D> *)B.chirp, *fb = (const Cx<D> *)B.fb, *tw = (const Cx<D> *)B.tw;
     if (B.L > 0)
-        k_dst_bluestein<D, true><<<nu, kDstThreads, B.lds, st>>>(q, rhs, bh, nullptr, 0, chirp, fb, tw, g.nr, g.nz, B.L,
+        k_dst_bluestein<D, true><<<nu, dst_threads(B.L), B.lds, st>>>(q, rhs, bh, nullptr, 0, chirp, fb, tw, g.nr, g.nz, B.L,
                                                            g.dr, g.dz);
     else
         k_dst_rows<D><<<nu, 256, m * sizeof(D), st>>>(q, rhs, g.sine, bh, g.nr, g.nz, g.dr, g.dz);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // tridiagonal solves: cyclic reduction up to 1024 rows, Thomas sweeps above
+    // tridiagonal solves: cyclic reduction up to 256 rows, and up to 1024
+    // rows while the modes are too few to fill the GPU with Thomas sweeps
+    // (one thread per mode); Thomas sweeps otherwise
     if (nu <= 256)
         k_pcr<D, 4, 4><<<(m + 3) / 4, 256, 0, st>>>(bh, g.nr, g.nz, g.dr, g.dz);
-    else if (nu <= 512)
+    else if (nu <= 512 && m < kPcrMaxModes)
         k_pcr<D, 8, 2><<<(m + 1) / 2, 128, 0, st>>>(bh, g.nr, g.nz, g.dr, g.dz);
-    else if (nu <= 1024)
+    else if (nu <= 1024 && m < kPcrMaxModes)
         k_pcr<D, 16, 1><<<m, 64, 0, st>>>(bh, g.nr, g.nz, g.dr, g.dz);
     else
         k_thomas<D><<<(m + 255) / 256, 256, 0, st>>>(bh, g.tcp, g.tinv, g.nr, g.nz, g.dr);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (B.L > 0)
-        k_dst_bluestein<D, false><<<nu, kDstThreads, B.lds, st>>>(nullptr, nullptr, bh, phi, accumulate ? 1 : 0, chirp, fb,
+        k_dst_bluestein<D, false><<<nu, dst_threads(B.L), B.lds, st>>>(nullptr, nullptr, bh, phi, accumulate ? 1 : 0, chirp, fb,
                                                             tw, g.nr, g.nz, B.L, g.dr, g.dz);
     else
         k_idst_rows<D><<<nu, 256, m * sizeof(D), st>>>(bh, g.sine, phi, g.nr, g.nz, accumulate ? 1 : 0);
