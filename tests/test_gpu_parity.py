@@ -300,13 +300,17 @@ def test_pic_update_empty_population():
     g.close()
 
 
-def test_full_size_c2_sampled_step():
+@pytest.mark.parametrize("sort_every", [0, 100])
+def test_full_size_c2_sampled_step(sort_every):
     """The 256x1024 grid at its full 1e6-pack population, space charge on, in
-    the launch configuration the benchmark times: deposit grid bit-exact at
-    full size, and 2000 sampled packs stepped by the oracle one by one."""
+    the launch configuration the benchmark times (with the slot sort of its
+    headline runs, which reorders the slots at step 0 and deposits straight
+    into the grid, and without): deposit grid bit-exact at full size, and
+    2000 sampled packs stepped by the oracle one by one."""
     n = 1_000_000
-    _say("full-size C2 sampled", n)
+    _say("full-size C2 sampled", n, "sort_every", sort_every)
     f, ions, srcs, op, _ = synth.config_c2()
+    op.sort_every = sort_every
     snap = synth.pack_snapshot(n, f, seed=31, z_hi=3e-3, r_hi=6e-4, v_sigma=40.0, v_drift=250.0,
                                e_lo=1.5e-18, e_hi=3e-18, weight=0.012483)
     from oracle.binding import OracleSim
@@ -320,14 +324,15 @@ def test_full_size_c2_sampled_step():
     o.write_packs(snap)
     o.pic_update()
     assert np.array_equal(g.read_charge(), o.read_charge())
-    op2 = synth.Operating(**{**op.__dict__, "sc_on": 0})
+    op2 = synth.Operating(**{**op.__dict__, "sc_on": 0, "sort_every": 0})
     o.set_operating(op2)
     pick = np.sort(np.random.default_rng(5).choice(n, 2000, replace=False))
     sub = {k: v[pick] for k, v in snap.items()}
     o.write_packs(sub)
     o.step(1)
-    a = g.read_packs()
-    a = {k: v[pick] for k, v in a.items()}  # slots are in snapshot order
+    a = by_id(g.read_packs())  # ids are the snapshot's slot numbers
+    assert np.array_equal(a["id"], np.arange(n))
+    a = {k: v[pick] for k, v in a.items()}
     r = step_errors(a, o.read_packs(), f.grid.dr, thermal_speed(), sub["h"])
     _say(f"  max dx {r['max_dx']:.2e} dv {r['max_dv']:.2e} de {r['max_de']:.2e}")
     assert r["ok"].sum() >= 1999
