@@ -701,7 +701,7 @@ def copy_calibration():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: --gpus above 1 is not supported (no multi-GPU path)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU: --gpus above 1 is not supported (no multi-GPU path)"}))
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench needs a GPU"
