@@ -1180,11 +1180,10 @@ constexpr int64_t kDepositSumBlocks = 4096;
 // E = -grad(phi) on nodes: central differences, one-sided at the outer
 // edges, E_r = 0 on the axis.  clear (nullable): a charge grid zeroed on
 // the way, for the next deposit that adds into it.
-static __global__ __launch_bounds__(256) void k_bake(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
-                                                     double dz, unsigned long long *clear) {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= (int64_t)nr * nz) return;
-    if (clear) clear[n] = 0ull;
+// E = -grad Phi at node n (central differences, one-sided at the ends, zero
+// radial field on the axis).
+__device__ __forceinline__ double2 sc_field_at(const double *phi, int64_t n, int32_t nr, int32_t nz, double dr,
+                                              double dz) {
     const int32_t i = (int32_t)(n % nr), j = (int32_t)(n / nr);
     double vr, vz;
     if (i == 0) vr = 0.0;
@@ -1193,7 +1192,15 @@ static __global__ __launch_bounds__(256) void k_bake(const double *phi, double2 
     if (j == 0) vz = -(phi[n + nr] - phi[n]) / dz;
     else if (j == nz - 1) vz = -(phi[n] - phi[n - nr]) / dz;
     else vz = -(phi[n + nr] - phi[n - nr]) / (2.0 * dz);
-    e[n] = make_double2(vr, vz);
+    return make_double2(vr, vz);
+}
+
+static __global__ __launch_bounds__(256) void k_bake(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
+                                                     double dz, unsigned long long *clear) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)nr * nz) return;
+    if (clear) clear[n] = 0ull;
+    e[n] = sc_field_at(phi, n, nr, nz, dr, dz);
 }
 
 // Folded static table: (E_DC + V_off E_OFF + E_SC, E_RF), converted to the
@@ -1222,6 +1229,24 @@ __global__ __launch_bounds__(256) void k_fold(Tab *etab, const double2 *edc, con
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= nn) return;
     const double2 d = edc[n], o = eoff[n], c = esc[n], r = erf[n];
+    const float sc[4] = {s0, s1, s2, s3};
+    put4(etab, n, d.x + v_off * o.x + c.x, d.y + v_off * o.y + c.y, r.x, r.y, sc);
+}
+
+// k_bake and k_fold in one pass over the nodes (the space-charge update):
+// the field of the new potential is written out and folded into the step's
+// table at once.
+template <class Tab>
+__global__ __launch_bounds__(256) void k_bake_fold(const double *phi, double2 *e, int32_t nr, int32_t nz, double dr,
+                                                   double dz, unsigned long long *clear, Tab *etab, const double2 *edc,
+                                                   const double2 *eoff, const double2 *erf, double v_off, float s0,
+                                                   float s1, float s2, float s3) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)nr * nz) return;
+    if (clear) clear[n] = 0ull;
+    const double2 c = sc_field_at(phi, n, nr, nz, dr, dz);
+    e[n] = c;
+    const double2 d = edc[n], o = eoff[n], r = erf[n];
     const float sc[4] = {s0, s1, s2, s3};
     put4(etab, n, d.x + v_off * o.x + c.x, d.y + v_off * o.y + c.y, r.x, r.y, sc);
 }

@@ -306,6 +306,25 @@ static int32_t fold(mc_ctx *ctx) {
     return fold_table<float4>(ctx);
 }
 
+// The field of the new space-charge potential and the step's table from it,
+// in one kernel (clear: the other charge grid of a direct deposit, or null).
+template <class Tab>
+static int32_t bake_fold_table(mc_ctx *ctx, unsigned long long *clear) {
+    const int64_t nn = (int64_t)ctx->nr * ctx->nz;
+    k_bake_fold<Tab><<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->phi_sc, ctx->e_sc, ctx->nr, ctx->nz, ctx->dr,
+                                                                ctx->dz, clear, static_cast<Tab *>(ctx->etab),
+                                                                ctx->e_dc, ctx->e_off, ctx->e_rf, ctx->op.v_off,
+                                                                ctx->esc[0], ctx->esc[1], ctx->esc[2], ctx->esc[3]);
+    LAUNCHCHK();
+    return MC_OK;
+}
+
+static int32_t bake_fold(mc_ctx *ctx, unsigned long long *clear) {
+    if (!ctx->fp32()) return bake_fold_table<double4>(ctx, clear);
+    if (ctx->bf16()) return bake_fold_table<bf16x4>(ctx, clear);
+    return bake_fold_table<float4>(ctx, clear);
+}
+
 template <class P, class Tab>
 static int32_t launch_emit(mc_ctx *ctx, int si, int64_t count, PackPtrs<typename P::T> p) {
     Src &S = ctx->srcs[si];
@@ -674,10 +693,7 @@ static int32_t pic_update_t(mc_ctx *ctx, PackPtrs<typename P::T> p) {
     }
     {
         Timer t(ctx, MC_K_FIELD);
-        k_bake<<<grid_for(nn), kBlock, 0, ctx->stream>>>(ctx->phi_sc, ctx->e_sc, ctx->nr, ctx->nz, ctx->dr, ctx->dz,
-                                                         direct ? ctx->qnext : nullptr);
-        LAUNCHCHK();
-        int32_t rc = fold(ctx);
+        const int32_t rc = bake_fold(ctx, direct ? ctx->qnext : nullptr);
         if (rc) return rc;
     }
     return MC_OK;
