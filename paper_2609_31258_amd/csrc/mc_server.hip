@@ -381,9 +381,12 @@ static int32_t pic_query(mc_server *S, Query &Q, PackPtrs<typename P::T> p) {
         }
         SCHK(mask_correct<D>(S->pg, S->cap, bh, Q.rhs, Q.phi, S->stream));
     }
-    k_bake<<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.phi, Q.e_sc, S->nr, S->nz, S->dr, S->dz, nullptr);
+    // the field of the new potential folded into the query's table in one pass
+    k_bake_fold<Tab><<<blocks_for(nn), kBlk, 0, S->stream>>>(Q.phi, Q.e_sc, S->nr, S->nz, S->dr, S->dz, nullptr,
+                                                             static_cast<Tab *>(Q.etab), S->e_dc, S->e_off, S->e_rf,
+                                                             Q.q.op.v_off, S->esc[0], S->esc[1], S->esc[2], S->esc[3]);
     SCHK(hipGetLastError());
-    return fold_query<Tab>(S, Q);
+    return MC_OK;
 }
 
 template <class P, class Tab>
