@@ -8,6 +8,7 @@
 //               terminal tallies (Eq. 8)
 //   k_deposit   int64 cloud-in-cell deposit (PIC section)
 //   k_bake, k_fold  E = -grad(phi) on nodes; folded static field table
+//               (k_bake_fold: both in one pass, the space-charge update)
 //   k_hit       electrode hit table from the mask and hit distance
 //   k_snapshot  read-time tallies of the active population
 //
