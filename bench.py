@@ -428,22 +428,6 @@ def run_c1_full():
             "speedup": wall_o / wall_g}
 
 
-def c5_snapshot(f, ions, n: int, seed: int, weights):
-    """The large configuration's packs after its emission ramp, as a seeded
-    snapshot: the ten species in equal shares (round robin), positions within
-    3 mm of the injection plane and 0.3 mm of the axis, velocities thermal
-    about the gas flow, internal energies of an Einstein solid at 300-1500 K."""
-    import numpy as np
-    from paper_2609_31258_amd import synth
-    snap = synth.pack_snapshot(n, f, seed=seed, z_hi=3e-3, r_hi=3e-4, v_sigma=50.0, v_drift=300.0)
-    tag = (np.arange(n) % len(ions)).astype(np.int32)
-    snap["tag"] = tag
-    snap["w"] = np.asarray(weights, dtype=np.float64)[tag]
-    dof = np.array([3 * i.n_atoms - 6 for i in ions], dtype=np.float64)[tag]
-    snap["e_int"] = dof * 1.380649e-23 * 300.0 * np.random.default_rng(seed + 1).uniform(0.3, 1.5, n)
-    return snap
-
-
 def run_large(steps: int, fill: bool, n_packs: int = 16_000_000, sort_every: int = 0):
     """The large configuration in the FP32 form (1024x8192 grid, 1.6e7 packs
     of ten species, space charge every 5 steps): a timed window of `steps`
@@ -457,8 +441,7 @@ def run_large(steps: int, fill: bool, n_packs: int = 16_000_000, sort_every: int
     from paper_2609_31258_amd import mucite, synth
     f, ions, srcs, op, meta = synth.config_c5(n_packs=n_packs)
     op.sort_every = sort_every
-    # each species' pack weight: its share of the current over its packs per step
-    w = [src.current_a * op.dt / (ion.charge_z * 1.602176634e-19) / src.packs_per_step for src, ion in zip(srcs, ions)]
+    w = synth.config_c5_pack_weights(ions, srcs, op)
     sim = mucite.Sim(seed=synth.SEED, pack_capacity=n_packs, precision=1, timing=True)
     if fill:
         sim.setup(f, ions, srcs, op)
@@ -466,7 +449,7 @@ def run_large(steps: int, fill: bool, n_packs: int = 16_000_000, sort_every: int
         start = "after its 1e4-step emission ramp"
     else:
         sim.setup(f, ions, [], op)
-        snap = c5_snapshot(f, ions, n_packs, synth.SEED, w)
+        snap = synth.c5_post_ramp_snapshot(f, ions, w, n_packs, synth.SEED)
         sim.write_packs(snap)
         del snap
         _fill(sim, 5, "large warmup")
@@ -482,7 +465,7 @@ def run_large(steps: int, fill: bool, n_packs: int = 16_000_000, sort_every: int
     o = OracleSim(synth.SEED)
     op.sc_on = 0
     o.setup(f, ions, [], op)
-    o.write_packs(c5_snapshot(f, ions, n_cpu, synth.SEED + 3, w))
+    o.write_packs(synth.c5_post_ramp_snapshot(f, ions, w, n_cpu, synth.SEED + 3))
     t0 = time.perf_counter()
     o.step(cpu_steps)
     wall_o = time.perf_counter() - t0

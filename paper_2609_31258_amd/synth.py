@@ -281,6 +281,26 @@ def config_c5(n_packs: int = 16_000_000, emit_steps: int = 10_000, current_a: fl
     return f, ions, srcs, op, {"steps": 100_000, "emit_steps": emit_steps}
 
 
+def config_c5_pack_weights(ions, srcs, op) -> List[float]:
+    """Each species' pack weight in the large configuration: its share of the
+    current over its packs per step (ions per pack)."""
+    return [src.current_a * op.dt / (ion.charge_z * E_CHARGE) / src.packs_per_step for src, ion in zip(srcs, ions)]
+
+
+def c5_post_ramp_snapshot(f: Fields, ions, weights, n: int, seed: int = SEED) -> Dict[str, np.ndarray]:
+    """The large configuration's packs after its emission ramp, as a seeded
+    snapshot: the ten species in equal shares (round robin), positions within
+    3 mm of the injection plane and 0.3 mm of the axis, velocities thermal
+    about the gas flow, internal energies of an Einstein solid at 300-1500 K."""
+    snap = pack_snapshot(n, f, seed=seed, z_hi=3e-3, r_hi=3e-4, v_sigma=50.0, v_drift=300.0)
+    tag = (np.arange(n) % len(ions)).astype(np.int32)
+    snap["tag"] = tag
+    snap["w"] = np.asarray(weights, dtype=np.float64)[tag]
+    dof = np.array([3 * i.n_atoms - 6 for i in ions], dtype=np.float64)[tag]
+    snap["e_int"] = dof * K_B * 300.0 * np.random.default_rng(seed + 1).uniform(0.3, 1.5, n)
+    return snap
+
+
 def serving_queries(n_queries: int = 256, rate_hz: float = 20.0, seed: int = SEED,
                     pack_lo: float = 1e3, pack_hi: float = 1e6) -> List[Dict]:
     """Design queries with Poisson arrivals: RF amplitude U(50, 300) V, DC

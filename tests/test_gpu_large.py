@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from paper_2609_31258_amd import synth
-from tests.parity_util import make_pair, step_errors, thermal_speed
+from tests.parity_util import by_id, make_pair, step_errors, thermal_speed
 
 pytestmark = pytest.mark.gpu
 
@@ -166,3 +166,66 @@ def test_large_configuration_runs_with_space_charge():
         assert np.array_equal(np.asarray(t[k]), np.asarray(t2[k])), k
     assert np.array_equal(p["x"], p2["x"]) and np.array_equal(p["e_int"], p2["e_int"])
     _say(f"  classes {t['class_n'].tolist()} collisions {t['n_coll']} pack-steps {t['pack_steps']}")
+
+
+def test_large_full_population_sorted_step():
+    """The large configuration in the launch configuration the benchmark
+    times: 1.6e7 packs of ten species (the post-ramp snapshot), FP32 form,
+    the slot sort of its runs (slots reordered by species and cell at step 0,
+    then a direct deposit).  With space charge on, the full-size deposit is
+    bit-exact against the oracle's; with it off, the slots come out in
+    (species, cell) order and 2000 sampled packs, matched by id, agree with
+    the oracle stepping them one by one within the FP32 form's bounds."""
+    from oracle.binding import OracleSim
+    from paper_2609_31258_amd import mucite
+    n = 16_000_000
+    f, ions, srcs, op, _ = synth.config_c5(n_packs=n)
+    op.sort_every = 20
+    w = synth.config_c5_pack_weights(ions, srcs, op)
+    snap = _two_float(synth.c5_post_ramp_snapshot(f, ions, w, n, synth.SEED))
+    _say("large full population, sorted, fp32, space charge on", n)
+    o = OracleSim(synth.SEED)
+    o.setup(f, ions, [], op)
+    o.write_packs(snap)
+    o.deposit()
+    q_ref = o.read_charge()
+    o.close()
+    g = mucite.Sim(seed=synth.SEED, pack_capacity=n, precision=1)
+    g.setup(f, ions, [], op)
+    g.write_packs(snap)
+    g.step(1)
+    assert np.array_equal(g.read_charge(), q_ref)
+    g.close()
+    del q_ref
+    _say("large full population, sorted, fp32, space charge off", n)
+    op.sc_on = 0
+    g = mucite.Sim(seed=synth.SEED, pack_capacity=n, precision=1)
+    g.setup(f, ions, [], op)
+    g.write_packs(snap)
+    g.step(1)
+    raw = g.read_packs()
+    g.close()
+    # slot order: (species, lower-left CIC node at the start of the step)
+    ids = raw["id"]
+    assert np.array_equal(np.sort(ids), np.arange(n)) and not np.array_equal(ids, np.arange(n))
+    gr = f.grid
+    fi = np.minimum(np.floor(np.sqrt(snap["x"] ** 2 + snap["y"] ** 2) * (1.0 / gr.dr)), gr.nr - 2)
+    fj = np.clip(np.floor(snap["z"] * (1.0 / gr.dz)), 0, gr.nz - 2)
+    key = snap["tag"].astype(np.int64) * (gr.nr * gr.nz) + fj.astype(np.int64) * gr.nr + fi.astype(np.int64)
+    assert np.all(np.diff(key[ids]) >= 0)
+    a = by_id(raw)
+    del raw
+    pick = np.sort(np.random.default_rng(6).choice(n, 2000, replace=False))
+    a = {k: v[pick] for k, v in a.items()}
+    sub = {k: v[pick] for k, v in snap.items()}
+    o = OracleSim(synth.SEED)
+    o.setup(f, ions, [], synth.Operating(**{**op.__dict__, "sort_every": 0}))
+    o.write_packs(sub)
+    o.step(1)
+    r = step_errors(a, o.read_packs(), gr.dr, thermal_speed(), sub["h"])
+    o.close()
+    flips = int((~r["same_status"]).sum())
+    _say(f"  max dx {r['max_dx']:.2e} dv {r['max_dv']:.2e} de {r['max_de']:.2e} median dv "
+         f"{np.median(r['dv']):.2e} flips {flips}")
+    assert flips <= 2
+    assert np.median(r["dv"]) < 1e-3 and np.median(r["dx"]) < 1e-5
