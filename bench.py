@@ -26,7 +26,9 @@ Poisson solve, the snapshots and the adaptive step (`next_rows`), the large
 horizon with the oracle timed beside it, serving latency under overload and
 at a sustainable load with the oracle's service time on a sample of the
 queries, and the CPU oracle's rate on a bounded sample of the same workload
-on this host's cores.
+on this host's cores.  On request (--population-sweep), the hybrid form's
+step kernel at several populations, fitted as a fixed cost per launch plus a
+cost per pack.
 """
 from __future__ import annotations
 
@@ -181,6 +183,9 @@ def parse():
     ap.add_argument("--large-fill", action="store_true",
                     help="large configuration: run its 1e4-step emission ramp instead of starting from a snapshot")
     ap.add_argument("--no-c1", action="store_true", help="skip the 128x512 full-horizon run and its oracle timing")
+    ap.add_argument("--population-sweep", default="",
+                    help="comma list of pack counts: time the hybrid form's step kernel at each population "
+                         "(HIP events) and fit its per-launch time as intercept + slope x packs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     return ap.parse_args()
@@ -249,6 +254,42 @@ def run_gpu(precision: int, steps: int, warmup: int, langevin: bool = False, sor
     _say(f"{name}: {r['pack_steps'] / r['wall']:.3e} pack-steps/s, {r['wall'] * 1e3 / steps:.3f} ms/step, "
          f"{r['active']} active")
     return r
+
+
+def run_population_sweep(populations, steps: int, sort_every: int):
+    """The hybrid form's step kernel at several populations of the 256x1024
+    workload (its emission ramp cut to each population, then `steps` steps
+    with HIP events): per-launch time against packs, fitted as intercept +
+    slope x packs.  The slope is the marginal cost of a pack (its bytes over
+    it give the bandwidth the kernel sustains once it is full); the intercept
+    is what a launch costs beyond that (ramp-up, drain, the events)."""
+    import numpy as np
+    from paper_2609_31258_amd import mucite, synth
+    rows = []
+    for n in populations:
+        f, ions, srcs, op, _ = synth.config_c2()
+        srcs[0].n_total = n
+        op.sort_every = sort_every
+        op.langevin_on, op.lv_z_lo, op.lv_z_hi, op.lv_switch = 1, 0.0, 1e-3, 0.05
+        sim = mucite.Sim(seed=synth.SEED, pack_capacity=n, precision=1, timing=False)
+        sim.setup(f, ions, srcs, op)
+        _fill(sim, (n + srcs[0].packs_per_step - 1) // srcs[0].packs_per_step + 20, f"sweep {n} ramp")
+        r = _timed(sim, steps, events=True)
+        sim.close()
+        t = r["timing"]
+        ms = t["ms"]["step"] / max(t["launches"]["step"], 1)
+        rows.append({"packs": n, "active": r["active"], "wavefronts": (n + 63) // 64, "step_ms": ms,
+                     "langevin_fraction": r["langevin"] / max(r["pack_steps"], 1)})
+        _say(f"sweep: {n} packs, step kernel {ms:.5f} ms")
+    out = {"kernel": "k_step (hybrid form)", "steps_per_population": steps, "rows": rows}
+    if len(rows) >= 2:
+        x = np.array([q["active"] for q in rows], dtype=np.float64)
+        y = np.array([q["step_ms"] for q in rows], dtype=np.float64)
+        slope, icpt = np.polyfit(x, y, 1)
+        out["fit"] = {"slope_ps_per_pack": slope * 1e9, "intercept_us": icpt * 1e3,
+                      "marginal_GBps": BYTES_LANGEVIN["fp32"] / (slope * 1e-3) / 1e9 if slope > 0 else None,
+                      "bytes_per_pack_step": BYTES_LANGEVIN["fp32"]}
+    return out
 
 
 def hbm_roofline(r, precision: str, kernel: str, traffic_key=None):
@@ -752,6 +793,9 @@ def main():
         out["large"] = run_large(args.large_steps, args.large_fill, sort_every=args.large_sort_every)
     if not args.no_next_rows:
         out["next_rows"] = run_next_rows(args.steps, sort_every=args.sort_every)
+    if args.population_sweep:
+        pops = [int(v) for v in args.population_sweep.split(",") if v.strip()]
+        out["hybrid_population_sweep"] = run_population_sweep(pops, args.steps, args.sort_every)
     if not args.no_serving:
         out["serving"] = run_serving(args.serving_queries, args.serving_rate, args.serving_steps, 1,
                                      args.serving_budget_gib, 64)
