@@ -502,7 +502,7 @@ def run_large(steps: int, fill: bool, n_packs: int = 16_000_000, sort_every: int
                 for i in ions) / len(ions)
     _say(f"large: {ps / r['wall']:.3e} pack-steps/s, {r['wall'] * 1e3 / steps:.3f} ms/step")
     # oracle slice
-    n_cpu, cpu_steps = 100_000, 10
+    n_cpu, cpu_steps = 100_000, 100
     o = OracleSim(synth.SEED)
     op.sc_on = 0
     o.setup(f, ions, [], op)
