@@ -463,8 +463,12 @@ __device__ __forceinline__ void accumulate_hazard(const StepArgs<P, Tab> &a, con
     a.p.h[s] = a.p.h[s] + rate<P>(sp.act_kind, (T)sp.act_a, (T)sp.act_b, te) * (T)a.dt;
 }
 
-// One pack, one step.
-template <class P, class Tab>
+// One pack, one step.  kOneSpecies: every pack carries tag 0 (a context
+// that defines one species, or a serving query), so the tag array is not
+// read and the species record sits at one address for the whole wavefront
+// (read through the scalar cache, not by a vector load that waits for the
+// pack's tag: one dependent trip fewer before the push).
+template <class P, class Tab, bool kOneSpecies>
 __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, StepCount &n, uint32_t k0, uint32_t k1) {
     using T = typename P::T;
     PackCount pc{0, 0, 0, 0, 0, 0};
@@ -480,7 +484,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
     int64_t id = 0;
     if (s < a.n_slots) {
         status = a.p.status[s];
-        tag = a.p.tag[s];
+        if constexpr (!kOneSpecies) tag = a.p.tag[s];
         x0 = a.p.x[s];
         y0 = a.p.y[s];
         z0 = a.p.z[s];
@@ -500,7 +504,7 @@ __device__ __forceinline__ void step_one(const StepArgs<P, Tab> &a, int64_t s, S
         // used and the dissociation constants hold no registers through the
         // collision loop (at five waves in the FP32 form and three in the FP64
         // form they would spill)
-        const Species &sp = a.sp[tag];
+        const Species &sp = a.sp[kOneSpecies ? 0 : tag];
         const T dt = (T)a.dt, qm = (T)sp.qm, hd = (T)0.5 * dt;
         const T xl0 = xl, yl0 = yl, zl0 = zl;
 
@@ -695,7 +699,7 @@ constexpr int step_waves() {
     return P::kTwo ? (sizeof(Tab) == 8 ? 5 : 4) : 3;
 }
 
-template <class P, class Tab>
+template <class P, class Tab, bool kOneSpecies>
 __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P, Tab> a) {
     if (a.dyn) {
         // the step's time, length and RF stage coefficients from the device
@@ -710,7 +714,7 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step(StepArgs<P
     }
     P::prepare_tables(a.tables);
     StepCount n{0, 0, 0, 0, 0, 0, 0};
-    step_one(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
+    step_one<P, Tab, kOneSpecies>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, a.k0, a.k1);
     flush_counts(a.t, n);
 }
 
@@ -866,8 +870,9 @@ __global__ __launch_bounds__(256, (step_waves<P, Tab>())) void k_step_multi(cons
     const StepArgs<P, Tab> &a = descs[q];
     P::prepare_tables(a.tables);
     StepCount n{0, 0, 0, 0, 0, 0, 0};
-    // the random key is the query's, the same for the whole block: scalar
-    step_one(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n,
+    // the random key is the query's, the same for the whole block: scalar;
+    // a query defines one species, so its packs all carry tag 0
+    step_one<P, Tab, true>(a, (int64_t)(blockIdx.x - prefix[q]) * blockDim.x + threadIdx.x, n,
              __builtin_amdgcn_readfirstlane(a.k0), __builtin_amdgcn_readfirstlane(a.k1));
     flush_counts(a.t, n);
 }

@@ -422,7 +422,13 @@ static int32_t launch_step(mc_ctx *ctx, PackPtrs<typename P::T> p, double t0, do
     StepArgs<P, Tab> a = step_args<P, Tab>(ctx, p, t0, dt);
     a.dyn = dyn;
     Timer t(ctx, MC_K_STEP);
-    k_step<P, Tab><<<(unsigned)((ctx->n_slots + kStepBlock - 1) / kStepBlock), kStepBlock, 0, ctx->stream>>>(a);
+    const unsigned nb = (unsigned)((ctx->n_slots + kStepBlock - 1) / kStepBlock);
+    // one species defined: every pack carries tag 0 (tags are checked
+    // against the species on write, and sources name a defined species)
+    if (ctx->ions.size() == 1)
+        k_step<P, Tab, true><<<nb, kStepBlock, 0, ctx->stream>>>(a);
+    else
+        k_step<P, Tab, false><<<nb, kStepBlock, 0, ctx->stream>>>(a);
     LAUNCHCHK();
     return MC_OK;
 }
