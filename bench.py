@@ -67,16 +67,18 @@ OPS_CANDIDATE = 276       # every candidate inside the step: two Philox blocks, 
 OPS_ACCEPTED = 161        # accepted candidate: third block, impulsive update, scattering
 OPS_EXCHANGE = 18         # internal-energy exchange (taken with probability alpha)
 
-# Algorithmic HBM bytes per active pack-step of the fused step kernel: read
-# status, tag, id, position, velocity, internal energy and hazard; write back
-# position, velocity, internal energy and hazard.  FP64: 80 + 64 B.  FP32 form
+# Algorithmic HBM bytes per active pack-step of the fused step kernel in a
+# context that defines one species (every workload timed here): read status,
+# id, position, velocity, internal energy and hazard; write back position,
+# velocity, internal energy and hazard.  FP64: 76 + 64 B.  FP32 form
 # (two-float position and internal energy, FP32 velocity and hazard):
-# 64 + 48 B.  An inactive slot costs its status word (4 B).
-BYTES_STEP = {"fp64": 144, "fp32": 112}
+# 60 + 48 B.  With several species each pack also reads its 4-byte tag.  An
+# inactive slot costs its status word (4 B).
+BYTES_STEP = {"fp64": 140, "fp32": 108}
 # A pack on the hybrid Langevin branch neither reads nor writes its internal
-# energy and hazard: FP32 form 52 B read (status, tag, id, position,
-# velocity) + 36 B written (position, velocity).
-BYTES_LANGEVIN = {"fp64": 112, "fp32": 88}
+# energy and hazard: FP32 form 48 B read (status, id, position, velocity) +
+# 36 B written (position, velocity).
+BYTES_LANGEVIN = {"fp64": 108, "fp32": 84}
 # Deposit: status, position (FP64, or the FP32 form's hi+lo pairs) and the
 # int64 charge of every active pack (the LDS-aggregated grid atomics are
 # counted as L2 traffic, not HBM), plus one write of the int64 grid.
