@@ -364,6 +364,41 @@ def test_full_size_c2_sampled_step(form, sort_every):
     g.close()
 
 
+@pytest.mark.parametrize("precision,langevin", [(0, 0), (1, 0), (1, 1)])
+def test_one_species_kernel_equals_the_general_one(precision, langevin):
+    """A context that defines one species steps with the kernel that reads
+    the species record once per wavefront and no tag array; the same packs
+    in a context that also defines a second, unused species take the
+    general kernel (record and tag read per pack).  Both must agree bit for
+    bit over steps with space-charge updates and the slot sort."""
+    from paper_2609_31258_amd import mucite
+    n = 20_000
+    f, ions, srcs, op, _ = synth.config_c2(n_packs=n)
+    op.sc_every, op.sort_every = 4, 6
+    if langevin:
+        op.langevin_on, op.lv_z_lo, op.lv_z_hi, op.lv_switch = 1, 0.0, 1e-3, 0.05
+    other = synth.Ion(800.0, 2, 300e-20, 240)
+    _say("one-species kernel against the general one", precision, langevin)
+    snap = synth.pack_snapshot(n, f, seed=41, z_hi=3e-3, r_hi=6e-4, v_sigma=40.0, v_drift=250.0,
+                               e_lo=1.5e-18, e_hi=3e-18, weight=0.5)
+    out = []
+    for species in (ions, ions + [other]):
+        g = mucite.Sim(seed=synth.SEED, pack_capacity=n, precision=precision)
+        g.setup(f, species, [], op)
+        g.write_packs(snap)
+        g.step(13)
+        out.append((by_id(g.read_packs()), g.read_tallies(), g.read_charge()))
+        g.close()
+    (a, ta, qa), (b, tb, qb) = out
+    for k in ("id", "x", "y", "z", "vx", "vy", "vz", "e_int", "h", "status"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(qa, qb)
+    for k in ("class_n", "class_w", "n_cand", "n_coll", "n_langevin", "loss_map"):
+        assert np.array_equal(np.asarray(ta[k]), np.asarray(tb[k])), k
+    if langevin:
+        assert ta["n_langevin"] > 0
+
+
 # ---------------------------------------------------------------------------
 # Statistics over a run that transmits and loses packs
 # ---------------------------------------------------------------------------
